@@ -1,0 +1,140 @@
+/*
+ * voge.h -- C ABI of libvoge, the rendering hot path of VoGE on AMD MI355X
+ * (gfx950, CDNA4).
+ *
+ * VoGE ("VoGE: A Differentiable Volume Renderer using Gaussian Ellipsoids for
+ * Analysis-by-Synthesis", Wang et al., ICLR 2023) renders a set of Gaussian
+ * ellipsoid kernels seen by a pinhole camera.  For every pixel ray the library
+ *   1. transforms each kernel to camera space (Sec. 3.3, Eq. 3-4),
+ *   2. traces it along the ray: peak depth l, log peak density q and the 1D
+ *      precision a = 1/sigma^2 (Sec. 3.3, Eq. 5-6; App. A.1),
+ *   3. keeps the K nearest kernels (by l) whose peak density e^q exceeds eta,
+ *      after a conservative coarse stage on screen tiles (Sec. 3.3
+ *      "Coarse-to-fine rendering"; App. A.3),
+ *   4. evaluates the closed-form transmittance T(l_k) as an erf sum and the
+ *      weights W_k = T(l_k) e^{q_k} (Eq. 7-8; App. A.2), and
+ *   5. blends the per-kernel attributes: C = sum_k W_k c_k (Eq. 8).
+ * The backward returns gradients w.r.t. the kernels and the camera (the paper
+ * states both, Sec. 3.3), with the kept sets held fixed.
+ *
+ * Conventions
+ *   - Array arguments are DEVICE pointers to contiguous, row-major buffers
+ *     owned by the caller (float32 unless stated).  Structs passed by pointer
+ *     (camera, params) live in HOST memory and are read before return.
+ *   - Kernel k: means[k*3 + d]; covariance Sigma_k packed as covs[k*6 + e] in
+ *     the order xx, xy, xz, yy, yz, zz (must be symmetric positive definite);
+ *     attributes attrs[k*C + c].
+ *   - Camera: X_cam = R X + T with R row-major; focal F and principal point
+ *     (cx = O_x, cy = O_y) in pixels.  The ray of pixel (i, j), row i and
+ *     column j, has direction ((i - O_y)/F, (j - O_x)/F, 1) (Eq. 5).
+ *   - Images are HWC: image[(i*W + j)*C + c].
+ *   - Absorption tau = 1; the erf argument is (t - l_m) sqrt(a_m) as printed in
+ *     Eq. 7; the transmittance sum runs over the kept set, including k; ties in
+ *     l are broken by a fixed kernel order; kernels need l > 0; background 0.
+ *   - Every call is asynchronous on `stream` (a hipStream_t, 0 = default) and
+ *     allocates nothing.  Calls are reentrant across distinct workspaces; two
+ *     calls in flight on one workspace race.
+ *   - Outputs are overwritten, never accumulated.
+ *   - Return value: VOGE_OK, or a negative VOGE_E* code with a message from
+ *     voge_last_error().  Host-checked errors leave outputs untouched.
+ *   - Conditions found on the device (a covariance that is not SPD, a
+ *     non-finite input) do not fail the call: the affected kernel is left out
+ *     of the render and gets zero gradient, and a bit is set in the
+ *     workspace's status word (voge_status).
+ *
+ * Limits: 0 <= N < 2^24 kernels, 1 <= C <= 1024 channels, 1 <= H, W <= 32767,
+ * 1 <= K <= 64, 0 < eta < 1, F > 0.
+ */
+#ifndef VOGE_H
+#define VOGE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VOGE_OK 0
+#define VOGE_EINVAL (-1)      /* bad argument: shape, null pointer, range      */
+#define VOGE_ENOSPACE (-2)    /* workspace smaller than voge_workspace_size()  */
+#define VOGE_EHIP (-3)        /* a HIP runtime call failed                     */
+
+#define VOGE_STATUS_NOTSPD 1     /* some covariance was not SPD (skipped)      */
+#define VOGE_STATUS_NONFINITE 2  /* some centre or covariance was not finite   */
+
+#define VOGE_REUSE_PREP 1     /* backward flag: workspace holds this camera's prep */
+
+typedef struct voge_camera {
+    float R[9];               /* world -> camera rotation, row-major           */
+    float T[3];               /* translation                                   */
+    float focal;              /* F, pixels                                     */
+    float cx;                 /* O_x: principal point column                   */
+    float cy;                 /* O_y: principal point row                      */
+    int32_t height;           /* H                                             */
+    int32_t width;            /* W                                             */
+} voge_camera_t;
+
+typedef struct voge_params {
+    float eta;                /* density threshold: keep kernels with e^q > eta (App. A.3, default 0.01) */
+    int32_t K;                /* K' nearest kernels kept per ray (App. A.3, default 20)                 */
+} voge_params_t;
+
+typedef struct voge_ctx voge_ctx_t;
+
+/* Create a library context bound to HIP device `device`.  Host memory only;
+ * the calls below run on that device (the caller's current device is
+ * restored on return).  Errors: VOGE_EINVAL (null ctx), VOGE_EHIP. */
+int voge_create(voge_ctx_t** ctx, int device);
+
+/* Release a context (no device memory is owned by it). */
+int voge_destroy(voge_ctx_t* ctx);
+
+/* Bytes of workspace needed for N kernels, C channels and this camera's image
+ * size; with_backward = 1 sizes it for voge_render_backward as well (the
+ * forward uses a prefix of the same layout, so one workspace serves both).
+ * The workspace must be device memory aligned to 256 bytes. */
+int voge_workspace_size(int N, int C, const voge_camera_t* cam, const voge_params_t* params, int with_backward,
+                        size_t* bytes);
+
+/* Forward render (Sec. 3.3, Eq. 3-8).
+ *   image    [H*W*C]  out: C_p = sum_{k in S_p} W_k c_k
+ *   wsum     [H*W]    out, optional (NULL): sum_{k in S_p} W_k
+ *   kept     [H*W*K]  out, optional (NULL), int32: original indices of the kept
+ *                     kernels in ascending l, -1 padded
+ *   workspace         device, >= voge_workspace_size(..., 0); afterwards it
+ *                     holds this camera's prepared kernels (VOGE_REUSE_PREP). */
+int voge_render_forward(voge_ctx_t* ctx, const float* means, const float* covs, const float* attrs, int N, int C,
+                        const voge_camera_t* cam, const voge_params_t* params, float* image, float* wsum,
+                        int32_t* kept, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Backward of voge_render_forward for upstream gradient grad_image [H*W*C]
+ * (the kept sets are held fixed; selection is not differentiable).
+ *   grad_means [N*3], grad_covs [N*6] (w.r.t. the 6 packed numbers: each
+ *   off-diagonal entry stands for both matrix positions), grad_attrs [N*C]:
+ *   all required, overwritten.
+ *   grad_camera [15] optional (NULL): dL/dR (9, row-major, entries treated as
+ *   independent), dL/dT (3), dL/dF, dL/dO_x, dL/dO_y.
+ *   flags: VOGE_REUSE_PREP when `workspace` still holds the preparation done
+ *   by voge_render_forward for the same kernels, camera and params (skips it).
+ *   workspace: >= voge_workspace_size(..., 1). */
+int voge_render_backward(voge_ctx_t* ctx, const float* means, const float* covs, const float* attrs, int N, int C,
+                         const voge_camera_t* cam, const voge_params_t* params, const float* grad_image,
+                         float* grad_means, float* grad_covs, float* grad_attrs, float* grad_camera, int flags,
+                         void* workspace, size_t workspace_bytes, void* stream);
+
+/* Read the workspace's device status word (VOGE_STATUS_* bits of the last
+ * forward, or backward without VOGE_REUSE_PREP).  Synchronises `stream`. */
+int voge_status(const void* workspace, int32_t* device_status, void* stream);
+
+/* Message of the last error on this thread ("" if none). */
+const char* voge_last_error(void);
+
+/* ABI version: major * 10000 + minor * 100 + patch. */
+int voge_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VOGE_H */

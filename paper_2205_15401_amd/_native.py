@@ -1,0 +1,151 @@
+"""ctypes binding of libvoge (include/voge.h, include/voge_debug.h).
+
+Argument marshalling only: every function here calls the C entry point of
+the same name.  Pointers are plain integers (device addresses), streams are
+hipStream_t handles as integers.  Importing this module does not load the
+library; the first call does, and fails loudly when it is not built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvoge.so")
+
+VOGE_OK = 0
+VOGE_EINVAL = -1
+VOGE_ENOSPACE = -2
+VOGE_EHIP = -3
+VOGE_STATUS_NOTSPD = 1
+VOGE_STATUS_NONFINITE = 2
+VOGE_REUSE_PREP = 1
+
+EXPORTS = [
+    "voge_create", "voge_destroy", "voge_workspace_size", "voge_render_forward",
+    "voge_render_backward", "voge_status", "voge_last_error", "voge_version", "voge_debug_phi",
+    "voge_profile_enable", "voge_profile_read",
+]
+
+
+class VogeCamera(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_float * 9), ("T", ctypes.c_float * 3), ("focal", ctypes.c_float),
+                ("cx", ctypes.c_float), ("cy", ctypes.c_float), ("height", ctypes.c_int32),
+                ("width", ctypes.c_int32)]
+
+
+class VogeParams(ctypes.Structure):
+    _fields_ = [("eta", ctypes.c_float), ("K", ctypes.c_int32)]
+
+
+class VogePhaseTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("total_ms", ctypes.c_double), ("count", ctypes.c_int64)]
+
+
+class VogeError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libvoge error {code}: {msg}")
+        self.code = code
+
+
+_LOCK = threading.Lock()
+_LIB = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libvoge.so and declare its signatures."""
+    global _LIB
+    with _LOCK:
+        if _LIB is not None:
+            return _LIB
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built; run `python -m paper_2205_15401_amd.build`")
+        lib = ctypes.CDLL(path)
+        P, I, SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+        CamP, ParP = ctypes.POINTER(VogeCamera), ctypes.POINTER(VogeParams)
+        lib.voge_create.argtypes = [ctypes.POINTER(P), I]
+        lib.voge_destroy.argtypes = [P]
+        lib.voge_workspace_size.argtypes = [I, I, CamP, ParP, I, ctypes.POINTER(SZ)]
+        lib.voge_render_forward.argtypes = [P, P, P, P, I, I, CamP, ParP, P, P, P, P, SZ, P]
+        lib.voge_render_backward.argtypes = [P, P, P, P, I, I, CamP, ParP, P, P, P, P, P, I, P, SZ, P]
+        lib.voge_status.argtypes = [P, ctypes.POINTER(ctypes.c_int32), P]
+        lib.voge_last_error.argtypes = []
+        lib.voge_last_error.restype = ctypes.c_char_p
+        lib.voge_version.argtypes = []
+        lib.voge_debug_phi.argtypes = [P, P, I, P]
+        lib.voge_profile_enable.argtypes = [P, I]
+        lib.voge_profile_read.argtypes = [P, ctypes.POINTER(VogePhaseTime), I, ctypes.POINTER(I), I]
+        for name in EXPORTS:
+            if name != "voge_last_error":
+                getattr(lib, name).restype = I
+        _LIB = lib
+        return lib
+
+
+def voge_last_error() -> str:
+    return load().voge_last_error().decode()
+
+
+def _check(rc: int) -> int:
+    if rc != VOGE_OK:
+        raise VogeError(rc, voge_last_error())
+    return rc
+
+
+def voge_version() -> int:
+    return load().voge_version()
+
+
+def voge_create(device: int) -> int:
+    h = ctypes.c_void_p()
+    _check(load().voge_create(ctypes.byref(h), int(device)))
+    return h.value
+
+
+def voge_destroy(ctx: int) -> None:
+    _check(load().voge_destroy(ctypes.c_void_p(ctx)))
+
+
+def voge_workspace_size(N: int, C: int, cam: VogeCamera, params: VogeParams, with_backward: bool) -> int:
+    out = ctypes.c_size_t()
+    _check(load().voge_workspace_size(int(N), int(C), ctypes.byref(cam), ctypes.byref(params),
+                                      int(bool(with_backward)), ctypes.byref(out)))
+    return out.value
+
+
+def voge_render_forward(ctx, means, covs, attrs, N, C, cam, params, image, wsum, kept, workspace,
+                        workspace_bytes, stream) -> int:
+    return _check(load().voge_render_forward(ctx, means, covs, attrs, int(N), int(C), ctypes.byref(cam),
+                                             ctypes.byref(params), image, wsum, kept, workspace,
+                                             int(workspace_bytes), stream))
+
+
+def voge_render_backward(ctx, means, covs, attrs, N, C, cam, params, grad_image, grad_means, grad_covs,
+                         grad_attrs, grad_camera, flags, workspace, workspace_bytes, stream) -> int:
+    return _check(load().voge_render_backward(ctx, means, covs, attrs, int(N), int(C), ctypes.byref(cam),
+                                              ctypes.byref(params), grad_image, grad_means, grad_covs,
+                                              grad_attrs, grad_camera, int(flags), workspace,
+                                              int(workspace_bytes), stream))
+
+
+def voge_status(workspace, stream) -> int:
+    st = ctypes.c_int32()
+    _check(load().voge_status(workspace, ctypes.byref(st), stream))
+    return st.value
+
+
+def voge_debug_phi(x, y, n, stream) -> int:
+    return _check(load().voge_debug_phi(x, y, int(n), stream))
+
+
+def voge_profile_enable(ctx, enable: bool) -> int:
+    return _check(load().voge_profile_enable(ctx, int(bool(enable))))
+
+
+def voge_profile_read(ctx, reset: bool = True):
+    """{phase name: (total ms, count)}."""
+    arr = (VogePhaseTime * 16)()
+    n = ctypes.c_int()
+    _check(load().voge_profile_read(ctx, arr, 16, ctypes.byref(n), int(bool(reset))))
+    return {arr[i].name.decode(): (arr[i].total_ms, int(arr[i].count)) for i in range(min(n.value, 16))}

@@ -1,0 +1,55 @@
+"""Comparison rules between the GPU library and the FP64 oracle.
+
+Tolerance (the hot path's stated bar: 1e-5 relative in FP32; kept sets exact
+except for near ties):
+  * images: |C_gpu - C_ref| <= RTOL * (|C_ref| + sum_k W_k |c_k|) per element,
+    the floor being the oracle's absolute blend sum (C can cancel);
+  * kept sets: equal, except at pixels the oracle flags (a near tie at the
+    K-th place within 1e-6 relative in l, or a kernel within 1e-5 of the
+    threshold ln eta); such pixels are left out of the element comparison;
+  * gradients: |g - g_ref| <= RTOL * (sum over pixels of |contribution|)
+    per element, and ||g - g_ref||_inf <= RTOL ||g_ref||_inf per tensor.
+"""
+
+import numpy as np
+import torch
+
+RTOL = 1e-5
+
+
+def to_dev(a, device="cuda"):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float32))).to(device)
+
+
+def compare_images(img_gpu, ref_image, ref_absum, rtol=RTOL, mask=None):
+    """img_gpu, ref_image, ref_absum: (n, C).  Returns max ratio err/bound."""
+    g = np.asarray(img_gpu, np.float64)
+    r = np.asarray(ref_image, np.float64)
+    bound = rtol * (np.abs(r) + np.asarray(ref_absum, np.float64)) + 1e-30
+    err = np.abs(g - r)
+    if mask is not None:
+        err = err[mask]
+        bound = bound[mask]
+    ratio = (err / bound).max() if err.size else 0.0
+    return float(ratio)
+
+
+def compare_kept(kept_gpu, ref_kept, ref_flags):
+    """Both (n, K) int arrays.  Returns (n mismatching pixels, n mismatching unflagged pixels, mask of equal)."""
+    kg = np.asarray(kept_gpu)
+    kr = np.asarray(ref_kept)
+    same = np.all(kg == kr, axis=1)
+    bad_unflagged = (~same) & (np.asarray(ref_flags) == 0)
+    return int((~same).sum()), int(bad_unflagged.sum()), same
+
+
+def compare_grad(g, ref, ref_abs, rtol=RTOL):
+    """Returns (max per-element ratio, inf-norm ratio)."""
+    g = np.asarray(g, np.float64).reshape(-1)
+    r = np.asarray(ref, np.float64).reshape(-1)
+    a = np.asarray(ref_abs, np.float64).reshape(-1)
+    err = np.abs(g - r)
+    bound = rtol * a + 1e-30
+    elem = float((err / bound).max()) if err.size else 0.0
+    inf = float(err.max() / (rtol * np.abs(r).max() + 1e-30)) if err.size else 0.0
+    return elem, inf
