@@ -366,8 +366,11 @@ void oracle_transmittance(const double* rec, int n, const double* t, int nt, dou
  * kept set of each pixel is held fixed.  Gradients (all overwritten):
  *   g_means[N*3], g_covs[N*6] (w.r.t. the 6 packed numbers, off-diagonals once),
  *   g_attrs[N*C], g_cam[15] (R row-major, T, F, O_x, O_y).
- * a_* (optional) receive, per element, the sum over pixels of the absolute
- * value of each pixel's contribution: the scale for comparisons.
+ * a_* (optional) receive, per element, the scale for comparisons: every
+ * term of the computation carried with its absolute value through the same
+ * linear steps (each pair term of the transmittance derivative, each term of
+ * the chain to world space), i.e. the sum of the absolute values of all
+ * per-pair contributions to that element.
  * Returns the number of skipped kernels or -1. */
 int oracle_backward(const double* means, const double* covs, const double* attrs, int N, int C,
                     const double* cam15, int H, int W, double eta, int K,
@@ -404,10 +407,14 @@ int oracle_backward(const double* means, const double* covs, const double* attrs
         cand_t* kept = (cand_t*)malloc(sizeof(cand_t) * (size_t)(N > 0 ? N : 1));
         double* E = (double*)malloc(sizeof(double) * (size_t)K);
         double* Wt = (double*)malloc(sizeof(double) * (size_t)K);
-        double* dm = (double*)malloc(sizeof(double) * (size_t)K);
-        double* dl = (double*)malloc(sizeof(double) * (size_t)K);
-        double* da = (double*)malloc(sizeof(double) * (size_t)K);
-        double* dE = (double*)malloc(sizeof(double) * (size_t)K);
+        double* dm = (double*)malloc(sizeof(double) * (size_t)K * 8);
+        double* dl = dm + K;
+        double* da = dl + K;
+        double* dE = da + K;
+        double* adm = dE + K;      /* absolute-value companions of dm, dl, da, dE */
+        double* adl = adm + K;
+        double* ada = adl + K;
+        double* adE = ada + K;
 
 #pragma omp for schedule(dynamic, 16)
         for (int64_t p = 0; p < npx; ++p) {
@@ -423,17 +430,19 @@ int oracle_backward(const double* means, const double* covs, const double* attrs
             /* C = sum_k W_k c_k:  dL/dc_k = W_k G;  dL/dW_k = G . c_k */
             for (int k = 0; k < keff; ++k) {
                 const double* ck = attrs + (size_t)kept[k].idx * C;
-                double g = 0.0;
+                double g = 0.0, ag = 0.0;
                 for (int c = 0; c < C; ++c) {
-                    g += G[c] * (double)ck[c];
+                    g += G[c] * ck[c];
+                    ag += fabs(G[c] * ck[c]);
                     gA[(size_t)kept[k].idx * C + c] += Wt[k] * G[c];
                     aA[(size_t)kept[k].idx * C + c] += fabs(Wt[k] * G[c]);
                 }
                 /* W_k = exp(-E_k) e^{q_k}: direct path through e^{q_k}, and dL/dE_k */
                 dm[k] = g * exp(-E[k]);
+                adm[k] = ag * exp(-E[k]);
                 dE[k] = -g * Wt[k];
-                dl[k] = 0.0;
-                da[k] = 0.0;
+                adE[k] = ag * Wt[k];
+                dl[k] = da[k] = adl[k] = ada[k] = 0.0;
             }
             /* E_k = sum_m m_m Phi(x_km),  x_km = (l_k - l_m) sqrt(a_m),
              * Phi(x) = (1 + erf x)/2,  Phi'(x) = exp(-x^2)/sqrt(pi) */
@@ -445,10 +454,15 @@ int oracle_backward(const double* means, const double* covs, const double* attrs
                     double dPhi = exp(-x * x) / sqrt(M_PI);
                     double mm = exp(kept[m].q);
                     dm[m] += dE[k] * Phi;
+                    adm[m] += adE[k] * Phi;
                     double dx = dE[k] * mm * dPhi;
+                    double adx = adE[k] * mm * dPhi;
                     dl[k] += dx * s_m;
                     dl[m] -= dx * s_m;
+                    adl[k] += adx * s_m;
+                    adl[m] += adx * s_m;
                     da[m] += dx * (kept[k].l - kept[m].l) / (2.0 * s_m);
+                    ada[m] += adx * fabs(kept[k].l - kept[m].l) / (2.0 * s_m);
                 }
             }
             /* chain (q, l, a) -> camera-space (M, S) and the ray D (App. A.1):
@@ -459,37 +473,60 @@ int oracle_backward(const double* means, const double* covs, const double* attrs
                 const ker_t* kk = &ks[kept[k].idx];
                 double l = kept[k].l, a = kept[k].a;
                 double dq = dm[k] * exp(kept[k].q);
+                double adq = adm[k] * exp(kept[k].q);
                 double V[3], SV[3], SD[3];
                 for (int d = 0; d < 3; ++d) V[d] = kk->M[d] - l * D[d];
                 mat_vec(kk->S, V, SV);
                 mat_vec(kk->S, D, SD);
-                double gMc[3], GS[9], gD[3];
+                double gMc[3], GS[9], gD[3], agMc[3], aGS[9], agD[3];
                 for (int d = 0; d < 3; ++d) {
                     gMc[d] = -dq * SV[d] + dl[k] * SD[d] / a;
+                    agMc[d] = adq * fabs(SV[d]) + adl[k] * fabs(SD[d]) / a;
                     gD[d] = dq * l * SV[d] + dl[k] * (SV[d] - l * SD[d]) / a + da[k] * 2.0 * SD[d];
+                    agD[d] = adq * l * fabs(SV[d]) + adl[k] * (fabs(SV[d]) + l * fabs(SD[d])) / a +
+                             ada[k] * 2.0 * fabs(SD[d]);
                 }
                 for (int r = 0; r < 3; ++r)
-                    for (int c = 0; c < 3; ++c)
+                    for (int c = 0; c < 3; ++c) {
                         GS[3 * r + c] = -0.5 * dq * V[r] * V[c] + dl[k] * D[r] * V[c] / a + da[k] * D[r] * D[c];
+                        aGS[3 * r + c] = 0.5 * adq * fabs(V[r] * V[c]) + adl[k] * fabs(D[r] * V[c]) / a +
+                                         ada[k] * fabs(D[r] * D[c]);
+                    }
                 /* camera space -> world space (Eq. 3-4) */
-                double gMw[3];
+                double aR[9], aS0[9], aM0[3];
+                for (int e = 0; e < 9; ++e) {
+                    aR[e] = fabs(cam.R[e]);
+                    aS0[e] = fabs(kk->S0[e]);
+                }
+                for (int d = 0; d < 3; ++d) aM0[d] = fabs(kk->M0[d]);
+                double aRt[9];
+                mat_transpose(aR, aRt);
+                double gMw[3], agMw[3];
                 mat_t_vec(cam.R, gMc, gMw);                        /* R^T gM           */
+                mat_t_vec(aR, agMc, agMw);
                 double t1[9], GS0[9], t2[9], GSig[9];
                 mat_mul(Rt, GS, t1);
                 mat_mul(t1, cam.R, GS0);                           /* R^T G_S R        */
                 mat_mul(kk->S0, GS0, t2);
                 mat_mul(t2, kk->S0, GSig);                         /* S0 G S0          */
                 for (int e = 0; e < 9; ++e) GSig[e] = -GSig[e];    /* d(A^-1) = -A^-1 dA A^-1 */
+                double u1[9], aGS0[9], u2[9], aGSig[9];
+                mat_mul(aRt, aGS, u1);
+                mat_mul(u1, aR, aGS0);
+                mat_mul(aS0, aGS0, u2);
+                mat_mul(u2, aS0, aGSig);
                 double pk[6] = {GSig[0], GSig[1] + GSig[3], GSig[2] + GSig[6],
                                 GSig[4], GSig[5] + GSig[7], GSig[8]};
+                double apk[6] = {aGSig[0], aGSig[1] + aGSig[3], aGSig[2] + aGSig[6],
+                                 aGSig[4], aGSig[5] + aGSig[7], aGSig[8]};
                 size_t n = (size_t)kept[k].idx;
                 for (int d = 0; d < 3; ++d) {
                     gM[n * 3 + d] += gMw[d];
-                    aM[n * 3 + d] += fabs(gMw[d]);
+                    aM[n * 3 + d] += agMw[d];
                 }
                 for (int e = 0; e < 6; ++e) {
                     gC[n * 6 + e] += pk[e];
-                    aC[n * 6 + e] += fabs(pk[e]);
+                    aC[n * 6 + e] += apk[e];
                 }
                 /* camera extrinsics: dL/dR = gM M0^T + G_S R S0^T + G_S^T R S0, dL/dT = gM */
                 double gR[9], RS0[9], A1[9], A2[9], GSt[9];
@@ -497,36 +534,37 @@ int oracle_backward(const double* means, const double* covs, const double* attrs
                 mat_mul(GS, RS0, A1);          /* S0 symmetric: R S0^T = R S0 */
                 mat_transpose(GS, GSt);
                 mat_mul(GSt, RS0, A2);
+                double aRS0[9], aA1[9], aA2[9], aGSt[9];
+                mat_mul(aR, aS0, aRS0);
+                mat_mul(aGS, aRS0, aA1);
+                mat_transpose(aGS, aGSt);
+                mat_mul(aGSt, aRS0, aA2);
                 for (int r = 0; r < 3; ++r)
-                    for (int c = 0; c < 3; ++c)
+                    for (int c = 0; c < 3; ++c) {
                         gR[3 * r + c] = gMc[r] * kk->M0[c] + A1[3 * r + c] + A2[3 * r + c];
-                for (int e = 0; e < 9; ++e) {
-                    gK[e] += gR[e];
-                    aK[e] += fabs(gR[e]);
-                }
+                        aK[3 * r + c] += agMc[r] * aM0[c] + aA1[3 * r + c] + aA2[3 * r + c];
+                    }
+                for (int e = 0; e < 9; ++e) gK[e] += gR[e];
                 for (int d = 0; d < 3; ++d) {
                     gK[9 + d] += gMc[d];
-                    aK[9 + d] += fabs(gMc[d]);
+                    aK[9 + d] += agMc[d];
                 }
                 /* intrinsics through D = ((i - O_y)/F, (j - O_x)/F, 1) (Eq. 5) */
-                double gF = -gD[0] * ((double)i - cam.Oy) / (cam.F * cam.F) - gD[1] * ((double)j - cam.Ox) / (cam.F * cam.F);
-                double gOx = -gD[1] / cam.F;
-                double gOy = -gD[0] / cam.F;
+                double F2 = cam.F * cam.F;
+                double gF = -gD[0] * ((double)i - cam.Oy) / F2 - gD[1] * ((double)j - cam.Ox) / F2;
+                double aF = agD[0] * fabs((double)i - cam.Oy) / F2 + agD[1] * fabs((double)j - cam.Ox) / F2;
                 gK[12] += gF;
-                gK[13] += gOx;
-                gK[14] += gOy;
-                aK[12] += fabs(gF);
-                aK[13] += fabs(gOx);
-                aK[14] += fabs(gOy);
+                gK[13] += -gD[1] / cam.F;
+                gK[14] += -gD[0] / cam.F;
+                aK[12] += aF;
+                aK[13] += agD[1] / cam.F;
+                aK[14] += agD[0] / cam.F;
             }
         }
         free(kept);
         free(E);
         free(Wt);
         free(dm);
-        free(dl);
-        free(da);
-        free(dE);
     }
     /* reduce the per-thread accumulators in thread order */
     double* out_g[4] = {g_means, g_covs, g_attrs, g_cam};

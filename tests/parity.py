@@ -34,12 +34,24 @@ def compare_images(img_gpu, ref_image, ref_absum, rtol=RTOL, mask=None):
     return float(ratio)
 
 
-def compare_kept(kept_gpu, ref_kept, ref_flags):
-    """Both (n, K) int arrays.  Returns (n mismatching pixels, n mismatching unflagged pixels, mask of equal)."""
-    kg = np.asarray(kept_gpu)
-    kr = np.asarray(ref_kept)
+def compare_kept(kept_gpu, ref_kept, ref_flags, ref_l=None):
+    """Kept sets as sets: both (n, K) int arrays, -1 padded.  The order inside
+    a set is not part of the result (the blend is order-free); when ref_l
+    (n, K) is given, the GPU order must still be ascending in the oracle's l,
+    up to ties within 1e-6 relative.
+    Returns (n mismatching pixels, n mismatching unflagged pixels, mask of equal)."""
+    kg = np.sort(np.asarray(kept_gpu), axis=1)
+    kr = np.sort(np.asarray(ref_kept), axis=1)
     same = np.all(kg == kr, axis=1)
     bad_unflagged = (~same) & (np.asarray(ref_flags) == 0)
+    if ref_l is not None:
+        kgo = np.asarray(kept_gpu)
+        kro = np.asarray(ref_kept)
+        for p in np.flatnonzero(same):
+            lut = {int(i): float(l) for i, l in zip(kro[p], ref_l[p]) if i >= 0}
+            ls = [lut[int(i)] for i in kgo[p] if i >= 0]
+            for a, b in zip(ls, ls[1:]):
+                assert b >= a - 1e-6 * abs(a), ("kept list not ascending in l", p, ls)
     return int((~same).sum()), int(bad_unflagged.sum()), same
 
 

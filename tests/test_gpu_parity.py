@@ -51,7 +51,7 @@ def check_forward(scene, cam, K, eta=0.01, pixels=None, max_flagged_frac=0.01):
     img, wsum, kept, st = gpu_forward(scene, cam, K, eta)
     ref = oracle_forward(scene, cam, K, eta, pixels)
     sel = np.arange(cam.height * cam.width) if pixels is None else np.asarray(pixels)
-    n_bad, n_bad_unflagged, same = compare_kept(kept[sel], ref.kept_idx, ref.flags)
+    n_bad, n_bad_unflagged, same = compare_kept(kept[sel], ref.kept_idx, ref.flags, ref.kept_rec[..., 0])
     assert n_bad_unflagged == 0, f"{n_bad_unflagged} unflagged pixels with different kept sets"
     assert n_bad <= max_flagged_frac * len(sel) + 1
     r_img = compare_images(img[sel], ref.image, ref.absum, mask=same)
@@ -64,17 +64,20 @@ def check_forward(scene, cam, K, eta=0.01, pixels=None, max_flagged_frac=0.01):
 # ------------------------------------------------------------------ Phi
 
 def test_device_phi_matches_erf():
-    from scipy.special import erf
+    from scipy.special import erfc
     x = np.concatenate([np.linspace(-12, 12, 200_001), [0.0, -0.0, 1e-30, -1e-30, 40.0, -40.0]]).astype(np.float32)
     xt = torch.from_numpy(x).cuda()
     y = torch.empty_like(xt)
     nat.voge_debug_phi(xt.data_ptr(), y.data_ptr(), x.size, torch.cuda.current_stream().cuda_stream)
-    ref = 0.5 * (1.0 + erf(x.astype(np.float64)))
+    ref = 0.5 * erfc(-x.astype(np.float64))      # accurate in both tails
     err = np.abs(y.cpu().numpy().astype(np.float64) - ref)
     assert err.max() < 2.5e-7, err.max()
+    # far tail: relative accuracy is bounded by the rounding of the FP32
+    # exponential's argument, about |x|^2 * 2^-24 (x = -8: 4e-6)
     neg = x < -1
     rel = err[neg] / np.maximum(ref[neg], 1e-300)
-    assert rel[ref[neg] > 1e-30].max() < 1e-6
+    keep = ref[neg] > 1e-30
+    assert np.all(rel[keep] < 1e-6 + 2e-7 * x[neg][keep].astype(np.float64) ** 2)
 
 
 # ------------------------------------------------------------- forward
