@@ -89,7 +89,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--cpu-sample", type=int, default=65536, help="rays for the oracle baseline (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=131072, help="rays for the oracle baseline (0 = skip)")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="after timing, copy this many bytes device-to-device once (a plain copy kernel of "
+                         "known size that scales the HBM byte counters of a profile)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -157,6 +160,15 @@ def main():
     phases = nat.voge_profile_read(ctx, reset=True)
     nat.voge_profile_enable(ctx, False)
     per_step = np.array([events[i].elapsed_time(events[i + 1]) for i in range(args.steps)])
+    if args.calibrate_copy > 0:
+        n4 = args.calibrate_copy // 4
+        src = torch.ones(n4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {n4 * 4} bytes done")
+        del src, dst
     total_ms = events[0].elapsed_time(events[-1])
     ms_per_step = total_ms / args.steps
     rays = H * W

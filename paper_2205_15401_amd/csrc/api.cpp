@@ -171,6 +171,7 @@ Plan plan_workspace(int N, int C, int H, int W, int K) {
     p.off_tileD = take(sizeof(double) * 3 * (size_t)p.n_tiles);
     p.off_camP = take(sizeof(double) * 12 * (size_t)p.n_epi_blocks);
     p.off_bw = take(16 * k * p.S);
+    p.off_pairs = take(32 * k * p.S);    // PairRec
     p.bwd_bytes = off;
     return p;
 }
@@ -200,6 +201,7 @@ WsPtrs carve(void* base, const Plan& p, bool with_backward) {
         w.tileD = reinterpret_cast<double*>(b + p.off_tileD);
         w.camP = reinterpret_cast<double*>(b + p.off_camP);
         w.bw = reinterpret_cast<float4*>(b + p.off_bw);
+        w.pairs = reinterpret_cast<PairRec*>(b + p.off_pairs);
     }
     return w;
 }
@@ -287,6 +289,7 @@ voge::TraceArgs trace_args(const voge::WsPtrs& w, const voge::Plan& p, int N, in
     ta.gS = w.gS;
     ta.tileD = w.tileD;
     ta.bw = w.bw;
+    ta.pairs = w.pairs;
     return ta;
 }
 
@@ -356,9 +359,7 @@ int voge_render_backward(voge_ctx_t* ctx, const float* means, const float* covs,
     }
     if (N > 0) {
         ProfScope ps(ctx, "zero", s);
-        voge::launch_fill_u32(w.gM, (size_t)N * 3, 0u, s);
-        voge::launch_fill_u32(w.gS, (size_t)N * 6, 0u, s);
-        voge::launch_fill_u32(grad_attrs, (size_t)N * C, 0u, s);
+        voge::launch_zero3(w.gM, (size_t)N * 3, w.gS, (size_t)N * 6, grad_attrs, (size_t)N * C, s);
     }
     ta.grad_image = grad_image;
     ta.grad_attrs = grad_attrs;

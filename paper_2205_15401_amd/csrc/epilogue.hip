@@ -111,24 +111,36 @@ __global__ __launch_bounds__(EPI_THREADS) void k_epilogue(EpiArgs A) {
     }
 }
 
-__global__ void k_cam_finalize(EpiArgs A, int nblk) {
-    const int e = threadIdx.x;
-    if (e < 12) {
+// One block: a fixed-order tree reduction of the per-block and per-tile
+// partials into the 15 camera gradients.
+constexpr int FIN_THREADS = 256;
+
+__global__ __launch_bounds__(FIN_THREADS) void k_cam_finalize(EpiArgs A, int nblk) {
+    __shared__ double s_part[FIN_THREADS];
+    const int tid = threadIdx.x;
+    for (int e = 0; e < 15; ++e) {
         double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += A.camP[(size_t)b * 12 + e];
-        A.grad_camera[e] = (float)s;
-    } else if (e < 15) {
-        const int comp = (e == 12) ? 2 : (e == 13 ? 1 : 0);   // F <- z, O_x <- y, O_y <- x
-        double s = 0.0;
-        for (int t = 0; t < A.n_tiles; ++t) s += A.tileD[(size_t)t * 3 + comp];
-        A.grad_camera[e] = (float)(e == 12 ? s : -s);
+        if (e < 12) {
+            for (int b = tid; b < nblk; b += FIN_THREADS) s += A.camP[(size_t)b * 12 + e];
+        } else {
+            const int comp = (e == 12) ? 2 : (e == 13 ? 1 : 0);   // F <- z, O_x <- y, O_y <- x
+            for (int t = tid; t < A.n_tiles; t += FIN_THREADS) s += A.tileD[(size_t)t * 3 + comp];
+        }
+        s_part[tid] = s;
+        __syncthreads();
+        for (int off = FIN_THREADS / 2; off > 0; off >>= 1) {
+            if (tid < off) s_part[tid] += s_part[tid + off];
+            __syncthreads();
+        }
+        if (tid == 0) A.grad_camera[e] = (float)(e == 13 || e == 14 ? -s_part[0] : s_part[0]);
+        __syncthreads();
     }
 }
 
 hipError_t launch_epilogue(const EpiArgs& a, hipStream_t s) {
     const int nblk = (a.N + EPI_THREADS - 1) / EPI_THREADS;
     if (nblk > 0) hipLaunchKernelGGL(k_epilogue, dim3(nblk), dim3(EPI_THREADS), 0, s, a);
-    if (a.grad_camera) hipLaunchKernelGGL(k_cam_finalize, dim3(1), dim3(64), 0, s, a, nblk);
+    if (a.grad_camera) hipLaunchKernelGGL(k_cam_finalize, dim3(1), dim3(FIN_THREADS), 0, s, a, nblk);
     return hipGetLastError();
 }
 

@@ -141,7 +141,7 @@ __global__ void k_prep_records(const float* __restrict__ means, const float* __r
 // one exclusive scan, then a stable scatter that ranks equal digits inside a
 // wave with ballots and across waves through LDS.
 constexpr int SORT_THREADS = 256;
-constexpr int SORT_ROUNDS = 16;
+constexpr int SORT_ROUNDS = 2;
 constexpr int SORT_TILE = SORT_THREADS * SORT_ROUNDS;
 
 int sort_blocks(int N) { return (N + SORT_TILE - 1) / SORT_TILE; }
@@ -161,28 +161,31 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const uint32_t* __re
     hist[(size_t)tid * nblk + blockIdx.x] = cnt[tid];
 }
 
-// exclusive scan of n counters, one block of 1024 threads
+// exclusive scan of n counters, one block of 1024 threads: each thread scans
+// a contiguous run serially, then the run totals are scanned in LDS
 __global__ __launch_bounds__(1024) void k_sort_scan(uint32_t* __restrict__ hist, int n) {
     __shared__ uint32_t buf[1024];
-    __shared__ uint32_t carry;
     const int tid = threadIdx.x;
-    if (tid == 0) carry = 0;
+    const int per = (n + 1023) / 1024;
+    const int b0 = tid * per;
+    uint32_t run = 0;
+    for (int j = 0; j < per; ++j)
+        if (b0 + j < n) run += hist[b0 + j];
+    buf[tid] = run;
     __syncthreads();
-    for (int base = 0; base < n; base += 1024) {
-        const int i = base + tid;
-        const uint32_t x = i < n ? hist[i] : 0u;
-        buf[tid] = x;
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t y = tid >= off ? buf[tid - off] : 0u;
         __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            const uint32_t y = tid >= off ? buf[tid - off] : 0u;
-            __syncthreads();
-            buf[tid] += y;
-            __syncthreads();
+        buf[tid] += y;
+        __syncthreads();
+    }
+    uint32_t base = buf[tid] - run;
+    for (int j = 0; j < per; ++j) {
+        if (b0 + j < n) {
+            const uint32_t x = hist[b0 + j];
+            hist[b0 + j] = base;
+            base += x;
         }
-        if (i < n) hist[i] = carry + buf[tid] - x;
-        __syncthreads();
-        if (tid == 1023) carry += buf[1023];
-        __syncthreads();
     }
 }
 
@@ -233,7 +236,24 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, size_t n, uint32_t v) {
     if (i < n) p[i] = v;
 }
 
+// zero three float ranges in one launch
+__global__ void k_zero3(float* __restrict__ a, size_t na, float* __restrict__ b, size_t nb, float* __restrict__ c,
+                        size_t nc) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < na) { a[i] = 0.f; return; }
+    i -= na;
+    if (i < nb) { b[i] = 0.f; return; }
+    i -= nb;
+    if (i < nc) c[i] = 0.f;
+}
+
 // ------------------------------------------------------------- launchers
+void launch_zero3(float* a, size_t na, float* b, size_t nb, float* c, size_t nc, hipStream_t s) {
+    const size_t n = na + nb + nc;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_zero3, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, na, b, nb, c, nc);
+}
+
 void launch_fill_u32(void* p, size_t n, uint32_t v, hipStream_t s) {
     if (n == 0) return;
     const size_t blocks = (n + 255) / 256;

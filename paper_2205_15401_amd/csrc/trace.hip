@@ -108,6 +108,13 @@ __device__ __forceinline__ int tile_of_block(const TraceArgs& A) {
     return xcd_tile(blockIdx.x, gridDim.x);
 }
 
+// Largest kept count in the wave, as a scalar (uniform branches on it).
+__device__ __forceinline__ int wave_max_keff(int keff) {
+    int kmax = keff;
+    for (int off = WAVE / 2; off > 0; off >>= 1) kmax = max(kmax, __shfl_xor(kmax, off));
+    return __builtin_amdgcn_readfirstlane(kmax);
+}
+
 // ------------------------------------------------------------------ select
 template <int KB>
 __global__ __launch_bounds__(TILE_THREADS) void k_select(TraceArgs A) {
@@ -197,23 +204,25 @@ __global__ __launch_bounds__(TILE_THREADS) void k_blend(TraceArgs A) {
     const PixelCtx P = pixel_of(tile, ntx, A.H, A.W, A.cx, A.cy);
     const size_t S = A.S;
     const int keff = P.valid ? A.keff[P.q] : 0;
-    int kmax = keff;
-    for (int off = WAVE / 2; off > 0; off >>= 1) kmax = max(kmax, __shfl_xor(kmax, off));
+    const int kmax = wave_max_keff(keff);
+    const double* pl = A.kl_l + P.q;
+    const float* pm = A.kl_m + P.q;
+    const float* ps = A.kl_s + P.q;
 
     double lk[KB];
     float E[KB];
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
-        lk[k] = k < keff ? A.kl_l[(size_t)k * S + P.q] : 0.0;
+        lk[k] = k < keff ? pl[(size_t)k * S] : 0.0;
         E[k] = 0.f;
     }
     // E_k = sum_m m_m Phi((l_k - l_m) s_m): m streams from the list, k in registers
     for (int m = 0; m < kmax; ++m) {
         const bool in = m < keff;
-        const size_t o = (size_t)m * S + P.q;
-        const double lm = in ? A.kl_l[o] : 0.0;
-        const float mm = in ? A.kl_m[o] : 0.f;
-        const float sm = in ? A.kl_s[o] : 1.f;
+        const size_t o = (size_t)m * S;
+        const double lm = in ? pl[o] : 0.0;
+        const float mm = in ? pm[o] : 0.f;
+        const float sm = in ? ps[o] : 1.f;
 #pragma unroll
         for (int k = 0; k < KB; ++k) {
             if (k < kmax) {
@@ -266,8 +275,12 @@ __global__ __launch_bounds__(TILE_THREADS) void k_blend(TraceArgs A) {
 //     dq/dM = -S V,  dq/dS = -V V^T / 2,  dq/dD' = l S V
 //     dl/dM = S D'/a, dl/dS = sym(D' V^T)/a, dl/dD' = (S V - l S D')/a
 //     da/dS = D' D'^T, da/dD' = 2 S D'
-// Per-kernel sums are pre-reduced per tile in an LDS hash table keyed by
-// rank and added to global memory once per (tile, kernel, value).
+//
+// Reduction over pixels without float atomics in LDS: the pixel lanes leave
+// per-pair scalars (dq, dl, da, W) in the list scratch, a counting sort in
+// LDS groups the tile's (pixel, slot) pairs by kernel, and one lane per kernel
+// walks its pairs, runs the chain in FP64 and accumulates in registers; each
+// (tile, kernel) then makes one global atomic add per output value.
 
 __device__ __forceinline__ int hash_slot(int* s_hkey, int hmask, int rank) {
     int h = (int)(((uint32_t)rank * 2654435761u) >> 7) & hmask;
@@ -284,54 +297,164 @@ __device__ __forceinline__ double wave_sum(double x) {
     return x;
 }
 
+// The chain for one (pixel, kernel) pair: camera-space gradient of the
+// centre (out[0..2]) and of the symmetric inverse covariance (out[3..8],
+// xx xy xz yy yz zz), and dL/dD' added to gD.
+__device__ __forceinline__ void pair_chain(const GeoRec& G, double D0, double D1, double D2, double l, double dq,
+                                           double dlt, double dat, double out[9], double gD[3]) {
+    const double s0 = G.S[0], s1 = G.S[1], s2 = G.S[2], s3 = G.S[3], s4 = G.S[4], s5 = G.S[5];
+    const double V0 = G.M[0] - l * D0, V1 = G.M[1] - l * D1, V2 = G.M[2] - l * D2;
+    const double SV0 = s0 * V0 + s1 * V1 + s2 * V2;
+    const double SV1 = s1 * V0 + s3 * V1 + s4 * V2;
+    const double SV2 = s2 * V0 + s4 * V1 + s5 * V2;
+    const double SD0 = s0 * D0 + s1 * D1 + s2 * D2;
+    const double SD1 = s1 * D0 + s3 * D1 + s4 * D2;
+    const double SD2 = s2 * D0 + s4 * D1 + s5 * D2;
+    const double ia = 1.0 / (D0 * SD0 + D1 * SD1 + D2 * SD2);
+    const double dlk = dlt * ia;
+    const double hq = -0.5 * dq;
+    out[0] = -dq * SV0 + dlk * SD0;
+    out[1] = -dq * SV1 + dlk * SD1;
+    out[2] = -dq * SV2 + dlk * SD2;
+    out[3] = hq * V0 * V0 + dlk * D0 * V0 + dat * D0 * D0;
+    out[4] = hq * V0 * V1 + dlk * 0.5 * (D0 * V1 + D1 * V0) + dat * D0 * D1;
+    out[5] = hq * V0 * V2 + dlk * 0.5 * (D0 * V2 + D2 * V0) + dat * D0 * D2;
+    out[6] = hq * V1 * V1 + dlk * D1 * V1 + dat * D1 * D1;
+    out[7] = hq * V1 * V2 + dlk * 0.5 * (D1 * V2 + D2 * V1) + dat * D1 * D2;
+    out[8] = hq * V2 * V2 + dlk * D2 * V2 + dat * D2 * D2;
+    gD[0] += dq * l * SV0 + dlk * (SV0 - l * SD0) + 2.0 * dat * SD0;
+    gD[1] += dq * l * SV1 + dlk * (SV1 - l * SD1) + 2.0 * dat * SD1;
+    gD[2] += dq * l * SV2 + dlk * (SV2 - l * SD2) + 2.0 * dat * SD2;
+}
+
+// LDS of k_bwd: hash keys, pair counts, offsets and the compact list of
+// used table entries (hcap ints each).
+size_t bwd_lds_bytes(int hcap, int KB) {
+    (void)KB;
+    const size_t table = (size_t)hcap * 4 * sizeof(int);
+    const size_t partials = (size_t)TILE_THREADS * (2 * (9 + 8) * sizeof(float) + 2 * sizeof(int));
+    return table > partials ? table : partials;
+}
+
+// One (pixel, kernel) pair of a tile, stored in kernel-sorted order.
+struct __align__(16) PairRec {
+    float dq, dl, da, w;   // dL/dq, dL/dl (D' units), dL/da, W
+    double l;              // depth l (D' units)
+    int pt;                // pixel within the tile (lane id)
+    int rank;              // kernel rank
+};
+static_assert(sizeof(PairRec) == 32, "PairRec is 32 bytes");
+
+constexpr int RED_CH = 8;              // attribute channels per reduction pass
+constexpr int RED_NV = 9 + RED_CH;     // values per partial sum
+
+// Add one kernel's partial sums to global memory: the 9 geometric values
+// (pass 0 only) and attribute channels c0 .. c0+nc-1.
+__device__ __forceinline__ void flush_values(const TraceArgs& A, int rank, const float* v, bool geom, int c0,
+                                             int nc) {
+    if (geom) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) unsafeAtomicAdd(&A.gM[(size_t)rank * 3 + q], v[q]);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) unsafeAtomicAdd(&A.gS[(size_t)rank * 6 + q], v[3 + q]);
+    }
+    const size_t idx = A.rec[rank].idx;
+    for (int q = 0; q < nc; ++q) unsafeAtomicAdd(&A.grad_attrs[idx * A.C + c0 + q], v[9 + q]);
+}
+
 template <int KB>
 __global__ __launch_bounds__(TILE_THREADS) void k_bwd(TraceArgs A, int hcap) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double s_red[TILE_THREADS / WAVE][3];
+    __shared__ int s_scan[TILE_THREADS];
+    __shared__ int s_scan2[TILE_THREADS];
     const int tid = threadIdx.x;
     const int ntx = (A.W + TILE - 1) / TILE;
     const int tile = tile_of_block(A);
     const PixelCtx P = pixel_of(tile, ntx, A.H, A.W, A.cx, A.cy);
     const size_t S = A.S;
-    const int C = A.C, NACC = 9 + C;
-
+    const int C = A.C;
     int* s_hkey = reinterpret_cast<int*>(smem);
-    float* s_acc = reinterpret_cast<float*>(smem + sizeof(int) * hcap);
-    for (int i = tid; i < hcap; i += TILE_THREADS) s_hkey[i] = -1;
-    for (int i = tid; i < hcap * NACC; i += TILE_THREADS) s_acc[i] = 0.f;
+    int* s_cnt = s_hkey + hcap;
+    int* s_off = s_cnt + hcap;
+    int* s_used = s_off + hcap;
+    __shared__ int s_nused;
+    for (int i = tid; i < hcap; i += TILE_THREADS) {
+        s_hkey[i] = -1;
+        s_cnt[i] = 0;
+    }
 
     const int keff = P.valid ? A.keff[P.q] : 0;
-    int kmax = keff;
-    for (int off = WAVE / 2; off > 0; off >>= 1) kmax = max(kmax, __shfl_xor(kmax, off));
+    const int kmax = wave_max_keff(keff);
     const size_t p = (size_t)P.pi * A.W + P.pj;
+    const double* pl = A.kl_l + P.q;
+    const float* pm = A.kl_m + P.q;
+    const float* ps = A.kl_s + P.q;
+    const float* pT = A.kl_T + P.q;
+    const int* pi = A.kl_i + P.q;
+    float4* pbw = A.bw + P.q;
+    const float* Gp = A.grad_image + p * C;
+    PairRec* tile_pairs = A.pairs + (size_t)tile * TILE_THREADS * A.K;
 
     double lk[KB];
     float dE[KB], dl[KB], dmd[KB];
+    int ik[KB];
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
         lk[k] = 0.0;
         dE[k] = 0.f;
         dl[k] = 0.f;
         dmd[k] = 0.f;
+        ik[k] = 0;
         if (k < keff) {
-            const size_t o = (size_t)k * S + P.q;
-            lk[k] = A.kl_l[o];
-            const float T = A.kl_T[o];
-            const float W = T * A.kl_m[o];
-            const int ik = A.kl_i[o];
-            float g = 0.f;
-            for (int c = 0; c < C; ++c) g = fmaf(A.grad_image[p * C + c], A.attrs[(size_t)ik * C + c], g);
-            dE[k] = -g * W;
-            dmd[k] = g * T;
+            lk[k] = pl[(size_t)k * S];
+            ik[k] = pi[(size_t)k * S];
+        }
+    }
+    // g_k = G . c_k
+    float g[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) g[k] = 0.f;
+    if (keff > 0) {
+        if ((C & 3) == 0) {
+            const float4* G4 = reinterpret_cast<const float4*>(Gp);
+            const float4* A4 = reinterpret_cast<const float4*>(A.attrs);
+            const int C4 = C >> 2;
+            for (int c = 0; c < C4; ++c) {
+                const float4 Gc = G4[c];
+#pragma unroll
+                for (int k = 0; k < KB; ++k) {
+                    if (k < keff) {
+                        const float4 a = A4[(size_t)ik[k] * C4 + c];
+                        g[k] = fmaf(Gc.x, a.x, fmaf(Gc.y, a.y, fmaf(Gc.z, a.z, fmaf(Gc.w, a.w, g[k]))));
+                    }
+                }
+            }
+        } else {
+            for (int c = 0; c < C; ++c) {
+                const float Gc = Gp[c];
+#pragma unroll
+                for (int k = 0; k < KB; ++k)
+                    if (k < keff) g[k] = fmaf(Gc, A.attrs[(size_t)ik[k] * C + c], g[k]);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        if (k < keff) {
+            const float T = pT[(size_t)k * S];
+            const float W = T * pm[(size_t)k * S];
+            dE[k] = -g[k] * W;
+            dmd[k] = g[k] * T;
         }
     }
     // pair loop: m streams from the list; its sums over k go to the scratch list
     for (int m = 0; m < kmax; ++m) {
         const bool in = m < keff;
-        const size_t o = (size_t)m * S + P.q;
-        const double lm = in ? A.kl_l[o] : 0.0;
-        const float mm = in ? A.kl_m[o] : 0.f;
-        const float sm = in ? A.kl_s[o] : 1.f;
+        const size_t o = (size_t)m * S;
+        const double lm = in ? pl[o] : 0.0;
+        const float mm = in ? pm[o] : 0.f;
+        const float sm = in ? ps[o] : 1.f;
         const float hs = 0.5f / sm;
         float acc_dm = 0.f, acc_dl = 0.f, acc_da = 0.f;
 #pragma unroll
@@ -349,93 +472,208 @@ __global__ __launch_bounds__(TILE_THREADS) void k_bwd(TraceArgs A, int hcap) {
                 acc_da = fmaf(dx, d * hs, acc_da);
             }
         }
-        if (in) A.bw[o] = make_float4(acc_dm, acc_dl, acc_da, 0.f);
+        if (in) pbw[o] = make_float4(acc_dm, acc_dl, acc_da, 0.f);
     }
-    __syncthreads();   // LDS table initialised
-
-    double gDx = 0.0, gDy = 0.0, gDz = 0.0;
-    const double D0 = P.u, D1 = P.v, D2 = (double)A.F;
+    // per-pair scalars: dq = dL/dq, dl = dL/dl (D' units), da = dL/da, W
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
-        if (k >= keff) continue;
-        const size_t o = (size_t)k * S + P.q;
-        const float4 acc = A.bw[o];
-        const int rank = A.kl_r[o];
-        const int ik = A.kl_i[o];
-        const float mk = A.kl_m[o];
-        const float Wk = A.kl_T[o] * mk;
-        const GeoRec& G = A.geo[rank];
-        const double s0 = G.S[0], s1 = G.S[1], s2 = G.S[2], s3 = G.S[3], s4 = G.S[4], s5 = G.S[5];
-        const double l = lk[k];
-        const double V0 = G.M[0] - l * D0, V1 = G.M[1] - l * D1, V2 = G.M[2] - l * D2;
-        const double SV0 = s0 * V0 + s1 * V1 + s2 * V2;
-        const double SV1 = s1 * V0 + s3 * V1 + s4 * V2;
-        const double SV2 = s2 * V0 + s4 * V1 + s5 * V2;
-        const double SD0 = s0 * D0 + s1 * D1 + s2 * D2;
-        const double SD1 = s1 * D0 + s3 * D1 + s4 * D2;
-        const double SD2 = s2 * D0 + s4 * D1 + s5 * D2;
-        const double ia = 1.0 / (D0 * SD0 + D1 * SD1 + D2 * SD2);
-        const double dq = ((double)dmd[k] + (double)acc.x) * (double)mk;
-        const double dlk = ((double)dl[k] + (double)acc.y) * ia;
-        const double dak = (double)acc.z;
-        const double hq = -0.5 * dq;
-        float out[9];
-        out[0] = (float)(-dq * SV0 + dlk * SD0);
-        out[1] = (float)(-dq * SV1 + dlk * SD1);
-        out[2] = (float)(-dq * SV2 + dlk * SD2);
-        out[3] = (float)(hq * V0 * V0 + dlk * D0 * V0 + dak * D0 * D0);
-        out[4] = (float)(hq * V0 * V1 + dlk * 0.5 * (D0 * V1 + D1 * V0) + dak * D0 * D1);
-        out[5] = (float)(hq * V0 * V2 + dlk * 0.5 * (D0 * V2 + D2 * V0) + dak * D0 * D2);
-        out[6] = (float)(hq * V1 * V1 + dlk * D1 * V1 + dak * D1 * D1);
-        out[7] = (float)(hq * V1 * V2 + dlk * 0.5 * (D1 * V2 + D2 * V1) + dak * D1 * D2);
-        out[8] = (float)(hq * V2 * V2 + dlk * D2 * V2 + dak * D2 * D2);
-        gDx += dq * l * SV0 + dlk * (SV0 - l * SD0) + 2.0 * dak * SD0;
-        gDy += dq * l * SV1 + dlk * (SV1 - l * SD1) + 2.0 * dak * SD1;
-        gDz += dq * l * SV2 + dlk * (SV2 - l * SD2) + 2.0 * dak * SD2;
-
-        const int slot = hash_slot(s_hkey, hcap - 1, rank);
-        if (slot >= 0) {
-            float* dst = s_acc + (size_t)slot * NACC;
-#pragma unroll
-            for (int e = 0; e < 9; ++e) atomicAdd(&dst[e], out[e]);
-            for (int c = 0; c < C; ++c) atomicAdd(&dst[9 + c], Wk * A.grad_image[p * C + c]);
-        } else {
-#pragma unroll
-            for (int e = 0; e < 3; ++e) unsafeAtomicAdd(&A.gM[(size_t)rank * 3 + e], out[e]);
-#pragma unroll
-            for (int e = 0; e < 6; ++e) unsafeAtomicAdd(&A.gS[(size_t)rank * 6 + e], out[3 + e]);
-            for (int c = 0; c < C; ++c)
-                unsafeAtomicAdd(&A.grad_attrs[(size_t)ik * C + c], Wk * A.grad_image[p * C + c]);
+        if (k < keff) {
+            const size_t o = (size_t)k * S;
+            const float4 acc = pbw[o];
+            const float mk = pm[o];
+            pbw[o] = make_float4((dmd[k] + acc.x) * mk, dl[k] + acc.y, acc.z, pT[o] * mk);
         }
+    }
+    __syncthreads();   // table initialised
+
+    // counting sort of the tile's pairs by kernel; sp[k] = table slot << 16 | position
+    int sp[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        sp[k] = -1;
+        if (k < keff) {
+            const int sl = hash_slot(s_hkey, hcap - 1, A.kl_r[P.q + (size_t)k * S]);
+            if (sl >= 0) sp[k] = (sl << 16) | atomicAdd(&s_cnt[sl], 1);
+        }
+    }
+    __syncthreads();
+    // exclusive scans: s_cnt -> s_off, and the used entries -> s_used
+    {
+        const int per = (hcap + TILE_THREADS - 1) / TILE_THREADS;
+        int run = 0, nu = 0;
+        for (int j = 0; j < per; ++j) {
+            const int i = tid * per + j;
+            if (i < hcap) {
+                run += s_cnt[i];
+                nu += s_cnt[i] > 0;
+            }
+        }
+        s_scan[tid] = run;
+        s_scan2[tid] = nu;
+        __syncthreads();
+        for (int off = 1; off < TILE_THREADS; off <<= 1) {
+            const int y = tid >= off ? s_scan[tid - off] : 0;
+            const int y2 = tid >= off ? s_scan2[tid - off] : 0;
+            __syncthreads();
+            s_scan[tid] += y;
+            s_scan2[tid] += y2;
+            __syncthreads();
+        }
+        int base = s_scan[tid] - run, ub = s_scan2[tid] - nu;
+        for (int j = 0; j < per; ++j) {
+            const int i = tid * per + j;
+            if (i < hcap) {
+                s_off[i] = base;
+                base += s_cnt[i];
+                if (s_cnt[i] > 0) s_used[ub++] = i;
+            }
+        }
+        if (tid == TILE_THREADS - 1) s_nused = s_scan2[tid];
+    }
+    __syncthreads();
+    double gD[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        if (k < keff) {
+            if (sp[k] >= 0) {
+                const size_t o = (size_t)k * S;
+                const float4 sc = pbw[o];
+                PairRec r;
+                r.dq = sc.x;
+                r.dl = sc.y;
+                r.da = sc.z;
+                r.w = sc.w;
+                r.l = pl[o];
+                r.pt = tid;
+                r.rank = A.kl_r[P.q + o];
+                tile_pairs[s_off[sp[k] >> 16] + (sp[k] & 0xFFFF)] = r;
+            } else {
+                // table full: this pair goes straight to global memory
+                const size_t o = (size_t)k * S;
+                const int rank = A.kl_r[P.q + o];
+                const int idx = pi[o];
+                const float4 sc = pbw[o];
+                double out[9];
+                pair_chain(A.geo[rank], P.u, P.v, (double)A.F, pl[o], sc.x, sc.y, sc.z, out, gD);
+#pragma unroll
+                for (int e = 0; e < 3; ++e) unsafeAtomicAdd(&A.gM[(size_t)rank * 3 + e], (float)out[e]);
+#pragma unroll
+                for (int e = 0; e < 6; ++e) unsafeAtomicAdd(&A.gS[(size_t)rank * 6 + e], (float)out[3 + e]);
+                for (int c = 0; c < C; ++c) unsafeAtomicAdd(&A.grad_attrs[(size_t)idx * C + c], sc.w * Gp[c]);
+            }
+        }
+    }
+    __syncthreads();
+
+    // Balanced segmented reduction.  Lane t takes an equal, contiguous chunk
+    // of the tile's kernel-sorted pairs and sums runs of equal kernels.  A run
+    // that lies inside the chunk is complete and is added to global memory at
+    // once; the first and last runs of a chunk may continue in the neighbouring
+    // chunks, so they go to LDS, and the lane where a kernel's run starts adds
+    // up the continuation and flushes it: one global add per (tile, kernel,
+    // value).  Pass 0 reduces the 9 geometric values and the first RED_CH
+    // attribute channels, later passes the next RED_CH channels.
+    const int ti0 = (tile / ntx) * TILE, tj0 = (tile % ntx) * TILE;
+    const int n_pairs = s_off[hcap - 1] + s_cnt[hcap - 1];
+    __syncthreads();   // the table's LDS becomes the partial-sum buffers
+    float* s_head = reinterpret_cast<float*>(smem);
+    float* s_tail = s_head + TILE_THREADS * RED_NV;
+    int* s_hk = reinterpret_cast<int*>(s_tail + TILE_THREADS * RED_NV);
+    int* s_tk = s_hk + TILE_THREADS;
+    const int per = (n_pairs + TILE_THREADS - 1) / TILE_THREADS;
+    const int j0 = min(n_pairs, tid * per), j1 = min(n_pairs, j0 + per);
+    for (int c0 = 0; c0 == 0 || c0 < C; c0 += RED_CH) {
+        const bool geom = c0 == 0;
+        const int nc = max(0, min(RED_CH, C - c0));
+        const int v0 = geom ? 0 : 9;              // first value slot in use
+        float acc[RED_NV];
+#pragma unroll
+        for (int q = 0; q < RED_NV; ++q) acc[q] = 0.f;
+        int cur = -1, nseg = 0;
+        GeoRec G;
+        s_hk[tid] = -1;
+        s_tk[tid] = -1;
+        for (int j = j0; j <= j1; ++j) {
+            const bool end = j == j1;
+            const PairRec r = end ? PairRec{} : tile_pairs[j];
+            if (end || r.rank != cur) {
+                if (cur >= 0) {
+                    if (nseg == 0) {                                   // first run: may continue
+                        s_hk[tid] = cur;
+                        for (int q = v0; q < RED_NV; ++q) s_head[tid * RED_NV + q] = acc[q];
+                    } else if (end) {                                  // last run: may continue
+                        s_tk[tid] = cur;
+                        for (int q = v0; q < RED_NV; ++q) s_tail[tid * RED_NV + q] = acc[q];
+                    } else {                                           // complete run
+                        flush_values(A, cur, acc, geom, c0, nc);
+                    }
+                    ++nseg;
+                }
+                if (end) break;
+#pragma unroll
+                for (int q = 0; q < RED_NV; ++q) acc[q] = 0.f;
+                cur = r.rank;
+                if (geom) G = A.geo[cur];
+            }
+            const int w = r.pt / WAVE, ln = r.pt % WAVE;
+            const int row = ti0 + (w >> 1) * 8 + (ln >> 3), col = tj0 + (w & 1) * 8 + (ln & 7);
+            if (geom) {
+                double out[9];
+                pair_chain(G, (double)row - (double)A.cy, (double)col - (double)A.cx, (double)A.F, r.l, r.dq, r.dl,
+                           r.da, out, gD);
+#pragma unroll
+                for (int q = 0; q < 9; ++q) acc[q] += (float)out[q];
+            }
+            const float* Gq = A.grad_image + ((size_t)row * A.W + col) * C + c0;
+            if (nc == RED_CH && (C & 3) == 0) {
+#pragma unroll
+                for (int q = 0; q < RED_CH; q += 4) {
+                    const float4 g4 = *reinterpret_cast<const float4*>(Gq + q);
+                    acc[9 + q] = fmaf(r.w, g4.x, acc[9 + q]);
+                    acc[10 + q] = fmaf(r.w, g4.y, acc[10 + q]);
+                    acc[11 + q] = fmaf(r.w, g4.z, acc[11 + q]);
+                    acc[12 + q] = fmaf(r.w, g4.w, acc[12 + q]);
+                }
+            } else {
+                for (int q = 0; q < nc; ++q) acc[9 + q] = fmaf(r.w, Gq[q], acc[9 + q]);
+            }
+        }
+        __syncthreads();
+        // the lane where a kernel's run starts adds the continuation and flushes
+        for (int which = 0; which < 2; ++which) {
+            const int k = which == 0 ? s_hk[tid] : s_tk[tid];
+            if (k < 0) continue;
+            if (which == 0 && tid > 0) {
+                const int prev = s_tk[tid - 1] >= 0 ? s_tk[tid - 1] : s_hk[tid - 1];
+                if (prev == k) continue;                               // started in an earlier chunk
+            }
+            const float* own = (which == 0 ? s_head : s_tail) + tid * RED_NV;
+            float sum[RED_NV];
+#pragma unroll
+            for (int q = 0; q < RED_NV; ++q) sum[q] = q >= v0 ? own[q] : 0.f;
+            for (int t2 = tid + 1; t2 < TILE_THREADS && s_hk[t2] == k; ++t2) {
+                if (which == 0 && s_tk[tid] >= 0) break;              // own head run ended in this chunk
+                for (int q = v0; q < RED_NV; ++q) sum[q] += s_head[t2 * RED_NV + q];
+                if (s_tk[t2] >= 0) break;                             // the run ends inside chunk t2
+            }
+            flush_values(A, k, sum, geom, c0, nc);
+        }
+        __syncthreads();
     }
 
     // per-tile sum of dL/dD' (for the intrinsics), fixed order
     const int wave = tid / WAVE, lane = tid % WAVE;
-    gDx = wave_sum(gDx);
-    gDy = wave_sum(gDy);
-    gDz = wave_sum(gDz);
+    const double gx = wave_sum(gD[0]), gy = wave_sum(gD[1]), gz = wave_sum(gD[2]);
     if (lane == 0) {
-        s_red[wave][0] = gDx;
-        s_red[wave][1] = gDy;
-        s_red[wave][2] = gDz;
+        s_red[wave][0] = gx;
+        s_red[wave][1] = gy;
+        s_red[wave][2] = gz;
     }
     __syncthreads();
     if (tid < 3) {
-        double s = 0.0;
-        for (int w = 0; w < TILE_THREADS / WAVE; ++w) s += s_red[w][tid];
-        A.tileD[(size_t)tile * 3 + tid] = s;
-    }
-    // flush the table: one global add per (tile, kernel, value)
-    for (int i = tid; i < hcap; i += TILE_THREADS) {
-        const int rank = s_hkey[i];
-        if (rank < 0) continue;
-        const float* acc = s_acc + (size_t)i * NACC;
-#pragma unroll
-        for (int e = 0; e < 3; ++e) unsafeAtomicAdd(&A.gM[(size_t)rank * 3 + e], acc[e]);
-#pragma unroll
-        for (int e = 0; e < 6; ++e) unsafeAtomicAdd(&A.gS[(size_t)rank * 6 + e], acc[3 + e]);
-        const size_t idx = A.rec[rank].idx;
-        for (int c = 0; c < C; ++c) unsafeAtomicAdd(&A.grad_attrs[idx * C + c], acc[9 + c]);
+        double sum = 0.0;
+        for (int w = 0; w < TILE_THREADS / WAVE; ++w) sum += s_red[w][tid];
+        A.tileD[(size_t)tile * 3 + tid] = sum;
     }
 }
 
@@ -455,11 +693,8 @@ int pick_kbuf(int K) {
 }
 
 int table_capacity(int C) {
-    // LDS budget for the per-tile gradient table: 64 KiB
-    const size_t per = sizeof(int) + sizeof(float) * (size_t)(9 + C);
-    int cap = 1024;
-    while (cap > 1 && (size_t)cap * per > 65536) cap >>= 1;
-    return cap;
+    (void)C;
+    return 1024;   // distinct kernels one tile can reduce in LDS; more go to global atomics
 }
 
 template <int KB>
@@ -471,8 +706,7 @@ static hipError_t run_kb(int which, const TraceArgs& a, hipStream_t s) {
         hipLaunchKernelGGL(k_blend<KB>, dim3(nt), dim3(TILE_THREADS), 0, s, a);
     } else {
         const int hcap = table_capacity(a.C);
-        const size_t smem = (size_t)hcap * (sizeof(int) + sizeof(float) * (size_t)(9 + a.C));
-        hipLaunchKernelGGL(k_bwd<KB>, dim3(nt), dim3(TILE_THREADS), smem, s, a, hcap);
+        hipLaunchKernelGGL(k_bwd<KB>, dim3(nt), dim3(TILE_THREADS), bwd_lds_bytes(hcap, KB), s, a, hcap);
     }
     return hipGetLastError();
 }

@@ -9,6 +9,8 @@
 
 namespace voge {
 
+struct PairRec;
+
 // Device pointers into one caller-owned workspace (see plan_workspace).
 struct WsPtrs {
     WsHeader* hdr;
@@ -29,12 +31,13 @@ struct WsPtrs {
     int32_t* kl_r;    // rank (depth-bound order)
     int32_t* kl_i;    // original kernel index
     float4* bw;       // backward scratch: per-slot sums over the pair loop
+    PairRec* pairs;   // backward scratch: per-tile pair records, kernel-sorted [tiles][256 * K]
 };
 
 struct Plan {
     size_t off_keys, off_vals, off_keys2, off_vals2, off_hist, off_cull, off_rec, off_geo;
     size_t off_keff, off_kl_l, off_kl_m, off_kl_s, off_kl_T, off_kl_r, off_kl_i;
-    size_t off_gM, off_gS, off_tileD, off_camP, off_bw;
+    size_t off_gM, off_gS, off_tileD, off_camP, off_bw, off_pairs;
     size_t fwd_bytes, bwd_bytes;
     size_t S;          // list stride: n_tiles * 256
     int n_tiles, n_epi_blocks, sort_blocks;
@@ -47,6 +50,7 @@ int sort_blocks(int N);
 constexpr int EPI_THREADS = 256;
 
 void launch_fill_u32(void* p, size_t n, uint32_t v, hipStream_t s);
+void launch_zero3(float* a, size_t na, float* b, size_t nb, float* c, size_t nc, hipStream_t s);
 void launch_prep(const float* means, const float* covs, int N, const CamDev& cam, double rad2, const WsPtrs& w,
                  hipStream_t s);
 
@@ -79,10 +83,12 @@ struct TraceArgs {
     float* gS;
     double* tileD;
     float4* bw;
+    PairRec* pairs;
 };
 
 int pick_kbuf(int K);        // compiled K-buffer depth for a requested K
 int table_capacity(int C);   // entries of the per-tile gradient table
+size_t bwd_lds_bytes(int hcap, int KB);
 hipError_t launch_select(const TraceArgs& a, hipStream_t s);
 hipError_t launch_blend(const TraceArgs& a, hipStream_t s);
 hipError_t launch_bwd(const TraceArgs& a, hipStream_t s);
