@@ -260,9 +260,11 @@ int voge_workspace_size(int N, int C, const voge_camera_t* cam, const voge_param
 
 namespace {
 
-voge::TraceArgs trace_args(const voge::WsPtrs& w, const voge::Plan& p, int N, int C, const voge_camera_t* cam,
-                           const voge_params_t* params, const float* attrs) {
+voge::TraceArgs trace_args(const voge_ctx_t* ctx, const voge::WsPtrs& w, const voge::Plan& p, int N, int C,
+                           const voge_camera_t* cam, const voge_params_t* params, const float* attrs) {
     voge::TraceArgs ta{};
+    ta.hdr = w.hdr;
+    ta.n_cu = ctx->n_cu;
     ta.cull = w.cull;
     ta.rec = w.rec;
     ta.geo = w.geo;
@@ -327,7 +329,7 @@ int voge_render_forward(voge_ctx_t* ctx, const float* means, const float* covs, 
     if (!guard.ok) return fail(VOGE_EHIP, "cannot select the context's device");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const voge::WsPtrs w = voge::carve(workspace, p, false);
-    voge::TraceArgs ta = trace_args(w, p, N, C, cam, params, attrs);
+    voge::TraceArgs ta = trace_args(ctx, w, p, N, C, cam, params, attrs);
     ta.image = image;
     ta.wsum = wsum;
     ta.kept = kept;
@@ -353,7 +355,7 @@ int voge_render_backward(voge_ctx_t* ctx, const float* means, const float* covs,
     if (!guard.ok) return fail(VOGE_EHIP, "cannot select the context's device");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const voge::WsPtrs w = voge::carve(workspace, p, true);
-    voge::TraceArgs ta = trace_args(w, p, N, C, cam, params, attrs);
+    voge::TraceArgs ta = trace_args(ctx, w, p, N, C, cam, params, attrs);
     if (!(flags & VOGE_REUSE_PREP)) {
         if (int rc = run_forward(ctx, means, covs, cam, w, ta, s)) return rc;   // lists and T, no image
     }
@@ -366,6 +368,10 @@ int voge_render_backward(voge_ctx_t* ctx, const float* means, const float* covs,
     {
         ProfScope ps(ctx, "bwd", s);
         if (int rc = hip_check(voge::launch_bwd(ta, s), "backward launch")) return rc;
+    }
+    {
+        ProfScope ps(ctx, "bwd_reduce", s);
+        if (int rc = hip_check(voge::launch_bwd_reduce(ta, s), "backward reduce launch")) return rc;
     }
     voge::EpiArgs ea{};
     ea.means = means;

@@ -72,13 +72,36 @@ __device__ __forceinline__ PixelCtx pixel_of(int tile, int ntx, int H, int W, fl
     return P;
 }
 
-// The ray-tracing formulas; explicit fma() fixes the evaluation order.
-__device__ __forceinline__ void trace_one(const TraceRec& R, double u, double v, double& l, double& q2, double& a) {
+// b / a for a > 0: hardware reciprocal estimate, two Newton steps and a
+// residual correction (within an ulp or two of the rounded quotient).
+__device__ __forceinline__ double div_pos(double b, double a) {
+    double r = __builtin_amdgcn_rcp(a);
+    r = fma(fma(-a, r, 1.0), r, r);
+    r = fma(fma(-a, r, 1.0), r, r);
+    const double q = b * r;
+    return fma(fma(-a, q, b), r, q);
+}
+
+// The ray-tracing formulas; explicit fma() fixes the evaluation order so
+// every recomputation reproduces the same bits.
+template <typename Rec>
+__device__ __forceinline__ void trace_one(const Rec& R, double u, double v, double& l, double& q2, double& a) {
     a = fma(u, fma(R.A0, u, fma(R.A1, v, R.A2)), fma(v, fma(R.A3, v, R.A4), R.A5));
     const double b = fma(R.B0, u, fma(R.B1, v, R.B2));
-    l = b / a;
+    l = div_pos(b, a);
     q2 = fma(-b, l, R.c);
 }
+
+// A candidate staged in LDS: the trace coefficients with its screen bounds.
+struct __align__(16) StagedRec {
+    double A0, A1, A2, A3, A4, A5;
+    double B0, B1, B2;
+    double c;
+    float tlo;
+    uint32_t rank;
+    int16_t i0, i1, j0, j1;
+};
+static_assert(sizeof(StagedRec) == 96, "StagedRec is 96 bytes");
 
 __device__ __forceinline__ double key_upper_l(uint64_t key) {
     return __longlong_as_double((long long)(key | RANK_MASK));
@@ -104,8 +127,14 @@ __device__ __forceinline__ void kbuf_insert(uint64_t (&key)[KB], uint64_t nk) {
     }
 }
 
-__device__ __forceinline__ int tile_of_block(const TraceArgs& A) {
-    return xcd_tile(blockIdx.x, gridDim.x);
+// Block -> tile.  Workgroups are dealt round-robin to the 8 XCDs (block b
+// runs on XCD b % 8), so each XCD renders a contiguous band of tiles and the
+// kernels those tiles share stay in that XCD's L2.
+__device__ __forceinline__ int tile_of_block() {
+    const int b = blockIdx.x, nb = gridDim.x;
+    const int x = b & 7, local = b >> 3;
+    const int per = nb >> 3, rem = nb & 7;
+    return x * per + (x < rem ? x : rem) + local;
 }
 
 // Largest kept count in the wave, as a scalar (uniform branches on it).
@@ -117,12 +146,11 @@ __device__ __forceinline__ int wave_max_keff(int keff) {
 
 // ------------------------------------------------------------------ select
 template <int KB>
-__global__ __launch_bounds__(TILE_THREADS) void k_select(TraceArgs A) {
-    __shared__ TraceRec s_rec[TILE_THREADS];
+__device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
+    __shared__ StagedRec s_rec[TILE_THREADS];
     __shared__ int s_wcnt[TILE_THREADS / WAVE];
     const int tid = threadIdx.x, wave = tid / WAVE, lane = tid % WAVE;
     const int ntx = (A.W + TILE - 1) / TILE;
-    const int tile = tile_of_block(A);
     const PixelCtx P = pixel_of(tile, ntx, A.H, A.W, A.cx, A.cy);
     const int ti0 = (tile / ntx) * TILE, tj0 = (tile % ntx) * TILE;
     const int ti1 = ti0 + TILE - 1, tj1 = tj0 + TILE - 1;
@@ -130,14 +158,17 @@ __global__ __launch_bounds__(TILE_THREADS) void k_select(TraceArgs A) {
     uint64_t key[KB];
 #pragma unroll
     for (int s = 0; s < KB; ++s) key[s] = ~0ull;
+    uint64_t kth = ~0ull;                       // the K-th smallest key so far
     bool done = !P.valid;
+    // this wave's 8x8 block, for skipping candidates that cannot reach it
+    const int wi0 = ti0 + (wave >> 1) * 8, wj0 = tj0 + (wave & 1) * 8;
+    CullRec nxt;
+    if (tid < A.N) nxt = A.cull[tid];
     for (int base = 0; base < A.N; base += TILE_THREADS) {
         const int r = base + tid;
-        bool hit = false;
-        if (r < A.N) {
-            const CullRec c = A.cull[r];
-            hit = c.i0 <= ti1 && c.i1 >= ti0 && c.j0 <= tj1 && c.j1 >= tj0;
-        }
+        const CullRec c = nxt;
+        if (r + TILE_THREADS < A.N) nxt = A.cull[r + TILE_THREADS];   // prefetch the next chunk
+        const bool hit = r < A.N && c.i0 <= ti1 && c.i1 >= ti0 && c.j0 <= tj1 && c.j1 >= tj0;
         const uint64_t m = __ballot(hit);
         if (lane == 0) s_wcnt[wave] = __popcll(m);
         __syncthreads();
@@ -148,29 +179,38 @@ __global__ __launch_bounds__(TILE_THREADS) void k_select(TraceArgs A) {
             off += w < wave ? cw : 0;
             total += cw;
         }
-        if (hit) s_rec[off + __popcll(m & lanemask_lt())] = A.rec[r];
+        if (hit) {
+            const TraceRec& g = A.rec[r];
+            StagedRec& d = s_rec[off + __popcll(m & lanemask_lt())];
+            d.A0 = g.A0; d.A1 = g.A1; d.A2 = g.A2; d.A3 = g.A3; d.A4 = g.A4; d.A5 = g.A5;
+            d.B0 = g.B0; d.B1 = g.B1; d.B2 = g.B2; d.c = g.c;
+            d.tlo = c.tlo;
+            d.rank = (uint32_t)r;
+            d.i0 = c.i0; d.i1 = c.i1; d.j0 = c.j0; d.j1 = c.j1;
+        }
         __syncthreads();
-        for (int c = 0; c < total; ++c) {
+        for (int ci = 0; ci < total; ++ci) {
             if (__all(done)) break;
-            const TraceRec& R = s_rec[c];
-            const uint64_t kth = kth_key<KB>(key, A.K);
+            const StagedRec& R = s_rec[ci];
+            // whole-wave skip when the candidate's screen box misses this 8x8 block
+            if (R.i0 > wi0 + 7 || R.i1 < wi0 || R.j0 > wj0 + 7 || R.j1 < wj0) continue;
             if (!done && kth != ~0ull && (double)R.tlo > key_upper_l(kth)) done = true;
             if (!done) {
                 double l, q2, a;
                 trace_one(R, P.u, P.v, l, q2, a);
                 if (q2 < A.rad2 && l > 0.0) {
                     const uint64_t nk = ((uint64_t)__double_as_longlong(l) & ~RANK_MASK) | (uint64_t)R.rank;
-                    if (nk < kth) kbuf_insert<KB>(key, nk);
+                    if (nk < kth) {
+                        kbuf_insert<KB>(key, nk);
+                        kth = kth_key<KB>(key, A.K);
+                    }
                 }
             }
         }
         // every pixel done against the next chunk's first bound ends the tile
         const int nb = base + TILE_THREADS;
         bool fin = done;
-        if (!fin && nb < A.N) {
-            const uint64_t kth = kth_key<KB>(key, A.K);
-            fin = kth != ~0ull && (double)A.cull[nb].tlo > key_upper_l(kth);
-        }
+        if (!fin && nb < A.N) fin = kth != ~0ull && (double)A.cull[nb].tlo > key_upper_l(kth);
         if (__syncthreads_and(fin ? 1 : 0)) break;
     }
 
@@ -198,9 +238,8 @@ __global__ __launch_bounds__(TILE_THREADS) void k_select(TraceArgs A) {
 
 // ------------------------------------------------------------------- blend
 template <int KB>
-__global__ __launch_bounds__(TILE_THREADS) void k_blend(TraceArgs A) {
+__device__ __forceinline__ void blend_body(const TraceArgs& A, int tile) {
     const int ntx = (A.W + TILE - 1) / TILE;
-    const int tile = tile_of_block(A);
     const PixelCtx P = pixel_of(tile, ntx, A.H, A.W, A.cx, A.cy);
     const size_t S = A.S;
     const int keff = P.valid ? A.keff[P.q] : 0;
@@ -217,17 +256,26 @@ __global__ __launch_bounds__(TILE_THREADS) void k_blend(TraceArgs A) {
         E[k] = 0.f;
     }
     // E_k = sum_m m_m Phi((l_k - l_m) s_m): m streams from the list, k in registers
+    // slot m+1 is loaded while slot m is computed
+    double ln = keff > 0 ? pl[0] : 0.0;
+    float mn = keff > 0 ? pm[0] : 0.f, sn = keff > 0 ? ps[0] : 1.f;
     for (int m = 0; m < kmax; ++m) {
-        const bool in = m < keff;
-        const size_t o = (size_t)m * S;
-        const double lm = in ? pl[o] : 0.0;
-        const float mm = in ? pm[o] : 0.f;
-        const float sm = in ? ps[o] : 1.f;
+        const double lm = ln;
+        const float mm = mn, sm = sn;
+        const bool nin = m + 1 < keff;
+        const size_t o = (size_t)(m + 1) * S;
+        ln = nin ? pl[o] : 0.0;
+        mn = nin ? pm[o] : 0.f;
+        sn = nin ? ps[o] : 1.f;
+        // four independent pairs per uniform branch, so their chains interleave
 #pragma unroll
-        for (int k = 0; k < KB; ++k) {
-            if (k < kmax) {
-                const float x = (float)(lk[k] - lm) * sm;
-                E[k] = fmaf(mm, phi_cdf(x), E[k]);
+        for (int k0 = 0; k0 < KB; k0 += 4) {
+            if (k0 < kmax) {
+#pragma unroll
+                for (int k = k0; k < k0 + 4 && k < KB; ++k) {
+                    const float x = (float)(lk[k] - lm) * sm;
+                    E[k] = fmaf(mm, phi_cdf(x), E[k]);
+                }
             }
         }
     }
@@ -362,27 +410,14 @@ __device__ __forceinline__ void flush_values(const TraceArgs& A, int rank, const
     for (int q = 0; q < nc; ++q) unsafeAtomicAdd(&A.grad_attrs[idx * A.C + c0 + q], v[9 + q]);
 }
 
+// Backward, pixel phase: per-pair scalars (dq, dl, da, W) into the scratch list.
 template <int KB>
-__global__ __launch_bounds__(TILE_THREADS) void k_bwd(TraceArgs A, int hcap) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double s_red[TILE_THREADS / WAVE][3];
-    __shared__ int s_scan[TILE_THREADS];
-    __shared__ int s_scan2[TILE_THREADS];
+__device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile) {
     const int tid = threadIdx.x;
     const int ntx = (A.W + TILE - 1) / TILE;
-    const int tile = tile_of_block(A);
     const PixelCtx P = pixel_of(tile, ntx, A.H, A.W, A.cx, A.cy);
     const size_t S = A.S;
     const int C = A.C;
-    int* s_hkey = reinterpret_cast<int*>(smem);
-    int* s_cnt = s_hkey + hcap;
-    int* s_off = s_cnt + hcap;
-    int* s_used = s_off + hcap;
-    __shared__ int s_nused;
-    for (int i = tid; i < hcap; i += TILE_THREADS) {
-        s_hkey[i] = -1;
-        s_cnt[i] = 0;
-    }
 
     const int keff = P.valid ? A.keff[P.q] : 0;
     const int kmax = wave_max_keff(keff);
@@ -394,7 +429,6 @@ __global__ __launch_bounds__(TILE_THREADS) void k_bwd(TraceArgs A, int hcap) {
     const int* pi = A.kl_i + P.q;
     float4* pbw = A.bw + P.q;
     const float* Gp = A.grad_image + p * C;
-    PairRec* tile_pairs = A.pairs + (size_t)tile * TILE_THREADS * A.K;
 
     double lk[KB];
     float dE[KB], dl[KB], dmd[KB];
@@ -449,27 +483,36 @@ __global__ __launch_bounds__(TILE_THREADS) void k_bwd(TraceArgs A, int hcap) {
         }
     }
     // pair loop: m streams from the list; its sums over k go to the scratch list
+    // slot m+1 is loaded while slot m is computed
+    double ln = keff > 0 ? pl[0] : 0.0;
+    float mn = keff > 0 ? pm[0] : 0.f, sn = keff > 0 ? ps[0] : 1.f;
     for (int m = 0; m < kmax; ++m) {
         const bool in = m < keff;
         const size_t o = (size_t)m * S;
-        const double lm = in ? pl[o] : 0.0;
-        const float mm = in ? pm[o] : 0.f;
-        const float sm = in ? ps[o] : 1.f;
+        const double lm = ln;
+        const float mm = mn, sm = sn;
+        const bool nin = m + 1 < keff;
+        ln = nin ? pl[o + S] : 0.0;
+        mn = nin ? pm[o + S] : 0.f;
+        sn = nin ? ps[o + S] : 1.f;
         const float hs = 0.5f / sm;
         float acc_dm = 0.f, acc_dl = 0.f, acc_da = 0.f;
 #pragma unroll
-        for (int k = 0; k < KB; ++k) {
-            if (k < kmax) {
-                const float d = (float)(lk[k] - lm);
-                const float x = d * sm;
-                const float Phi = phi_cdf(x);
-                const float dPhi = __expf(-x * x) * INV_SQRT_PI;
-                acc_dm = fmaf(dE[k], Phi, acc_dm);
-                const float dx = dE[k] * mm * dPhi;
-                const float t = dx * sm;
-                dl[k] += t;
-                acc_dl -= t;
-                acc_da = fmaf(dx, d * hs, acc_da);
+        for (int k0 = 0; k0 < KB; k0 += 4) {
+            if (k0 < kmax) {
+#pragma unroll
+                for (int k = k0; k < k0 + 4 && k < KB; ++k) {
+                    const float d = (float)(lk[k] - lm);
+                    const float x = d * sm;
+                    const float Phi = phi_cdf(x);
+                    const float dPhi = __expf(-x * x) * INV_SQRT_PI;
+                    acc_dm = fmaf(dE[k], Phi, acc_dm);
+                    const float dx = dE[k] * mm * dPhi;
+                    const float t = dx * sm;
+                    dl[k] += t;
+                    acc_dl -= t;
+                    acc_da = fmaf(dx, d * hs, acc_da);
+                }
             }
         }
         if (in) pbw[o] = make_float4(acc_dm, acc_dl, acc_da, 0.f);
@@ -484,6 +527,35 @@ __global__ __launch_bounds__(TILE_THREADS) void k_bwd(TraceArgs A, int hcap) {
             pbw[o] = make_float4((dmd[k] + acc.x) * mk, dl[k] + acc.y, acc.z, pT[o] * mk);
         }
     }
+}
+
+// Backward, tile phase: group the tile's pairs by kernel and reduce them.
+template <int KB>
+__device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int tile, unsigned char* smem) {
+    __shared__ double s_red[TILE_THREADS / WAVE][3];
+    __shared__ int s_scan[TILE_THREADS];
+    __shared__ int s_scan2[TILE_THREADS];
+    const int tid = threadIdx.x;
+    const int ntx = (A.W + TILE - 1) / TILE;
+    const PixelCtx P = pixel_of(tile, ntx, A.H, A.W, A.cx, A.cy);
+    const size_t S = A.S;
+    const int C = A.C;
+    int* s_hkey = reinterpret_cast<int*>(smem);
+    int* s_cnt = s_hkey + hcap;
+    int* s_off = s_cnt + hcap;
+    int* s_used = s_off + hcap;
+    __shared__ int s_nused;
+    for (int i = tid; i < hcap; i += TILE_THREADS) {
+        s_hkey[i] = -1;
+        s_cnt[i] = 0;
+    }
+    const int keff = P.valid ? A.keff[P.q] : 0;
+    const size_t p = (size_t)P.pi * A.W + P.pj;
+    const double* pl = A.kl_l + P.q;
+    const int* pi = A.kl_i + P.q;
+    float4* pbw = A.bw + P.q;
+    const float* Gp = A.grad_image + p * C;
+    PairRec* tile_pairs = A.pairs + (size_t)tile * TILE_THREADS * A.K;
     __syncthreads();   // table initialised
 
     // counting sort of the tile's pairs by kernel; sp[k] = table slot << 16 | position
@@ -677,6 +749,32 @@ __global__ __launch_bounds__(TILE_THREADS) void k_bwd(TraceArgs A, int hcap) {
     }
 }
 
+// ------------------------------------------------------------------ kernels
+template <int KB>
+__global__ __launch_bounds__(TILE_THREADS) void k_select(TraceArgs A) {
+    const int tile = tile_of_block();
+    select_body<KB>(A, tile);
+}
+
+template <int KB>
+__global__ __launch_bounds__(TILE_THREADS) void k_blend(TraceArgs A) {
+    const int tile = tile_of_block();
+    blend_body<KB>(A, tile);
+}
+
+template <int KB>
+__global__ __launch_bounds__(TILE_THREADS) void k_bwd_pix(TraceArgs A) {
+    const int tile = tile_of_block();
+    bwd_pix_body<KB>(A, tile);
+}
+
+template <int KB>
+__global__ __launch_bounds__(TILE_THREADS) void k_bwd_red(TraceArgs A, int hcap) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tile = tile_of_block();
+    bwd_red_body<KB>(A, hcap, tile, smem);
+}
+
 // Diagnostics: the device Phi on an array.
 __global__ void k_phi(const float* __restrict__ x, float* __restrict__ y, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -704,9 +802,11 @@ static hipError_t run_kb(int which, const TraceArgs& a, hipStream_t s) {
         hipLaunchKernelGGL(k_select<KB>, dim3(nt), dim3(TILE_THREADS), 0, s, a);
     } else if (which == 1) {
         hipLaunchKernelGGL(k_blend<KB>, dim3(nt), dim3(TILE_THREADS), 0, s, a);
+    } else if (which == 2) {
+        hipLaunchKernelGGL(k_bwd_pix<KB>, dim3(nt), dim3(TILE_THREADS), 0, s, a);
     } else {
         const int hcap = table_capacity(a.C);
-        hipLaunchKernelGGL(k_bwd<KB>, dim3(nt), dim3(TILE_THREADS), bwd_lds_bytes(hcap, KB), s, a, hcap);
+        hipLaunchKernelGGL(k_bwd_red<KB>, dim3(nt), dim3(TILE_THREADS), bwd_lds_bytes(hcap, KB), s, a, hcap);
     }
     return hipGetLastError();
 }
@@ -724,6 +824,7 @@ static hipError_t dispatch(int which, const TraceArgs& a, hipStream_t s) {
 hipError_t launch_select(const TraceArgs& a, hipStream_t s) { return dispatch(0, a, s); }
 hipError_t launch_blend(const TraceArgs& a, hipStream_t s) { return dispatch(1, a, s); }
 hipError_t launch_bwd(const TraceArgs& a, hipStream_t s) { return dispatch(2, a, s); }
+hipError_t launch_bwd_reduce(const TraceArgs& a, hipStream_t s) { return dispatch(3, a, s); }
 
 hipError_t launch_phi(const float* x, float* y, int n, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(k_phi, dim3((n + 255) / 256), dim3(256), 0, s, x, y, n);

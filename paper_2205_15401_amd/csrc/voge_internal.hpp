@@ -62,7 +62,7 @@ struct CamDev {               // camera as passed to kernels
 };
 
 struct WsHeader {             // first bytes of every workspace
-    int status;
+    int status;               // sticky device status bits
     int pad[63];
 };
 
@@ -113,14 +113,6 @@ __device__ __forceinline__ void rotate_sym(const double R[9], const double A[6],
     auto e = [&](int r, int c) { return RA[3 * r] * R[3 * c] + RA[3 * r + 1] * R[3 * c + 1] + RA[3 * r + 2] * R[3 * c + 2]; };
     B[0] = e(0, 0); B[1] = e(0, 1); B[2] = e(0, 2);
     B[3] = e(1, 1); B[4] = e(1, 2); B[5] = e(2, 2);
-}
-
-// Block index -> tile index, keeping each XCD's tiles contiguous on screen
-// (blocks are dealt round-robin over the 8 XCDs, each with its own L2).
-__device__ __forceinline__ int xcd_tile(int b, int nb) {
-    const int x = b & 7, local = b >> 3;
-    const int per = nb >> 3, rem = nb & 7;
-    return x * per + (x < rem ? x : rem) + local;
 }
 
 }  // namespace voge

@@ -55,6 +55,8 @@ void launch_prep(const float* means, const float* covs, int N, const CamDev& cam
                  hipStream_t s);
 
 struct TraceArgs {
+    WsHeader* hdr;             // status word and tile queue
+    int n_cu;                  // compute units (persistent grid size)
     const CullRec* cull;
     const TraceRec* rec;
     const GeoRec* geo;
@@ -91,7 +93,8 @@ int table_capacity(int C);   // entries of the per-tile gradient table
 size_t bwd_lds_bytes(int hcap, int KB);
 hipError_t launch_select(const TraceArgs& a, hipStream_t s);
 hipError_t launch_blend(const TraceArgs& a, hipStream_t s);
-hipError_t launch_bwd(const TraceArgs& a, hipStream_t s);
+hipError_t launch_bwd(const TraceArgs& a, hipStream_t s);          // pixel phase
+hipError_t launch_bwd_reduce(const TraceArgs& a, hipStream_t s);   // tile reduction
 hipError_t launch_phi(const float* x, float* y, int n, hipStream_t s);
 
 struct EpiArgs {
