@@ -183,12 +183,15 @@ def main():
     roofline = None
     if os.path.exists(opc_path):
         opc = json.load(open(opc_path))
-        flops = {"select": opc["flop_select"], "blend": opc["flop_blend"], "bwd": opc["flop_bwd"]}
-        kname = {"select": f"k_select<{R_kb(K)}>", "blend": f"k_blend<{R_kb(K)}>", "bwd": f"k_bwd<{R_kb(K)}>"}
+        flops = {"select": opc["flop_select"], "blend": opc["flop_blend"], "bwd": opc["flop_bwd_pixel"],
+                 "bwd_reduce": opc["flop_bwd_chain"]}
+        kb = R_kb(K)
+        kname = {"select": f"k_select<{kb}>", "blend": f"k_blend<{kb}>", "bwd": f"k_bwd_pix<{kb}>",
+                 "bwd_reduce": f"k_bwd_red<{kb}>"}
         avg = {k: phases[k][0] / phases[k][1] for k in flops if k in phases and phases[k][1] > 0}
         dom = max(avg, key=avg.get)
         achieved = flops[dom] / (avg[dom] / 1e3) / 1e12
-        traffic = load_traffic(dom, job.name, source_digest())
+        traffic = load_traffic(kname[dom].split("<")[0], job.name, source_digest())
         roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(achieved / PEAK_FP32_TFLOPS, 6), "traffic": traffic,
                     "kernel": kname[dom], "avg_us": round(avg[dom] * 1e3, 2),

@@ -49,6 +49,8 @@ def count(job) -> dict:
     out["flop_select"] = O.FLOP_TRACE * out["sum_n_pass"]
     out["flop_blend"] = O.FLOP_PAIR * out["sum_k_eff_sq"] + O.flop_kept(C) * out["sum_k_eff"]
     out["flop_bwd"] = O.backward_flops(ke, C)
+    out["flop_bwd_pixel"] = O.FLOP_BPAIR * out["sum_k_eff_sq"] + O.flop_bkept_pixel(C) * out["sum_k_eff"]
+    out["flop_bwd_chain"] = O.flop_bkept_chain(C) * out["sum_k_eff"]
     out["flop_forward"] = O.forward_flops(r.n_pass, ke, C)
     out["flop_per_ray_fwd_bwd"] = (out["flop_forward"] + out["flop_bwd"]) / out["rays"]
     out["oracle_seconds"] = round(time.time() - t0, 2)

@@ -28,7 +28,8 @@ the arithmetic of the formulas as evaluated here, per unit of work:
   FLOP_BKEPT = 110 + 4C per kept kernel: G.c_k (2C), W_k G (C), accumulate
       attribute gradient (C), dm, dE (3), dq (1), S V and S D (30), dL/dM (10),
       symmetric dL/dS (40), dL/dD (20), accumulate M and S gradients (9 minus 3
-      counted above).
+      counted above).  Of these, 2C + 4 (G.c_k, dm, dE, dq) belong with the
+      per-pixel pair work and 106 + 2C with the per-kernel chain.
 """
 
 from __future__ import annotations
@@ -61,6 +62,14 @@ def flop_kept(C: int) -> int:
 
 def flop_bkept(C: int) -> int:
     return 110 + 4 * C
+
+
+def flop_bkept_pixel(C: int) -> int:
+    return 2 * C + 4
+
+
+def flop_bkept_chain(C: int) -> int:
+    return 106 + 2 * C
 
 
 def build(force: bool = False) -> str:

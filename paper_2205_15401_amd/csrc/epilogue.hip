@@ -111,30 +111,22 @@ __global__ __launch_bounds__(EPI_THREADS) void k_epilogue(EpiArgs A) {
     }
 }
 
-// One block: a fixed-order tree reduction of the per-block and per-tile
-// partials into the 15 camera gradients.
-constexpr int FIN_THREADS = 256;
+// One wave per camera value: a fixed-order reduction of the per-block and
+// per-tile partials (lane-strided sums, then a shuffle tree).
+constexpr int FIN_THREADS = 16 * WAVE;
 
 __global__ __launch_bounds__(FIN_THREADS) void k_cam_finalize(EpiArgs A, int nblk) {
-    __shared__ double s_part[FIN_THREADS];
-    const int tid = threadIdx.x;
-    for (int e = 0; e < 15; ++e) {
-        double s = 0.0;
-        if (e < 12) {
-            for (int b = tid; b < nblk; b += FIN_THREADS) s += A.camP[(size_t)b * 12 + e];
-        } else {
-            const int comp = (e == 12) ? 2 : (e == 13 ? 1 : 0);   // F <- z, O_x <- y, O_y <- x
-            for (int t = tid; t < A.n_tiles; t += FIN_THREADS) s += A.tileD[(size_t)t * 3 + comp];
-        }
-        s_part[tid] = s;
-        __syncthreads();
-        for (int off = FIN_THREADS / 2; off > 0; off >>= 1) {
-            if (tid < off) s_part[tid] += s_part[tid + off];
-            __syncthreads();
-        }
-        if (tid == 0) A.grad_camera[e] = (float)(e == 13 || e == 14 ? -s_part[0] : s_part[0]);
-        __syncthreads();
+    const int e = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    if (e >= 15) return;
+    double s = 0.0;
+    if (e < 12) {
+        for (int b = lane; b < nblk; b += WAVE) s += A.camP[(size_t)b * 12 + e];
+    } else {
+        const int comp = (e == 12) ? 2 : (e == 13 ? 1 : 0);   // F <- z, O_x <- y, O_y <- x
+        for (int t = lane; t < A.n_tiles; t += WAVE) s += A.tileD[(size_t)t * 3 + comp];
     }
+    s = wave_sum_d(s);
+    if (lane == 0) A.grad_camera[e] = (float)(e == 13 || e == 14 ? -s : s);
 }
 
 hipError_t launch_epilogue(const EpiArgs& a, hipStream_t s) {

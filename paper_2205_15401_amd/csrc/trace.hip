@@ -160,8 +160,6 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
     for (int s = 0; s < KB; ++s) key[s] = ~0ull;
     uint64_t kth = ~0ull;                       // the K-th smallest key so far
     bool done = !P.valid;
-    // this wave's 8x8 block, for skipping candidates that cannot reach it
-    const int wi0 = ti0 + (wave >> 1) * 8, wj0 = tj0 + (wave & 1) * 8;
     CullRec nxt;
     if (tid < A.N) nxt = A.cull[tid];
     for (int base = 0; base < A.N; base += TILE_THREADS) {
@@ -192,8 +190,6 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
         for (int ci = 0; ci < total; ++ci) {
             if (__all(done)) break;
             const StagedRec& R = s_rec[ci];
-            // whole-wave skip when the candidate's screen box misses this 8x8 block
-            if (R.i0 > wi0 + 7 || R.i1 < wi0 || R.j0 > wj0 + 7 || R.j1 < wj0) continue;
             if (!done && kth != ~0ull && (double)R.tlo > key_upper_l(kth)) done = true;
             if (!done) {
                 double l, q2, a;
@@ -298,12 +294,33 @@ __device__ __forceinline__ void blend_body(const TraceArgs& A, int tile) {
         }
     }
     if (A.image) {
-        for (int c = 0; c < A.C; ++c) {
-            float acc = 0.f;
+        if ((A.C & 3) == 0) {
+            // four channels per load and store
+            const int C4 = A.C >> 2;
+            const float4* a4 = reinterpret_cast<const float4*>(A.attrs);
+            float4* o4 = reinterpret_cast<float4*>(A.image) + p * C4;
+            for (int c = 0; c < C4; ++c) {
+                float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-            for (int k = 0; k < KB; ++k)
-                if (k < keff) acc = fmaf(Wt[k], A.attrs[(size_t)ik[k] * A.C + c], acc);
-            A.image[p * A.C + c] = acc;
+                for (int k = 0; k < KB; ++k) {
+                    if (k < keff) {
+                        const float4 v = a4[(size_t)ik[k] * C4 + c];
+                        acc.x = fmaf(Wt[k], v.x, acc.x);
+                        acc.y = fmaf(Wt[k], v.y, acc.y);
+                        acc.z = fmaf(Wt[k], v.z, acc.z);
+                        acc.w = fmaf(Wt[k], v.w, acc.w);
+                    }
+                }
+                o4[c] = acc;
+            }
+        } else {
+            for (int c = 0; c < A.C; ++c) {
+                float acc = 0.f;
+#pragma unroll
+                for (int k = 0; k < KB; ++k)
+                    if (k < keff) acc = fmaf(Wt[k], A.attrs[(size_t)ik[k] * A.C + c], acc);
+                A.image[p * A.C + c] = acc;
+            }
         }
     }
     if (A.wsum) A.wsum[p] = ws;
@@ -558,16 +575,27 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
     PairRec* tile_pairs = A.pairs + (size_t)tile * TILE_THREADS * A.K;
     __syncthreads();   // table initialised
 
-    // counting sort of the tile's pairs by kernel; sp[k] = table slot << 16 | position
-    int sp[KB];
+    // counting sort of the tile's pairs by kernel; sp[k] = table slot << 16 | position.
+    // All first probes are issued back to back; collisions (rare at this load
+    // factor) then probe on.
+    int sp[KB], rk[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) rk[k] = k < keff ? A.kl_r[P.q + (size_t)k * S] : -1;
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
         sp[k] = -1;
-        if (k < keff) {
-            const int sl = hash_slot(s_hkey, hcap - 1, A.kl_r[P.q + (size_t)k * S]);
-            if (sl >= 0) sp[k] = (sl << 16) | atomicAdd(&s_cnt[sl], 1);
+        if (rk[k] >= 0) {
+            const int h = (int)(((uint32_t)rk[k] * 2654435761u) >> 7) & (hcap - 1);
+            const int cur = atomicCAS(&s_hkey[h], -1, rk[k]);
+            sp[k] = (cur == -1 || cur == rk[k]) ? h : -2;
         }
     }
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+        if (sp[k] == -2) sp[k] = hash_slot(s_hkey, hcap - 1, rk[k]);
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+        if (sp[k] >= 0) sp[k] = (sp[k] << 16) | atomicAdd(&s_cnt[sp[k]], 1);
     __syncthreads();
     // exclusive scans: s_cnt -> s_off, and the used entries -> s_used
     {
@@ -665,9 +693,11 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
         GeoRec G;
         s_hk[tid] = -1;
         s_tk[tid] = -1;
+        PairRec nxt = j0 < j1 ? tile_pairs[j0] : PairRec{};
         for (int j = j0; j <= j1; ++j) {
             const bool end = j == j1;
-            const PairRec r = end ? PairRec{} : tile_pairs[j];
+            const PairRec r = nxt;
+            if (j + 1 < j1) nxt = tile_pairs[j + 1];
             if (end || r.rank != cur) {
                 if (cur >= 0) {
                     if (nseg == 0) {                                   // first run: may continue
