@@ -1,16 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark of the VoGE rendering hot path on one MI355X.
 
-One step = forward + backward of one 512x512 render of the 10,000-kernel
-torus (16 channels, K = 20, eta = 0.01) through the C ABI, with every input
-already resident in device memory.  Prints ONE JSON line on stdout:
+Headline: forward + backward of 256 camera poses of one 4,096-kernel torus
+(3 channels, 128x128, K = 20, eta = 0.01), rendered three ways with every
+input already resident in device memory:
 
-  value      Mrays/s of forward + backward (rays = pixels per step / step time)
-  latency    p50 / p99 of the per-step time (each step is one request)
-  roofline   the dominant kernel's algorithmic FLOP rate against the FP32
-             vector peak, its average duration measured live with HIP events
-  cpu_baseline  the FP64 oracle, forward + backward on a fixed random sample of
-             the same image's rays, timed on this host's cores
+  batched   one voge_render_batch call per step for all 256 poses, its
+            launches replayed from a HIP graph (the headline value)
+  eager     the same call without the graph
+  per-call  256 voge_render_forward + voge_render_backward pairs per step
+
+and, as context, the single 512x512 image of the 10,000-kernel torus
+(16 channels) per call.  Prints ONE JSON line on stdout:
+
+  value         Mrays/s of the batched forward + backward
+  latency_ms    p50 / p99 of the batched step (one request = one batch)
+  roofline      the dominant kernel of the batched step: its algorithmic FLOP
+                rate (FLOPs from the oracle's op count) against the FP32
+                vector peak, its average duration measured live with HIP
+                events on the stream it runs on
+  cpu_baseline  the FP64 oracle, forward + backward on a fixed random sample
+                of the same workload's rays, timed on this host's cores
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--cpu-sample RAYS]
 """
@@ -29,7 +39,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector peak (256 CUs, 2.4 GHz)
-PEAK_HBM_GBS = 8000.0
+POSES_NAME = "torus4096_256poses_128px_C3_K20"
 
 
 def log(*a):
@@ -58,38 +68,219 @@ def load_traffic(kernel: str, workload: str, digest: str):
     return float(m_b.group(1))
 
 
-def cpu_baseline(job, n_rays: int, seed: int = 7):
-    """FP64 oracle, forward + backward, on a fixed random sample of the rays."""
-    import numpy as np
-    from oracle import oracle as O
-
-    cam = job.camera
-    H, W, C = cam.height, cam.width, job.scene.channels
-    rng = np.random.default_rng(seed)
-    n = min(int(n_rays), H * W)
-    pix = np.sort(rng.choice(H * W, n, replace=False))
-    G = job.grad_image.reshape(-1, C)[pix]
+def oracle_threads() -> int:
     threads = len(os.sched_getaffinity(0))
     env_t = os.environ.get("OMP_NUM_THREADS")
     if env_t and env_t.isdigit():
         threads = min(threads, int(env_t))
+    return threads
+
+
+def cpu_baseline(jobs, n_rays: int, seed: int = 7):
+    """FP64 oracle, forward + backward, on a fixed random sample of the rays
+    of all jobs (the same number of rays from each)."""
+    import numpy as np
+    from oracle import oracle as O
+
+    rng = np.random.default_rng(seed)
+    per = max(1, int(n_rays) // len(jobs))
+    threads = oracle_threads()
+    samples = []
+    for job in jobs:
+        cam = job.camera
+        pix = np.sort(rng.choice(cam.height * cam.width, min(per, cam.height * cam.width), replace=False))
+        samples.append(pix)
     t0 = time.perf_counter()
-    O.forward(job.scene.means, job.scene.covs, job.scene.attrs, cam.as_vector(), H, W, job.K, job.eta,
-              pixels=pix, threads=threads)
-    O.backward(job.scene.means, job.scene.covs, job.scene.attrs, cam.as_vector(), H, W, job.K, G, job.eta,
-               pixels=pix, threads=threads)
+    n = 0
+    for job, pix in zip(jobs, samples):
+        cam, sc = job.camera, job.scene
+        H, W, C = cam.height, cam.width, sc.channels
+        G = job.grad_image.reshape(-1, C)[pix]
+        O.forward(sc.means, sc.covs, sc.attrs, cam.as_vector(), H, W, job.K, job.eta, pixels=pix, threads=threads)
+        O.backward(sc.means, sc.covs, sc.attrs, cam.as_vector(), H, W, job.K, G, job.eta, pixels=pix,
+                   threads=threads)
+        n += pix.size
     dt = time.perf_counter() - t0
+    cam = jobs[0].camera
     return {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} random rays of the {H}x{W} image (seed {seed}), forward + backward, "
-                      f"brute force over all {job.scene.n} kernels, FP64, {dt:.2f} s"}
+            "sample": f"{per} random rays from each of {len(jobs)} {cam.height}x{cam.width} renders ({n} rays, "
+                      f"seed {seed}), forward + backward, brute force over all {jobs[0].scene.n} kernels, FP64, "
+                      f"{dt:.2f} s"}
+
+
+class Timer:
+    """HIP events recorded on one stream around each step."""
+
+    def __init__(self, torch, stream):
+        self.torch, self.stream = torch, stream
+
+    def run(self, step, steps: int, warmup: int):
+        torch = self.torch
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        torch.cuda.synchronize()
+        ev[0].record(self.stream)
+        for i in range(steps):
+            step()
+            ev[i + 1].record(self.stream)
+        torch.cuda.synchronize()
+        per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+        return ev[0].elapsed_time(ev[-1]), per
+
+
+def kb_of(K: int) -> int:
+    for kb in (8, 16, 20, 32, 64):
+        if K <= kb:
+            return kb
+    return 64
+
+
+def roofline_of(phases, opc, K, workload):
+    flops = {"select": opc["flop_select"], "blend": opc["flop_blend"], "bwd": opc["flop_bwd_pixel"],
+             "bwd_reduce": opc["flop_bwd_chain"]}
+    kb = kb_of(K)
+    kname = {"select": f"k_select<{kb}>", "blend": f"k_blend<{kb}>", "bwd": f"k_bwd_pix<{kb}>",
+             "bwd_reduce": f"k_bwd_red<{kb}>"}
+    avg = {k: phases[k][0] / phases[k][1] for k in flops if k in phases and phases[k][1] > 0}
+    dom = max(avg, key=avg.get)
+    achieved = flops[dom] / (avg[dom] / 1e3) / 1e12
+    traffic = load_traffic(kname[dom].split("<")[0], workload, source_digest())
+    return {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 6), "traffic": traffic, "kernel": kname[dom],
+            "avg_us": round(avg[dom] * 1e3, 2), "algorithmic_flop_per_launch": flops[dom]}
+
+
+def pct(x, q):
+    import numpy as np
+    return round(float(np.percentile(np.asarray(x), q)), 5)
+
+
+def bench_poses(args, torch, dev):
+    import numpy as np
+    from paper_2205_15401_amd import _native as nat
+    from paper_2205_15401_amd import render as R
+    from paper_2205_15401_amd import scenes as S
+
+    jobs = S.config_poses()
+    sc = jobs[0].scene
+    N, C, H, W, K, eta = sc.n, sc.channels, jobs[0].camera.height, jobs[0].camera.width, jobs[0].K, jobs[0].eta
+    n = len(jobs)
+    log(f"[bench] workload {POSES_NAME}: {n} poses, N={N} C={C} {H}x{W} K={K}")
+    f32 = dict(dtype=torch.float32, device=dev)
+    m, c, a = (torch.from_numpy(x).to(dev) for x in (sc.means, sc.covs, sc.attrs))
+    cams = [R.camera_struct(j.camera) for j in jobs]
+    batch = R.Batch([(m, c, a)], [(0, cs, K, eta) for cs in cams], dev, backward=True, with_camera=True)
+    for i, j in enumerate(jobs):
+        batch.set_grad_image(i, torch.from_numpy(j.grad_image))
+    side = torch.cuda.Stream()
+    s = side.cuda_stream
+    timer = Timer(torch, side)
+    rays = n * H * W
+
+    # batched, graph replay (headline) and eager
+    total_g, per_g = timer.run(lambda: batch.run(forward=True, backward=True, graph=True, stream=s), args.steps,
+                               args.warmup)
+    total_e, per_e = timer.run(lambda: batch.run(forward=True, backward=True, stream=s), args.steps, args.warmup)
+    st = batch.status()
+    if any(st):
+        log(f"[bench] device status {st}")
+    ms_g, ms_e = total_g / args.steps, total_e / args.steps
+    log(f"[bench] batched graph {ms_g:.3f} ms/step ({rays / ms_g / 1e3:.1f} Mrays/s), eager {ms_e:.3f} ms/step "
+        f"({rays / ms_e / 1e3:.1f} Mrays/s)")
+
+    # per call: one render (forward + backward) at a time through one workspace
+    ctx = R.context(dev)
+    par = R.params_struct(K, eta)
+    wsb = nat.voge_workspace_size(N, C, cams[0], par, True)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    p = lambda t: t.data_ptr()  # noqa: E731
+    per_render = []
+
+    def step_per_call(record=None):
+        for i in range(n):
+            nat.voge_render_forward(ctx, p(m), p(c), p(a), N, C, cams[i], par, p(batch.images[i]), None, None,
+                                    p(ws), wsb, s)
+            nat.voge_render_backward(ctx, p(m), p(c), p(a), N, C, cams[i], par, p(batch.grad_images[i]),
+                                     p(batch.grad_means[i]), p(batch.grad_covs[i]), p(batch.grad_attrs[i]),
+                                     p(batch.grad_cameras[i]), nat.VOGE_REUSE_PREP, p(ws), wsb, s)
+            if record is not None:
+                record[i + 1].record(side)
+
+    total_p, _ = timer.run(step_per_call, args.per_call_steps, 1)
+    ms_p = total_p / args.per_call_steps
+    # per-render latency of the per-call mode
+    for _ in range(2):
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+        torch.cuda.synchronize()
+        evs[0].record(side)
+        step_per_call(evs)
+        torch.cuda.synchronize()
+        per_render += [evs[i].elapsed_time(evs[i + 1]) for i in range(n)]
+    log(f"[bench] per-call {ms_p:.3f} ms/step ({rays / ms_p / 1e3:.1f} Mrays/s)")
+
+    # kernel phases of the batched step (eager, so each launch is timed on its stream)
+    nat.voge_profile_enable(ctx, True)
+    nat.voge_profile_read(ctx, reset=True)
+    for _ in range(args.profile_steps):
+        batch.run(forward=True, backward=True, stream=s)
+    torch.cuda.synchronize()
+    phases = nat.voge_profile_read(ctx, reset=True)
+    nat.voge_profile_enable(ctx, False)
+    for name, (tot, cnt) in sorted(phases.items()):
+        log(f"[bench]   phase {name:10s} {tot / max(cnt, 1) * 1e3:10.2f} us avg over {cnt}")
+    del ws
+    return {
+        "value": rays / ms_g / 1e3, "ms": ms_g, "per": per_g, "eager_value": rays / ms_e / 1e3, "eager_ms": ms_e,
+        "eager_per": per_e, "per_call_value": rays / ms_p / 1e3, "per_call_ms": ms_p, "per_render": per_render,
+        "phases": phases, "rays": rays, "N": N, "C": C, "H": H, "W": W, "K": K, "eta": eta, "n": n, "jobs": jobs,
+    }
+
+
+def bench_torus(args, torch, dev):
+    from paper_2205_15401_amd import _native as nat
+    from paper_2205_15401_amd import render as R
+    from paper_2205_15401_amd import scenes as S
+
+    job = S.config_torus()
+    sc, cam = job.scene, job.camera
+    N, C, H, W, K = sc.n, sc.channels, cam.height, cam.width, job.K
+    means, covs, attrs, grad = (torch.from_numpy(x).to(dev) for x in (sc.means, sc.covs, sc.attrs, job.grad_image))
+    cs = R.camera_struct(cam)
+    par = R.params_struct(K, job.eta)
+    wsb = nat.voge_workspace_size(N, C, cs, par, True)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    f32 = dict(dtype=torch.float32, device=dev)
+    image = torch.empty((H, W, C), **f32)
+    gm, gc, ga, gk = (torch.empty(sh, **f32) for sh in ((N, 3), (N, 6), (N, C), (15,)))
+    ctx = R.context(dev)
+    stream = torch.cuda.current_stream(dev)
+    s = stream.cuda_stream
+    p = lambda t: t.data_ptr()  # noqa: E731
+
+    def step():
+        nat.voge_render_forward(ctx, p(means), p(covs), p(attrs), N, C, cs, par, p(image), None, None, p(ws), wsb, s)
+        nat.voge_render_backward(ctx, p(means), p(covs), p(attrs), N, C, cs, par, p(grad), p(gm), p(gc), p(ga),
+                                 p(gk), nat.VOGE_REUSE_PREP, p(ws), wsb, s)
+
+    total, per = Timer(torch, stream).run(step, args.torus_steps, args.warmup)
+    ms = total / args.torus_steps
+    log(f"[bench] single image {job.name}: {ms:.4f} ms/step, {H * W / ms / 1e3:.1f} Mrays/s")
+    return {"workload": job.name, "value": round(H * W / ms / 1e3, 3), "unit": "Mrays/s", "ms_per_step": round(ms, 5),
+            "steps": args.torus_steps, "mode": "per-call forward+backward",
+            "latency_ms": {"p50": pct(per, 50), "p99": pct(per, 99)}}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--cpu-sample", type=int, default=131072, help="rays for the oracle baseline (0 = skip)")
+    ap.add_argument("--steps", type=int, default=20, help="timed batched steps (256 renders each)")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--per-call-steps", type=int, default=3)
+    ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--torus-steps", type=int, default=50, help="timed steps of the single 512x512 image")
+    ap.add_argument("--cpu-sample", type=int, default=262144, help="rays for the oracle baseline (0 = skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="after timing, copy this many bytes device-to-device once (a plain copy kernel of "
                          "known size that scales the HBM byte counters of a profile)")
@@ -100,66 +291,14 @@ def main():
             "multi-GPU runs are not part of it (see DESIGN.md for how the path would shard).")
         sys.exit(2)
 
-    import numpy as np
     import torch
-
-    from paper_2205_15401_amd import _native as nat
-    from paper_2205_15401_amd import render as R
-    from paper_2205_15401_amd import scenes as S
 
     if not torch.cuda.is_available():
         log("no GPU visible")
         sys.exit(1)
     dev = torch.device("cuda:0")
-    job = S.config_torus()
-    sc, cam = job.scene, job.camera
-    N, C, H, W, K = sc.n, sc.channels, cam.height, cam.width, job.K
-    log(f"[bench] workload {job.name}: N={N} C={C} {H}x{W} K={K}")
-
-    means = torch.from_numpy(sc.means).to(dev)
-    covs = torch.from_numpy(sc.covs).to(dev)
-    attrs = torch.from_numpy(sc.attrs).to(dev)
-    grad = torch.from_numpy(job.grad_image).to(dev)
-    cs = R.camera_struct(cam)
-    par = R.params_struct(K, job.eta)
-    ws_bytes = nat.voge_workspace_size(N, C, cs, par, True)
-    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
-    image = torch.empty((H, W, C), dtype=torch.float32, device=dev)
-    gm = torch.empty((N, 3), dtype=torch.float32, device=dev)
-    gc = torch.empty((N, 6), dtype=torch.float32, device=dev)
-    ga = torch.empty((N, C), dtype=torch.float32, device=dev)
-    gk = torch.empty(15, dtype=torch.float32, device=dev)
-    ctx = R.context(dev)
-    stream = torch.cuda.current_stream(dev).cuda_stream
-    p = lambda t: t.data_ptr()  # noqa: E731
-
-    def step():
-        nat.voge_render_forward(ctx, p(means), p(covs), p(attrs), N, C, cs, par, p(image), None, None, p(ws),
-                                ws_bytes, stream)
-        nat.voge_render_backward(ctx, p(means), p(covs), p(attrs), N, C, cs, par, p(grad), p(gm), p(gc), p(ga),
-                                 p(gk), nat.VOGE_REUSE_PREP, p(ws), ws_bytes, stream)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    st = nat.voge_status(p(ws), stream)
-    if st != 0:
-        log(f"[bench] device status {st}")
-
-    nat.voge_profile_enable(ctx, True)
-    nat.voge_profile_read(ctx, reset=True)
-    events = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    events[0].record()
-    for i in range(args.steps):
-        step()
-        events[i + 1].record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    phases = nat.voge_profile_read(ctx, reset=True)
-    nat.voge_profile_enable(ctx, False)
-    per_step = np.array([events[i].elapsed_time(events[i + 1]) for i in range(args.steps)])
+    r = bench_poses(args, torch, dev)
+    single = bench_torus(args, torch, dev) if args.torus_steps > 0 else None
     if args.calibrate_copy > 0:
         n4 = args.calibrate_copy // 4
         src = torch.ones(n4, dtype=torch.float32, device=dev)
@@ -169,71 +308,49 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {n4 * 4} bytes done")
         del src, dst
-    total_ms = events[0].elapsed_time(events[-1])
-    ms_per_step = total_ms / args.steps
-    rays = H * W
-    value = rays / (ms_per_step / 1e3) / 1e6
-    log(f"[bench] {args.steps} steps in {total_ms:.2f} ms (wall {wall * 1e3:.1f} ms): {ms_per_step:.4f} ms/step, "
-        f"{value:.1f} Mrays/s")
-    for name, (tot, cnt) in sorted(phases.items()):
-        log(f"[bench]   phase {name:9s} {tot / max(cnt, 1) * 1e3:9.2f} us avg over {cnt}")
 
-    # roofline of the dominant kernel (FLOP counts from the oracle's op counter)
-    opc_path = os.path.join(ROOT, "oracle", f"opcount_{job.name}.json")
+    opc_path = os.path.join(ROOT, "oracle", f"opcount_{POSES_NAME}.json")
     roofline = None
     if os.path.exists(opc_path):
-        opc = json.load(open(opc_path))
-        flops = {"select": opc["flop_select"], "blend": opc["flop_blend"], "bwd": opc["flop_bwd_pixel"],
-                 "bwd_reduce": opc["flop_bwd_chain"]}
-        kb = R_kb(K)
-        kname = {"select": f"k_select<{kb}>", "blend": f"k_blend<{kb}>", "bwd": f"k_bwd_pix<{kb}>",
-                 "bwd_reduce": f"k_bwd_red<{kb}>"}
-        avg = {k: phases[k][0] / phases[k][1] for k in flops if k in phases and phases[k][1] > 0}
-        dom = max(avg, key=avg.get)
-        achieved = flops[dom] / (avg[dom] / 1e3) / 1e12
-        traffic = load_traffic(kname[dom].split("<")[0], job.name, source_digest())
-        roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / PEAK_FP32_TFLOPS, 6), "traffic": traffic,
-                    "kernel": kname[dom], "avg_us": round(avg[dom] * 1e3, 2),
-                    "algorithmic_flop_per_launch": flops[dom]}
+        roofline = roofline_of(r["phases"], json.load(open(opc_path)), r["K"], POSES_NAME)
     else:
         log(f"[bench] {opc_path} missing: roofline omitted")
 
     cpu = None
     if args.cpu_sample > 0:
         log(f"[bench] cpu baseline: oracle on {args.cpu_sample} rays ...")
-        cpu = cpu_baseline(job, args.cpu_sample)
+        cpu = cpu_baseline(r["jobs"], args.cpu_sample)
         log(f"[bench] cpu baseline {cpu['value']:.4f} Mrays/s on {cpu['cores']} threads")
 
     out = {
         "metric": "Mrays/s fwd+bwd at K=20, batched vs per-call; p50/p99 render latency",
-        "value": round(value, 3),
+        "value": round(r["value"], 3),
         "unit": "Mrays/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5),
+        "ms_per_step": round(r["ms"], 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": job.name, "kernels": N, "channels": C, "height": H, "width": W, "K": K,
-                   "eta": job.eta, "rays_per_step": rays, "mode": "per-call forward+backward"},
-        "latency_ms": {"p50": round(float(np.percentile(per_step, 50)), 5),
-                       "p99": round(float(np.percentile(per_step, 99)), 5)},
-        "phases_us": {k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in phases.items()},
+        "config": {"workload": POSES_NAME, "renders_per_step": r["n"], "kernels": r["N"], "channels": r["C"],
+                   "height": r["H"], "width": r["W"], "K": r["K"], "eta": r["eta"], "rays_per_step": r["rays"],
+                   "mode": "batched forward+backward: one voge_render_batch call per step, HIP graph replay"},
+        "latency_ms": {"p50": pct(r["per"], 50), "p99": pct(r["per"], 99)},
+        "batched_eager": {"value": round(r["eager_value"], 3), "ms_per_step": round(r["eager_ms"], 5),
+                          "latency_ms": {"p50": pct(r["eager_per"], 50), "p99": pct(r["eager_per"], 99)}},
+        "per_call": {"value": round(r["per_call_value"], 3), "ms_per_step": round(r["per_call_ms"], 5),
+                     "steps": args.per_call_steps,
+                     "render_latency_ms": {"p50": pct(r["per_render"], 50), "p99": pct(r["per_render"], 99)}},
+        "batched_vs_per_call": round(r["value"] / r["per_call_value"], 3),
+        "single_image": single,
+        "phases_us": {k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in r["phases"].items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-
-
-def R_kb(K: int) -> int:
-    for kb in (8, 16, 20, 32, 64):
-        if K <= kb:
-            return kb
-    return 64
 
 
 if __name__ == "__main__":

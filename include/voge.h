@@ -63,7 +63,17 @@ extern "C" {
 #define VOGE_STATUS_NOTSPD 1     /* some covariance was not SPD (skipped)      */
 #define VOGE_STATUS_NONFINITE 2  /* some centre or covariance was not finite   */
 
-#define VOGE_REUSE_PREP 1     /* backward flag: workspace holds this camera's prep */
+/* Call flags.  voge_render_backward takes VOGE_REUSE_PREP alone;
+ * voge_render_batch takes VOGE_FORWARD and/or VOGE_BACKWARD, optionally with
+ * VOGE_REUSE_PREP (backward only) and VOGE_GRAPH. */
+#define VOGE_REUSE_PREP 1     /* the workspace holds the preparation and kept
+                                 lists of a forward of the same items          */
+#define VOGE_FORWARD 2        /* batch: render the images                      */
+#define VOGE_BACKWARD 4       /* batch: gradients of the images                */
+#define VOGE_GRAPH 8          /* batch: replay the call's launches from a HIP
+                                 graph cached per shape (captured on first use) */
+
+#define VOGE_MAX_BATCH 4096   /* items per voge_render_batch call              */
 
 typedef struct voge_camera {
     float R[9];               /* world -> camera rotation, row-major           */
@@ -81,6 +91,28 @@ typedef struct voge_params {
 } voge_params_t;
 
 typedef struct voge_ctx voge_ctx_t;
+
+/* One render of a batch: a kernel set seen by a camera.  Pointers as in
+ * voge_render_forward / voge_render_backward (device memory); outputs that a
+ * call does not produce may be NULL.  Items may share kernel arrays (many
+ * cameras of one scene) but not output buffers. */
+typedef struct voge_item {
+    const float* means;       /* [N*3]                                          */
+    const float* covs;        /* [N*6] packed xx, xy, xz, yy, yz, zz            */
+    const float* attrs;       /* [N*C]                                          */
+    int32_t N;
+    int32_t C;
+    voge_camera_t camera;
+    voge_params_t params;
+    float* image;             /* [H*W*C] out, required with VOGE_FORWARD        */
+    float* wsum;              /* [H*W] out, optional                            */
+    int32_t* kept;            /* [H*W*K] out, optional                          */
+    const float* grad_image;  /* [H*W*C] in, required with VOGE_BACKWARD        */
+    float* grad_means;        /* [N*3] out, required with VOGE_BACKWARD         */
+    float* grad_covs;         /* [N*6] out, required with VOGE_BACKWARD         */
+    float* grad_attrs;        /* [N*C] out, required with VOGE_BACKWARD         */
+    float* grad_camera;       /* [15] out, optional                             */
+} voge_item_t;
 
 /* Create a library context bound to HIP device `device`.  Host memory only;
  * the calls below run on that device (the caller's current device is
@@ -122,6 +154,38 @@ int voge_render_backward(voge_ctx_t* ctx, const float* means, const float* covs,
                          const voge_camera_t* cam, const voge_params_t* params, const float* grad_image,
                          float* grad_means, float* grad_covs, float* grad_attrs, float* grad_camera, int flags,
                          void* workspace, size_t workspace_bytes, void* stream);
+
+/* Bytes of workspace for a batch of n_items (1 <= n_items <= VOGE_MAX_BATCH);
+ * with_backward = 1 sizes it for VOGE_BACKWARD too.  Only the shapes (N, C,
+ * camera size, K) of the items matter. */
+int voge_batch_workspace_size(const voge_item_t* items, int n_items, int with_backward, size_t* bytes);
+
+/* Render a batch of items in one sequence of launches: every item's kernels
+ * are prepared and depth-sorted together, then each stage covers the screen
+ * tiles of all items (items with K-buffers of one compiled depth share a
+ * launch).  Per item, the results are those of voge_render_forward and
+ * voge_render_backward on that item alone, up to the order of floating-point
+ * accumulation and the order of kernels at exactly equal depth.
+ *   items      host array [n_items], read before return
+ *   flags      VOGE_FORWARD, VOGE_BACKWARD or both; VOGE_REUSE_PREP with
+ *              VOGE_BACKWARD alone when `workspace` holds a forward of the
+ *              same items (shapes, kernels, cameras, params) -- then the kept
+ *              sets of that forward are used; VOGE_GRAPH replays the launches
+ *              from a HIP graph that the context caches per (workspace,
+ *              flags, item shapes); it needs a stream other than the null
+ *              stream, and the graph is captured on that stream at first use.
+ *   workspace  >= voge_batch_workspace_size(items, n_items, VOGE_BACKWARD set)
+ * The item table is staged through the context: two calls on one context may
+ * run from different threads, but calls in flight on one workspace race.
+ * Errors: VOGE_EINVAL (an item's shapes or pointers, flags), VOGE_ENOSPACE,
+ * VOGE_EHIP. */
+int voge_render_batch(voge_ctx_t* ctx, const voge_item_t* items, int n_items, int flags, void* workspace,
+                      size_t workspace_bytes, void* stream);
+
+/* Per-item device status words (VOGE_STATUS_* bits) of the last batch (or
+ * single render) on `workspace`, in the caller's item order.  Synchronises
+ * `stream`. */
+int voge_batch_status(const void* workspace, int n_items, int32_t* device_status, void* stream);
 
 /* Read the workspace's device status word (VOGE_STATUS_* bits of the last
  * forward, or backward without VOGE_REUSE_PREP).  Synchronises `stream`. */

@@ -7,6 +7,7 @@ sets -- the units the per-step FLOP constants of ``oracle.py`` multiply.
 The result is written next to this file as ``opcount_<workload>.json``.
 
     python -m oracle.opcount            # the 512x512 torus workload
+    python -m oracle.opcount poses      # 256 poses of the 4,096-kernel torus at 128x128
 """
 
 from __future__ import annotations
@@ -25,17 +26,26 @@ from oracle import oracle as O  # noqa: E402
 from paper_2205_15401_amd import scenes as S  # noqa: E402
 
 
-def count(job) -> dict:
-    cam = job.camera
+def count(jobs, name: str) -> dict:
+    """Counts over every ray of every job (all jobs share C)."""
+    if not isinstance(jobs, (list, tuple)):
+        jobs = [jobs]
     t0 = time.time()
-    r = O.forward(job.scene.means, job.scene.covs, job.scene.attrs, cam.as_vector(), cam.height, cam.width,
-                  job.K, job.eta)
-    ke = r.k_eff.astype(np.int64)
-    C = job.scene.channels
+    kes, n_pass, rays = [], 0, 0
+    for job in jobs:
+        cam = job.camera
+        r = O.forward(job.scene.means, job.scene.covs, job.scene.attrs, cam.as_vector(), cam.height, cam.width,
+                      job.K, job.eta)
+        kes.append(r.k_eff.astype(np.int64))
+        n_pass += int(r.n_pass.astype(np.int64).sum())
+        rays += cam.height * cam.width
+    ke = np.concatenate(kes)
+    C = jobs[0].scene.channels
     out = {
-        "workload": job.name,
-        "rays": int(cam.height * cam.width),
-        "sum_n_pass": int(r.n_pass.astype(np.int64).sum()),
+        "workload": name,
+        "renders": len(jobs),
+        "rays": int(rays),
+        "sum_n_pass": n_pass,
         "sum_k_eff": int(ke.sum()),
         "sum_k_eff_sq": int((ke * ke).sum()),
         "hit_rays": int((ke > 0).sum()),
@@ -51,7 +61,7 @@ def count(job) -> dict:
     out["flop_bwd"] = O.backward_flops(ke, C)
     out["flop_bwd_pixel"] = O.FLOP_BPAIR * out["sum_k_eff_sq"] + O.flop_bkept_pixel(C) * out["sum_k_eff"]
     out["flop_bwd_chain"] = O.flop_bkept_chain(C) * out["sum_k_eff"]
-    out["flop_forward"] = O.forward_flops(r.n_pass, ke, C)
+    out["flop_forward"] = O.FLOP_TRACE * n_pass + out["flop_blend"]
     out["flop_per_ray_fwd_bwd"] = (out["flop_forward"] + out["flop_bwd"]) / out["rays"]
     out["oracle_seconds"] = round(time.time() - t0, 2)
     return out
@@ -61,10 +71,16 @@ def path_for(name: str) -> str:
     return os.path.join(HERE, f"opcount_{name}.json")
 
 
+POSES_NAME = "torus4096_256poses_128px_C3_K20"
+
+
 def main():
-    job = S.config_torus()
-    res = count(job)
-    with open(path_for(job.name), "w") as f:
+    if len(sys.argv) > 1 and sys.argv[1] == "poses":
+        res = count(S.config_poses(), POSES_NAME)
+    else:
+        job = S.config_torus()
+        res = count(job, job.name)
+    with open(path_for(res["workload"]), "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps(res))
 

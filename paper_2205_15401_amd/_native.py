@@ -21,11 +21,16 @@ VOGE_EHIP = -3
 VOGE_STATUS_NOTSPD = 1
 VOGE_STATUS_NONFINITE = 2
 VOGE_REUSE_PREP = 1
+VOGE_FORWARD = 2
+VOGE_BACKWARD = 4
+VOGE_GRAPH = 8
+VOGE_MAX_BATCH = 4096
 
 EXPORTS = [
     "voge_create", "voge_destroy", "voge_workspace_size", "voge_render_forward",
     "voge_render_backward", "voge_status", "voge_last_error", "voge_version", "voge_debug_phi",
-    "voge_profile_enable", "voge_profile_read",
+    "voge_profile_enable", "voge_profile_read", "voge_batch_workspace_size", "voge_render_batch",
+    "voge_batch_status",
 ]
 
 
@@ -37,6 +42,14 @@ class VogeCamera(ctypes.Structure):
 
 class VogeParams(ctypes.Structure):
     _fields_ = [("eta", ctypes.c_float), ("K", ctypes.c_int32)]
+
+
+class VogeItem(ctypes.Structure):
+    _fields_ = [("means", ctypes.c_void_p), ("covs", ctypes.c_void_p), ("attrs", ctypes.c_void_p),
+                ("N", ctypes.c_int32), ("C", ctypes.c_int32), ("camera", VogeCamera), ("params", VogeParams),
+                ("image", ctypes.c_void_p), ("wsum", ctypes.c_void_p), ("kept", ctypes.c_void_p),
+                ("grad_image", ctypes.c_void_p), ("grad_means", ctypes.c_void_p), ("grad_covs", ctypes.c_void_p),
+                ("grad_attrs", ctypes.c_void_p), ("grad_camera", ctypes.c_void_p)]
 
 
 class VogePhaseTime(ctypes.Structure):
@@ -76,6 +89,10 @@ def load(path: str = LIB_PATH):
         lib.voge_debug_phi.argtypes = [P, P, I, P]
         lib.voge_profile_enable.argtypes = [P, I]
         lib.voge_profile_read.argtypes = [P, ctypes.POINTER(VogePhaseTime), I, ctypes.POINTER(I), I]
+        ItemP = ctypes.POINTER(VogeItem)
+        lib.voge_batch_workspace_size.argtypes = [ItemP, I, I, ctypes.POINTER(SZ)]
+        lib.voge_render_batch.argtypes = [P, ItemP, I, I, P, SZ, P]
+        lib.voge_batch_status.argtypes = [P, I, ctypes.POINTER(ctypes.c_int32), P]
         for name in EXPORTS:
             if name != "voge_last_error":
                 getattr(lib, name).restype = I
@@ -133,6 +150,32 @@ def voge_status(workspace, stream) -> int:
     st = ctypes.c_int32()
     _check(load().voge_status(workspace, ctypes.byref(st), stream))
     return st.value
+
+
+def item_array(items):
+    """A ctypes array of VogeItem from a sequence of VogeItem."""
+    arr = (VogeItem * len(items))()
+    for i, it in enumerate(items):
+        arr[i] = it
+    return arr
+
+
+def voge_batch_workspace_size(items, with_backward: bool) -> int:
+    arr = items if isinstance(items, ctypes.Array) else item_array(items)
+    out = ctypes.c_size_t()
+    _check(load().voge_batch_workspace_size(arr, len(arr), int(bool(with_backward)), ctypes.byref(out)))
+    return out.value
+
+
+def voge_render_batch(ctx, items, flags, workspace, workspace_bytes, stream) -> int:
+    arr = items if isinstance(items, ctypes.Array) else item_array(items)
+    return _check(load().voge_render_batch(ctx, arr, len(arr), int(flags), workspace, int(workspace_bytes), stream))
+
+
+def voge_batch_status(workspace, n_items, stream):
+    out = (ctypes.c_int32 * int(n_items))()
+    _check(load().voge_batch_status(workspace, int(n_items), out, stream))
+    return list(out)
 
 
 def voge_debug_phi(x, y, n, stream) -> int:

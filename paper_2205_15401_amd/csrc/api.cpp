@@ -2,6 +2,7 @@
 // workspace planning and kernel launches on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -12,6 +13,27 @@
 #include "voge.h"
 #include "voge_debug.h"
 #include "voge_launch.hpp"
+
+namespace {
+
+// A fixed ring of pinned host buffers, made at context creation, stages item
+// tables too large for launch arguments.
+constexpr int RING_SLOTS = 4;
+constexpr int GRAPH_CACHE = 32;
+
+struct Stage {
+    void* host = nullptr;
+    hipEvent_t done = nullptr;
+    bool used = false;
+};
+
+struct GraphEntry {
+    std::vector<int64_t> key;
+    hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;
+};
+
+}  // namespace
 
 struct voge_ctx {
     int device;
@@ -26,6 +48,14 @@ struct voge_ctx {
     std::vector<Pending> pending;
     std::vector<hipEvent_t> pool;
     std::map<std::string, std::pair<double, long long>> totals;
+    // batch tables and graphs
+    std::mutex stage_mu;
+    std::vector<Stage> ring;
+    int ring_next = 0;
+    size_t stage_bytes = 0;
+    std::mutex graph_mu;
+    std::vector<GraphEntry> graphs;
+    uint64_t tick = 0;
 };
 
 namespace {
@@ -135,59 +165,150 @@ namespace voge {
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-Plan plan_workspace(int N, int C, int H, int W, int K) {
-    (void)C;
-    Plan p{};
-    size_t off = align256(sizeof(WsHeader));
+// Sizes, table order and workspace layout of a batch.  Items are grouped by
+// K-buffer depth (stable), so each group's tiles are contiguous.
+BatchPlan plan_batch(const ItemShape* shapes, int n) {
+    BatchPlan p;
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return pick_kbuf(shapes[a].K) < pick_kbuf(shapes[b].K); });
+    p.items.resize(n);
+    for (int j = 0; j < n; ++j) {
+        ItemPlan& it = p.items[j];
+        it.caller = order[j];
+        it.s = shapes[order[j]];
+        it.kb = pick_kbuf(it.s.K);
+        it.n_tiles = ((it.s.H + TILE - 1) / TILE) * ((it.s.W + TILE - 1) / TILE);
+        it.S = (size_t)it.n_tiles * TILE_THREADS;
+        it.kern_start = p.total_kern;
+        it.tile_start = p.total_tiles;
+        it.pblk_start = p.total_pblk;
+        it.n_pblk = (it.s.N + PREP_THREADS - 1) / PREP_THREADS;
+        it.epi_start = p.total_epi;
+        it.n_epi = (it.s.N + EPI_THREADS - 1) / EPI_THREADS;
+        it.list_off = p.total_list;
+        it.attr_off = p.total_attr;
+        p.total_kern += it.s.N;
+        p.total_tiles += it.n_tiles;
+        p.total_pblk += it.n_pblk;
+        p.total_epi += it.n_epi;
+        p.total_list += (size_t)it.s.K * it.S;
+        p.total_attr += (size_t)it.s.N * it.s.C;
+        if (p.groups.empty() || p.groups.back().kb != it.kb)
+            p.groups.push_back({it.kb, j, 0, it.tile_start, 0});
+        p.groups.back().n_items += 1;
+        p.groups.back().n_tiles += it.n_tiles;
+    }
+    int ib = 0;
+    while ((1 << ib) < n) ++ib;
+    p.item_bits = ib;
+
+    size_t off = align256(PREFIX_BYTES);
     auto take = [&](size_t bytes) {
         const size_t o = off;
         off = align256(off + bytes);
         return o;
     };
-    const size_t n = N > 0 ? (size_t)N : 1;
-    const size_t k = K > 0 ? (size_t)K : 1;
-    p.n_tiles = ((H + TILE - 1) / TILE) * ((W + TILE - 1) / TILE);
-    p.S = (size_t)p.n_tiles * TILE_THREADS;
-    p.sort_blocks = sort_blocks((int)n);
-    p.off_keys = take(4 * n);
-    p.off_vals = take(4 * n);
-    p.off_keys2 = take(4 * n);
-    p.off_vals2 = take(4 * n);
+    const size_t nk = p.total_kern > 0 ? (size_t)p.total_kern : 1;
+    const size_t nl = p.total_list > 0 ? p.total_list : 1;
+    const size_t nt = p.total_tiles > 0 ? (size_t)p.total_tiles : 1;
+    p.sort_blocks = sort_blocks((int)nk);
+    p.off_items = take(sizeof(ItemDev) * (size_t)(n > 0 ? n : 1));
+    p.off_tile_item = take(sizeof(int) * nt);
+    p.off_pblk_item = take(sizeof(int) * (size_t)(p.total_pblk > 0 ? p.total_pblk : 1));
+    p.off_epi_item = take(sizeof(int) * (size_t)(p.total_epi > 0 ? p.total_epi : 1));
+    p.off_keys = take(4 * nk);
+    p.off_vals = take(4 * nk);
+    p.off_keys2 = take(4 * nk);
+    p.off_vals2 = take(4 * nk);
     p.off_hist = take(4 * 256 * (size_t)p.sort_blocks);
-    p.off_cull = take(sizeof(CullRec) * n);
-    p.off_rec = take(sizeof(TraceRec) * n);
-    p.off_geo = take(sizeof(GeoRec) * n);
-    p.off_keff = take(4 * p.S);
-    p.off_kl_l = take(8 * k * p.S);
-    p.off_kl_m = take(4 * k * p.S);
-    p.off_kl_s = take(4 * k * p.S);
-    p.off_kl_T = take(4 * k * p.S);
-    p.off_kl_r = take(4 * k * p.S);
-    p.off_kl_i = take(4 * k * p.S);
+    p.off_cull = take(sizeof(CullRec) * nk);
+    p.off_rec = take(sizeof(TraceRec) * nk);
+    p.off_geo = take(sizeof(GeoRec) * nk);
+    p.off_keff = take(4 * nt * TILE_THREADS);
+    p.off_kl_l = take(8 * nl);
+    p.off_kl_m = take(4 * nl);
+    p.off_kl_s = take(4 * nl);
+    p.off_kl_T = take(4 * nl);
+    p.off_kl_r = take(4 * nl);
+    p.off_kl_i = take(4 * nl);
     p.fwd_bytes = off;
-    p.n_epi_blocks = (int)((n + EPI_THREADS - 1) / EPI_THREADS);
-    p.off_gM = take(sizeof(float) * 3 * n);
-    p.off_gS = take(sizeof(float) * 6 * n);
-    p.off_tileD = take(sizeof(double) * 3 * (size_t)p.n_tiles);
-    p.off_camP = take(sizeof(double) * 12 * (size_t)p.n_epi_blocks);
-    p.off_bw = take(16 * k * p.S);
-    p.off_pairs = take(32 * k * p.S);    // PairRec
+    // gM [3 nk] | gS [6 nk] | gA [total_attr]: one contiguous range, cleared at once
+    p.off_grads = take(sizeof(float) * (9 * nk + p.total_attr));
+    p.off_tileD = take(sizeof(double) * 3 * nt);
+    p.off_camP = take(sizeof(double) * 12 * (size_t)(p.total_epi > 0 ? p.total_epi : 1));
+    p.off_bw = take(16 * nl);
+    p.off_pairs = take(32 * nl);    // PairRec
     p.bwd_bytes = off;
     return p;
 }
 
-WsPtrs carve(void* base, const Plan& p, bool with_backward) {
-    unsigned char* b = static_cast<unsigned char*>(base);
-    WsPtrs w{};
-    w.hdr = reinterpret_cast<WsHeader*>(b);
+}  // namespace voge
+
+namespace {
+
+int validate_item(const voge_item_t& it, int flags, int i) {
+    auto bad = [&](const char* what) { return fail(VOGE_EINVAL, "item " + std::to_string(i) + ": " + what); };
+    if (it.N < 0 || it.N >= voge::MAX_KERNELS) return bad("N must be in [0, 2^24)");
+    if (it.C < 1 || it.C > 1024) return bad("C must be in [1, 1024]");
+    if (it.N > 0 && (!it.means || !it.covs || !it.attrs)) return bad("means, covs and attrs are required");
+    if (int rc = check_camera(&it.camera)) return bad(g_err.c_str()), rc;
+    if (!(it.params.eta > 0.f && it.params.eta < 1.f)) return bad("eta must be in (0, 1)");
+    if (it.params.K < 1 || it.params.K > voge::MAX_K) return bad("K must be in [1, 64]");
+    if ((flags & VOGE_FORWARD) && !it.image) return bad("image is required with VOGE_FORWARD");
+    if (flags & VOGE_BACKWARD) {
+        if (!it.grad_image) return bad("grad_image is required with VOGE_BACKWARD");
+        if (it.N > 0 && (!it.grad_means || !it.grad_covs || !it.grad_attrs))
+            return bad("grad_means, grad_covs and grad_attrs are required with VOGE_BACKWARD");
+    }
+    return VOGE_OK;
+}
+
+voge::ItemShape shape_of(const voge_item_t& it) {
+    return {it.N, it.C, it.camera.height, it.camera.width, it.params.K};
+}
+
+// Carved device pointers of a batch workspace.
+struct BatchWs {
+    unsigned char* base;
+    voge::WsHeader* hdr;
+    int* status;
+    voge::ItemDev* items;
+    int *tile_item, *pblk_item, *epi_item;
+    uint32_t *keys, *vals, *keys2, *vals2, *hist;
+    voge::CullRec* cull;
+    voge::TraceRec* rec;
+    voge::GeoRec* geo;
+    int32_t* keff;
+    double* kl_l;
+    float *kl_m, *kl_s, *kl_T;
+    int32_t *kl_r, *kl_i;
+    float* grads;
+    double* tileD;
+    double* camP;
+    float4* bw;
+    voge::PairRec* pairs;
+};
+
+BatchWs carve_batch(void* ws, const voge::BatchPlan& p) {
+    unsigned char* b = static_cast<unsigned char*>(ws);
+    BatchWs w{};
+    w.base = b;
+    w.hdr = reinterpret_cast<voge::WsHeader*>(b);
+    w.status = reinterpret_cast<int*>(b + voge::OFF_STATUS);
+    w.items = reinterpret_cast<voge::ItemDev*>(b + p.off_items);
+    w.tile_item = reinterpret_cast<int*>(b + p.off_tile_item);
+    w.pblk_item = reinterpret_cast<int*>(b + p.off_pblk_item);
+    w.epi_item = reinterpret_cast<int*>(b + p.off_epi_item);
     w.keys = reinterpret_cast<uint32_t*>(b + p.off_keys);
     w.vals = reinterpret_cast<uint32_t*>(b + p.off_vals);
     w.keys2 = reinterpret_cast<uint32_t*>(b + p.off_keys2);
     w.vals2 = reinterpret_cast<uint32_t*>(b + p.off_vals2);
     w.hist = reinterpret_cast<uint32_t*>(b + p.off_hist);
-    w.cull = reinterpret_cast<CullRec*>(b + p.off_cull);
-    w.rec = reinterpret_cast<TraceRec*>(b + p.off_rec);
-    w.geo = reinterpret_cast<GeoRec*>(b + p.off_geo);
+    w.cull = reinterpret_cast<voge::CullRec*>(b + p.off_cull);
+    w.rec = reinterpret_cast<voge::TraceRec*>(b + p.off_rec);
+    w.geo = reinterpret_cast<voge::GeoRec*>(b + p.off_geo);
     w.keff = reinterpret_cast<int32_t*>(b + p.off_keff);
     w.kl_l = reinterpret_cast<double*>(b + p.off_kl_l);
     w.kl_m = reinterpret_cast<float*>(b + p.off_kl_m);
@@ -195,22 +316,293 @@ WsPtrs carve(void* base, const Plan& p, bool with_backward) {
     w.kl_T = reinterpret_cast<float*>(b + p.off_kl_T);
     w.kl_r = reinterpret_cast<int32_t*>(b + p.off_kl_r);
     w.kl_i = reinterpret_cast<int32_t*>(b + p.off_kl_i);
-    if (with_backward) {
-        w.gM = reinterpret_cast<float*>(b + p.off_gM);
-        w.gS = reinterpret_cast<float*>(b + p.off_gS);
-        w.tileD = reinterpret_cast<double*>(b + p.off_tileD);
-        w.camP = reinterpret_cast<double*>(b + p.off_camP);
-        w.bw = reinterpret_cast<float4*>(b + p.off_bw);
-        w.pairs = reinterpret_cast<PairRec*>(b + p.off_pairs);
-    }
+    w.grads = reinterpret_cast<float*>(b + p.off_grads);
+    w.tileD = reinterpret_cast<double*>(b + p.off_tileD);
+    w.camP = reinterpret_cast<double*>(b + p.off_camP);
+    w.bw = reinterpret_cast<float4*>(b + p.off_bw);
+    w.pairs = reinterpret_cast<voge::PairRec*>(b + p.off_pairs);
     return w;
 }
 
-}  // namespace voge
+// The device record of table entry j.
+voge::ItemDev item_record(const voge::BatchPlan& p, int j, const voge_item_t& src, const BatchWs& w, int flags,
+                          bool with_backward) {
+    const voge::ItemPlan& ip = p.items[j];
+    voge::ItemDev d{};
+    voge::TraceArgs& t = d.t;
+    const size_t k0 = (size_t)ip.kern_start, lo = ip.list_off;
+    t.cull = w.cull + k0;
+    t.rec = w.rec + k0;
+    t.geo = w.geo + k0;
+    t.N = ip.s.N;
+    t.H = ip.s.H;
+    t.W = ip.s.W;
+    t.K = ip.s.K;
+    t.C = ip.s.C;
+    t.n_tiles = ip.n_tiles;
+    t.S = ip.S;
+    t.F = src.camera.focal;
+    t.cx = src.camera.cx;
+    t.cy = src.camera.cy;
+    t.rad2 = -2.0 * std::log((double)src.params.eta);
+    t.attrs = src.attrs;
+    t.keff = w.keff + (size_t)ip.tile_start * voge::TILE_THREADS;
+    t.kl_l = w.kl_l + lo;
+    t.kl_m = w.kl_m + lo;
+    t.kl_s = w.kl_s + lo;
+    t.kl_T = w.kl_T + lo;
+    t.kl_r = w.kl_r + lo;
+    t.kl_i = w.kl_i + lo;
+    if (flags & VOGE_FORWARD) {
+        t.image = src.image;
+        t.wsum = src.wsum;
+        t.kept = src.kept;
+    }
+    if (with_backward) {
+        const size_t nk = p.total_kern > 0 ? (size_t)p.total_kern : 1;
+        float* gM = w.grads;
+        float* gS = gM + 3 * nk;
+        float* gA = gS + 6 * nk;
+        t.grad_image = src.grad_image;
+        t.gM = gM + 3 * k0;
+        t.gS = gS + 6 * k0;
+        t.gA = gA + ip.attr_off;
+        t.tileD = w.tileD + 3 * (size_t)ip.tile_start;
+        t.bw = w.bw + lo;
+        t.pairs = w.pairs + lo;
+        d.grad_means = src.grad_means;
+        d.grad_covs = src.grad_covs;
+        d.grad_attrs = src.grad_attrs;
+        d.grad_camera = src.grad_camera;
+        d.camP = w.camP + 12 * (size_t)ip.epi_start;
+    }
+    d.means = src.means;
+    d.covs = src.covs;
+    d.status = w.status + ip.caller;
+    d.cam = to_dev(&src.camera);
+    d.kern_start = ip.kern_start;
+    d.tile_start = ip.tile_start;
+    d.pblk_start = ip.pblk_start;
+    d.n_pblk = ip.n_pblk;
+    d.epi_start = ip.epi_start;
+    d.n_epi = ip.n_epi;
+    return d;
+}
+
+voge::BatchDev batch_dev(const voge::BatchPlan& p, const BatchWs& w) {
+    voge::BatchDev b{};
+    b.items = w.items;
+    b.n_items = (int)p.items.size();
+    b.pblk_item = w.pblk_item;
+    b.epi_item = w.epi_item;
+    b.item_bits = p.item_bits;
+    b.hdr = w.hdr;
+    return b;
+}
+
+voge::GroupDev group_dev(const voge::GroupPlan& g, const BatchWs& w) {
+    voge::GroupDev d{};
+    d.items = w.items;
+    d.tile_item = w.tile_item;
+    d.single = g.n_items == 1 ? g.first_item : -1;
+    d.tile0 = g.tile0;
+    d.n_tiles = g.n_tiles;
+    return d;
+}
+
+// Writes the item table into the workspace: through launch arguments for a
+// few items, else through a pinned staging buffer of the context's ring.
+int upload_items(voge_ctx_t* ctx, const std::vector<voge::ItemDev>& recs, const BatchWs& w, bool clear_status,
+                 hipStream_t s);
+
+// All launches of a call after the table upload.
+int launch_compute(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, int flags, bool profile,
+                   hipStream_t s) {
+    const voge::BatchDev b = batch_dev(p, w);
+    auto scope = [&](const char* name) { return ProfScope(profile ? ctx : nullptr, name, s); };
+    const bool fwd_part = (flags & VOGE_FORWARD) || !(flags & VOGE_REUSE_PREP);
+    if (fwd_part) {
+        {
+            ProfScope ps = scope("prep");
+            voge::launch_prep(b, p.total_pblk, p.total_kern, w.keys, w.vals, w.keys2, w.vals2, w.hist, w.cull, w.rec,
+                              w.geo, s);
+            if (int rc = hip_check(hipGetLastError(), "prep launch")) return rc;
+        }
+        {
+            ProfScope ps = scope("select");
+            for (const auto& g : p.groups)
+                if (int rc = hip_check(voge::launch_select(group_dev(g, w), g.kb, s), "select launch")) return rc;
+        }
+        {
+            ProfScope ps = scope("blend");
+            for (const auto& g : p.groups)
+                if (int rc = hip_check(voge::launch_blend(group_dev(g, w), g.kb, s), "blend launch")) return rc;
+        }
+    }
+    if (flags & VOGE_BACKWARD) {
+        {
+            ProfScope ps = scope("zero");
+            const size_t nk = p.total_kern > 0 ? (size_t)p.total_kern : 1;
+            voge::launch_fill_u32(w.grads, 9 * nk + p.total_attr, 0u, s);
+        }
+        {
+            ProfScope ps = scope("bwd");
+            for (const auto& g : p.groups)
+                if (int rc = hip_check(voge::launch_bwd(group_dev(g, w), g.kb, s), "backward launch")) return rc;
+        }
+        {
+            ProfScope ps = scope("bwd_reduce");
+            for (const auto& g : p.groups)
+                if (int rc = hip_check(voge::launch_bwd_reduce(group_dev(g, w), g.kb, s), "backward reduce launch"))
+                    return rc;
+        }
+        {
+            ProfScope ps = scope("epilogue");
+            if (int rc = hip_check(voge::launch_epilogue(b, p.total_epi, s), "epilogue launch")) return rc;
+        }
+    }
+    return VOGE_OK;
+}
+
+std::vector<int64_t> graph_key(const voge::BatchPlan& p, const void* ws, int flags) {
+    std::vector<int64_t> k;
+    k.reserve(3 + 5 * p.items.size());
+    k.push_back((int64_t)reinterpret_cast<uintptr_t>(ws));
+    k.push_back(flags);
+    k.push_back((int64_t)p.items.size());
+    for (const auto& it : p.items) {
+        k.push_back(it.caller);
+        k.push_back(it.s.N);
+        k.push_back(it.s.C);
+        k.push_back(((int64_t)it.s.H << 32) | (uint32_t)it.s.W);
+        k.push_back(it.s.K);
+    }
+    return k;
+}
+
+int run_graph(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, int flags, hipStream_t s);
+
+// The whole call: checks, plan, table, launches.
+int run_batch(voge_ctx_t* ctx, const voge_item_t* items, int n, int flags, void* workspace, size_t workspace_bytes,
+              hipStream_t s) {
+    const bool backward = (flags & VOGE_BACKWARD) != 0;
+    std::vector<voge::ItemShape> shapes(n);
+    for (int i = 0; i < n; ++i) shapes[i] = shape_of(items[i]);
+    const voge::BatchPlan p = voge::plan_batch(shapes.data(), n);
+    if (p.total_kern >= (1 << 30)) return fail(VOGE_EINVAL, "too many kernels in one batch");
+    if (workspace_bytes < (backward ? p.bwd_bytes : p.fwd_bytes)) return fail(VOGE_ENOSPACE, "workspace too small");
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return fail(VOGE_EHIP, "cannot select the context's device");
+    const BatchWs w = carve_batch(workspace, p);
+    std::vector<voge::ItemDev> recs(n);
+    for (int j = 0; j < n; ++j) recs[j] = item_record(p, j, items[p.items[j].caller], w, flags, backward);
+    const bool fwd_part = (flags & VOGE_FORWARD) || !(flags & VOGE_REUSE_PREP);
+    {
+        ProfScope ps(ctx, "upload", s);
+        if (int rc = upload_items(ctx, recs, w, fwd_part, s)) return rc;
+    }
+    if (flags & VOGE_GRAPH) return run_graph(ctx, p, w, flags, s);
+    return launch_compute(ctx, p, w, flags, true, s);
+}
+
+}  // namespace
+
+namespace {
+
+int upload_items(voge_ctx_t* ctx, const std::vector<voge::ItemDev>& recs, const BatchWs& w, bool clear_status,
+                 hipStream_t s) {
+    const int n = (int)recs.size();
+    if (n <= 2 * voge::INIT_ITEMS) {
+        for (int first = 0; first < n; first += voge::INIT_ITEMS) {
+            voge::InitPack pack{};
+            const int count = std::min(voge::INIT_ITEMS, n - first);
+            for (int b = 0; b < count; ++b) pack.it[b] = recs[first + b];
+            voge::launch_init(pack, first, count, true, w.items, w.tile_item, w.pblk_item, w.epi_item, w.hdr,
+                              clear_status, clear_status && first == 0, s);
+            if (int rc = hip_check(hipGetLastError(), "init launch")) return rc;
+        }
+        return VOGE_OK;
+    }
+    const size_t bytes = sizeof(voge::ItemDev) * (size_t)n;
+    std::lock_guard<std::mutex> g(ctx->stage_mu);
+    if (ctx->ring.empty() || bytes > ctx->stage_bytes) return fail(VOGE_EINVAL, "item table exceeds the staging area");
+    Stage& st = ctx->ring[ctx->ring_next];
+    ctx->ring_next = (ctx->ring_next + 1) % (int)ctx->ring.size();
+    if (st.used) {
+        if (int rc = hip_check(hipEventSynchronize(st.done), "hipEventSynchronize (staging)")) return rc;
+    }
+    std::memcpy(st.host, recs.data(), bytes);
+    if (int rc = hip_check(hipMemcpyAsync(w.items, st.host, bytes, hipMemcpyHostToDevice, s), "hipMemcpyAsync (items)"))
+        return rc;
+    if (int rc = hip_check(hipEventRecord(st.done, s), "hipEventRecord (staging)")) return rc;
+    st.used = true;
+    voge::InitPack none{};
+    voge::launch_init(none, 0, n, false, w.items, w.tile_item, w.pblk_item, w.epi_item, w.hdr, clear_status,
+                      clear_status, s);
+    return hip_check(hipGetLastError(), "init launch");
+}
+
+// Replays the call's launches from a cached graph, capturing it on `s` the
+// first time this (workspace, flags, shapes) key is seen.
+int run_graph(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, int flags, hipStream_t s) {
+    const std::vector<int64_t> key = graph_key(p, w.base, flags);
+    std::lock_guard<std::mutex> g(ctx->graph_mu);
+    GraphEntry* hit = nullptr;
+    for (auto& e : ctx->graphs)
+        if (e.key == key) hit = &e;
+    if (!hit) {
+        if (int rc = hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture"))
+            return rc;
+        const int rc_launch = launch_compute(ctx, p, w, flags, false, s);
+        hipGraph_t graph = nullptr;
+        const hipError_t e_end = hipStreamEndCapture(s, &graph);
+        if (rc_launch) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc_launch;
+        }
+        if (int rc = hip_check(e_end, "hipStreamEndCapture")) return rc;
+        hipGraphExec_t exec = nullptr;
+        const hipError_t e_inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (int rc = hip_check(e_inst, "hipGraphInstantiate")) return rc;
+        if ((int)ctx->graphs.size() >= GRAPH_CACHE) {
+            auto lru = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
+                                        [](const GraphEntry& a, const GraphEntry& b) { return a.last_use < b.last_use; });
+            (void)hipGraphExecDestroy(lru->exec);
+            ctx->graphs.erase(lru);
+        }
+        ctx->graphs.push_back({key, exec, 0});
+        hit = &ctx->graphs.back();
+    }
+    hit->last_use = ++ctx->tick;
+    ProfScope ps(ctx, "graph", s);
+    return hip_check(hipGraphLaunch(hit->exec, s), "hipGraphLaunch");
+}
+
+voge_item_t single_item(const float* means, const float* covs, const float* attrs, int N, int C,
+                        const voge_camera_t* cam, const voge_params_t* params) {
+    voge_item_t it{};
+    it.means = means;
+    it.covs = covs;
+    it.attrs = attrs;
+    it.N = N;
+    it.C = C;
+    it.camera = *cam;
+    it.params = *params;
+    return it;
+}
+
+int check_workspace(void* workspace) {
+    if (!workspace) return fail(VOGE_EINVAL, "workspace is null");
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(VOGE_EINVAL, "workspace must be 256-byte aligned");
+    return VOGE_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
-int voge_version(void) { return 10000; }
+int voge_version(void) { return 10100; }
 
 const char* voge_last_error(void) { return g_err.c_str(); }
 
@@ -223,9 +615,21 @@ int voge_create(voge_ctx_t** ctx, int device) {
     if (int rc = hip_check(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device),
                            "hipDeviceGetAttribute"))
         return rc;
+    DeviceGuard guard(device);
+    if (!guard.ok) return fail(VOGE_EHIP, "cannot select the device");
     voge_ctx_t* c = new voge_ctx();
     c->device = device;
     c->n_cu = n_cu;
+    c->stage_bytes = sizeof(voge::ItemDev) * (size_t)voge::MAX_BATCH;
+    c->ring.resize(RING_SLOTS);
+    for (auto& st : c->ring) {
+        hipError_t e = hipHostMalloc(&st.host, c->stage_bytes, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&st.done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            voge_destroy(c);
+            return hip_check(e, "staging allocation");
+        }
+    }
     *ctx = c;
     g_err.clear();
     return VOGE_OK;
@@ -242,6 +646,20 @@ int voge_destroy(voge_ctx_t* ctx) {
         }
         for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
     }
+    {
+        std::lock_guard<std::mutex> g(ctx->stage_mu);
+        for (auto& st : ctx->ring) {
+            if (st.done) {
+                if (st.used) (void)hipEventSynchronize(st.done);
+                (void)hipEventDestroy(st.done);
+            }
+            if (st.host) (void)hipHostFree(st.host);
+        }
+    }
+    {
+        std::lock_guard<std::mutex> g(ctx->graph_mu);
+        for (auto& e : ctx->graphs) (void)hipGraphExecDestroy(e.exec);
+    }
     delete ctx;
     return VOGE_OK;
 }
@@ -253,87 +671,25 @@ int voge_workspace_size(int N, int C, const voge_camera_t* cam, const voge_param
     if (C < 1 || C > 1024) return fail(VOGE_EINVAL, "C must be in [1, 1024]");
     if (int rc = check_camera(cam)) return rc;
     if (!params || params->K < 1 || params->K > voge::MAX_K) return fail(VOGE_EINVAL, "K must be in [1, 64]");
-    const voge::Plan p = voge::plan_workspace(N, C, cam->height, cam->width, params->K);
+    const voge::ItemShape sh{N, C, cam->height, cam->width, params->K};
+    const voge::BatchPlan p = voge::plan_batch(&sh, 1);
     *bytes = with_backward ? p.bwd_bytes : p.fwd_bytes;
+    g_err.clear();
     return VOGE_OK;
 }
-
-namespace {
-
-voge::TraceArgs trace_args(const voge_ctx_t* ctx, const voge::WsPtrs& w, const voge::Plan& p, int N, int C,
-                           const voge_camera_t* cam, const voge_params_t* params, const float* attrs) {
-    voge::TraceArgs ta{};
-    ta.hdr = w.hdr;
-    ta.n_cu = ctx->n_cu;
-    ta.cull = w.cull;
-    ta.rec = w.rec;
-    ta.geo = w.geo;
-    ta.N = N;
-    ta.H = cam->height;
-    ta.W = cam->width;
-    ta.K = params->K;
-    ta.C = C;
-    ta.n_tiles = p.n_tiles;
-    ta.S = p.S;
-    ta.F = cam->focal;
-    ta.cx = cam->cx;
-    ta.cy = cam->cy;
-    ta.rad2 = -2.0 * std::log((double)params->eta);
-    ta.attrs = attrs;
-    ta.keff = w.keff;
-    ta.kl_l = w.kl_l;
-    ta.kl_m = w.kl_m;
-    ta.kl_s = w.kl_s;
-    ta.kl_T = w.kl_T;
-    ta.kl_r = w.kl_r;
-    ta.kl_i = w.kl_i;
-    ta.gM = w.gM;
-    ta.gS = w.gS;
-    ta.tileD = w.tileD;
-    ta.bw = w.bw;
-    ta.pairs = w.pairs;
-    return ta;
-}
-
-// prep + sort + select + blend: the whole forward on `s`
-int run_forward(voge_ctx_t* ctx, const float* means, const float* covs, const voge_camera_t* cam,
-                const voge::WsPtrs& w, voge::TraceArgs ta, hipStream_t s) {
-    {
-        ProfScope ps(ctx, "prep", s);
-        voge::launch_fill_u32(&w.hdr->status, 1, 0u, s);
-        voge::launch_prep(means, covs, ta.N, to_dev(cam), ta.rad2, w, s);
-    }
-    {
-        ProfScope ps(ctx, "select", s);
-        if (int rc = hip_check(voge::launch_select(ta, s), "select launch")) return rc;
-    }
-    {
-        ProfScope ps(ctx, "blend", s);
-        if (int rc = hip_check(voge::launch_blend(ta, s), "blend launch")) return rc;
-    }
-    return VOGE_OK;
-}
-
-}  // namespace
 
 int voge_render_forward(voge_ctx_t* ctx, const float* means, const float* covs, const float* attrs, int N, int C,
                         const voge_camera_t* cam, const voge_params_t* params, float* image, float* wsum,
                         int32_t* kept, void* workspace, size_t workspace_bytes, void* stream) {
     if (int rc = check_common(ctx, means, covs, attrs, N, C, cam, params)) return rc;
     if (!image) return fail(VOGE_EINVAL, "image is required");
-    if (!workspace) return fail(VOGE_EINVAL, "workspace is null");
-    if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(VOGE_EINVAL, "workspace must be 256-byte aligned");
-    const voge::Plan p = voge::plan_workspace(N, C, cam->height, cam->width, params->K);
-    if (workspace_bytes < p.fwd_bytes) return fail(VOGE_ENOSPACE, "workspace too small");
-    DeviceGuard guard(ctx->device);
-    if (!guard.ok) return fail(VOGE_EHIP, "cannot select the context's device");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const voge::WsPtrs w = voge::carve(workspace, p, false);
-    voge::TraceArgs ta = trace_args(ctx, w, p, N, C, cam, params, attrs);
-    ta.image = image;
-    ta.wsum = wsum;
-    ta.kept = kept;
-    if (int rc = run_forward(ctx, means, covs, cam, w, ta, s)) return rc;
+    if (int rc = check_workspace(workspace)) return rc;
+    voge_item_t it = single_item(means, covs, attrs, N, C, cam, params);
+    it.image = image;
+    it.wsum = wsum;
+    it.kept = kept;
+    if (int rc = run_batch(ctx, &it, 1, VOGE_FORWARD, workspace, workspace_bytes, static_cast<hipStream_t>(stream)))
+        return rc;
     g_err.clear();
     return VOGE_OK;
 }
@@ -347,51 +703,63 @@ int voge_render_backward(voge_ctx_t* ctx, const float* means, const float* covs,
     if (N > 0 && (!grad_means || !grad_covs || !grad_attrs))
         return fail(VOGE_EINVAL, "grad_means, grad_covs and grad_attrs are required");
     if (flags & ~VOGE_REUSE_PREP) return fail(VOGE_EINVAL, "unknown flags");
-    if (!workspace) return fail(VOGE_EINVAL, "workspace is null");
-    if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(VOGE_EINVAL, "workspace must be 256-byte aligned");
-    const voge::Plan p = voge::plan_workspace(N, C, cam->height, cam->width, params->K);
-    if (workspace_bytes < p.bwd_bytes) return fail(VOGE_ENOSPACE, "workspace too small");
-    DeviceGuard guard(ctx->device);
-    if (!guard.ok) return fail(VOGE_EHIP, "cannot select the context's device");
+    if (int rc = check_workspace(workspace)) return rc;
+    voge_item_t it = single_item(means, covs, attrs, N, C, cam, params);
+    it.grad_image = grad_image;
+    it.grad_means = grad_means;
+    it.grad_covs = grad_covs;
+    it.grad_attrs = grad_attrs;
+    it.grad_camera = grad_camera;
+    if (int rc = run_batch(ctx, &it, 1, VOGE_BACKWARD | (flags & VOGE_REUSE_PREP), workspace, workspace_bytes,
+                           static_cast<hipStream_t>(stream)))
+        return rc;
+    g_err.clear();
+    return VOGE_OK;
+}
+
+int voge_batch_workspace_size(const voge_item_t* items, int n_items, int with_backward, size_t* bytes) {
+    if (!bytes) return fail(VOGE_EINVAL, "bytes is null");
+    if (!items || n_items < 1 || n_items > voge::MAX_BATCH) return fail(VOGE_EINVAL, "n_items must be in [1, 4096]");
+    std::vector<voge::ItemShape> shapes(n_items);
+    for (int i = 0; i < n_items; ++i) {
+        if (int rc = validate_item(items[i], 0, i)) return rc;
+        shapes[i] = shape_of(items[i]);
+    }
+    const voge::BatchPlan p = voge::plan_batch(shapes.data(), n_items);
+    *bytes = with_backward ? p.bwd_bytes : p.fwd_bytes;
+    g_err.clear();
+    return VOGE_OK;
+}
+
+int voge_render_batch(voge_ctx_t* ctx, const voge_item_t* items, int n_items, int flags, void* workspace,
+                      size_t workspace_bytes, void* stream) {
+    if (!ctx) return fail(VOGE_EINVAL, "ctx is null");
+    if (!items || n_items < 1 || n_items > voge::MAX_BATCH) return fail(VOGE_EINVAL, "n_items must be in [1, 4096]");
+    if (flags & ~(VOGE_FORWARD | VOGE_BACKWARD | VOGE_REUSE_PREP | VOGE_GRAPH))
+        return fail(VOGE_EINVAL, "unknown flags");
+    if (!(flags & (VOGE_FORWARD | VOGE_BACKWARD))) return fail(VOGE_EINVAL, "VOGE_FORWARD or VOGE_BACKWARD is required");
+    if ((flags & VOGE_REUSE_PREP) && (flags & VOGE_FORWARD))
+        return fail(VOGE_EINVAL, "VOGE_REUSE_PREP goes with VOGE_BACKWARD alone");
+    if ((flags & VOGE_GRAPH) && stream == nullptr) return fail(VOGE_EINVAL, "VOGE_GRAPH needs a non-null stream");
+    if (int rc = check_workspace(workspace)) return rc;
+    for (int i = 0; i < n_items; ++i)
+        if (int rc = validate_item(items[i], flags, i)) return rc;
+    if (int rc = run_batch(ctx, items, n_items, flags, workspace, workspace_bytes, static_cast<hipStream_t>(stream)))
+        return rc;
+    g_err.clear();
+    return VOGE_OK;
+}
+
+int voge_batch_status(const void* workspace, int n_items, int32_t* device_status, void* stream) {
+    if (!workspace || !device_status) return fail(VOGE_EINVAL, "workspace and device_status are required");
+    if (n_items < 1 || n_items > voge::MAX_BATCH) return fail(VOGE_EINVAL, "n_items must be in [1, 4096]");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const voge::WsPtrs w = voge::carve(workspace, p, true);
-    voge::TraceArgs ta = trace_args(ctx, w, p, N, C, cam, params, attrs);
-    if (!(flags & VOGE_REUSE_PREP)) {
-        if (int rc = run_forward(ctx, means, covs, cam, w, ta, s)) return rc;   // lists and T, no image
-    }
-    if (N > 0) {
-        ProfScope ps(ctx, "zero", s);
-        voge::launch_zero3(w.gM, (size_t)N * 3, w.gS, (size_t)N * 6, grad_attrs, (size_t)N * C, s);
-    }
-    ta.grad_image = grad_image;
-    ta.grad_attrs = grad_attrs;
-    {
-        ProfScope ps(ctx, "bwd", s);
-        if (int rc = hip_check(voge::launch_bwd(ta, s), "backward launch")) return rc;
-    }
-    {
-        ProfScope ps(ctx, "bwd_reduce", s);
-        if (int rc = hip_check(voge::launch_bwd_reduce(ta, s), "backward reduce launch")) return rc;
-    }
-    voge::EpiArgs ea{};
-    ea.means = means;
-    ea.covs = covs;
-    ea.rec = w.rec;
-    ea.N = N;
-    ea.C = C;
-    ea.cam = to_dev(cam);
-    ea.gM = w.gM;
-    ea.gS = w.gS;
-    ea.tileD = w.tileD;
-    ea.n_tiles = p.n_tiles;
-    ea.camP = w.camP;
-    ea.grad_means = grad_means;
-    ea.grad_covs = grad_covs;
-    ea.grad_camera = grad_camera;
-    {
-        ProfScope ps(ctx, "epilogue", s);
-        if (int rc = hip_check(voge::launch_epilogue(ea, s), "epilogue launch")) return rc;
-    }
+    const auto* src = static_cast<const unsigned char*>(workspace) + voge::OFF_STATUS;
+    if (int rc = hip_check(hipMemcpyAsync(device_status, src, sizeof(int32_t) * (size_t)n_items,
+                                          hipMemcpyDeviceToHost, s),
+                           "hipMemcpyAsync"))
+        return rc;
+    if (int rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize")) return rc;
     g_err.clear();
     return VOGE_OK;
 }

@@ -19,9 +19,17 @@ __device__ __forceinline__ double wave_sum_d(double x) {
     return x;
 }
 
-__global__ __launch_bounds__(EPI_THREADS) void k_epilogue(EpiArgs A) {
+// One thread per kernel rank of an item; a block belongs to one item.  The
+// attribute gradients, accumulated in rank order, go to the caller's buffer
+// in original order.
+__global__ __launch_bounds__(EPI_THREADS) void k_epilogue(BatchDev B) {
     __shared__ double s_red[EPI_THREADS / WAVE][12];
-    const int r = blockIdx.x * EPI_THREADS + threadIdx.x;
+    const int item = B.n_items == 1 ? 0 : B.epi_item[blockIdx.x];
+    const ItemDev& it = B.items[item];
+    const TraceArgs& A = it.t;
+    const int lb = blockIdx.x - it.epi_start;
+    const int r = lb * EPI_THREADS + threadIdx.x;
+    const bool want_cam = it.grad_camera != nullptr;
     double part[12];
 #pragma unroll
     for (int e = 0; e < 12; ++e) part[e] = 0.0;
@@ -32,20 +40,18 @@ __global__ __launch_bounds__(EPI_THREADS) void k_epilogue(EpiArgs A) {
         double M0[3], Sig[6], S0[6];
         bool ok = true;
         for (int d = 0; d < 3; ++d) {
-            M0[d] = (double)A.means[n * 3 + d];
+            M0[d] = (double)it.means[n * 3 + d];
             ok = ok && isfinite(M0[d]);
         }
         for (int e = 0; e < 6; ++e) {
-            Sig[e] = (double)A.covs[n * 6 + e];
+            Sig[e] = (double)it.covs[n * 6 + e];
             ok = ok && isfinite(Sig[e]);
         }
         ok = ok && spd_inverse6(Sig, S0);
         if (ok) {
             double R[9];
-            for (int e = 0; e < 9; ++e) R[e] = (double)A.cam.R[e];
+            for (int e = 0; e < 9; ++e) R[e] = (double)it.cam.R[e];
             const double g0 = A.gM[(size_t)r * 3], g1 = A.gM[(size_t)r * 3 + 1], g2 = A.gM[(size_t)r * 3 + 2];
-            const double* gs = nullptr;
-            (void)gs;
             double G[9];
             {
                 const float* q = A.gS + (size_t)r * 6;
@@ -76,7 +82,7 @@ __global__ __launch_bounds__(EPI_THREADS) void k_epilogue(EpiArgs A) {
             gc[3] = Y[4];
             gc[4] = Y[5] + Y[7];
             gc[5] = Y[8];
-            if (A.grad_camera) {
+            if (want_cam) {
                 // dL/dR = g M0^T + 2 G R S0
                 double RS[9];
                 for (int a = 0; a < 3; ++a)
@@ -92,10 +98,14 @@ __global__ __launch_bounds__(EPI_THREADS) void k_epilogue(EpiArgs A) {
                 part[11] = g2;
             }
         }
-        for (int d = 0; d < 3; ++d) A.grad_means[n * 3 + d] = (float)gm[d];
-        for (int e = 0; e < 6; ++e) A.grad_covs[n * 6 + e] = (float)gc[e];
+        for (int d = 0; d < 3; ++d) it.grad_means[n * 3 + d] = (float)gm[d];
+        for (int e = 0; e < 6; ++e) it.grad_covs[n * 6 + e] = (float)gc[e];
+        const int C = A.C;
+        const float* ga = A.gA + (size_t)r * C;
+        float* go = it.grad_attrs + n * C;
+        for (int c = 0; c < C; ++c) go[c] = ga[c];
     }
-    if (A.grad_camera) {
+    if (want_cam) {
         const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
 #pragma unroll
         for (int e = 0; e < 12; ++e) {
@@ -106,33 +116,35 @@ __global__ __launch_bounds__(EPI_THREADS) void k_epilogue(EpiArgs A) {
         if (threadIdx.x < 12) {
             double s = 0.0;
             for (int w = 0; w < EPI_THREADS / WAVE; ++w) s += s_red[w][threadIdx.x];
-            A.camP[(size_t)blockIdx.x * 12 + threadIdx.x] = s;
+            it.camP[(size_t)lb * 12 + threadIdx.x] = s;
         }
     }
 }
 
-// One wave per camera value: a fixed-order reduction of the per-block and
-// per-tile partials (lane-strided sums, then a shuffle tree).
+// One block per item, one wave per camera value: a fixed-order reduction of
+// the item's per-block and per-tile partials (lane-strided sums, then a
+// shuffle tree).
 constexpr int FIN_THREADS = 16 * WAVE;
 
-__global__ __launch_bounds__(FIN_THREADS) void k_cam_finalize(EpiArgs A, int nblk) {
+__global__ __launch_bounds__(FIN_THREADS) void k_cam_finalize(BatchDev B) {
+    const ItemDev& it = B.items[blockIdx.x];
+    if (it.grad_camera == nullptr) return;
     const int e = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     if (e >= 15) return;
     double s = 0.0;
     if (e < 12) {
-        for (int b = lane; b < nblk; b += WAVE) s += A.camP[(size_t)b * 12 + e];
+        for (int b = lane; b < it.n_epi; b += WAVE) s += it.camP[(size_t)b * 12 + e];
     } else {
         const int comp = (e == 12) ? 2 : (e == 13 ? 1 : 0);   // F <- z, O_x <- y, O_y <- x
-        for (int t = lane; t < A.n_tiles; t += WAVE) s += A.tileD[(size_t)t * 3 + comp];
+        for (int t = lane; t < it.t.n_tiles; t += WAVE) s += it.t.tileD[(size_t)t * 3 + comp];
     }
     s = wave_sum_d(s);
-    if (lane == 0) A.grad_camera[e] = (float)(e == 13 || e == 14 ? -s : s);
+    if (lane == 0) it.grad_camera[e] = (float)(e == 13 || e == 14 ? -s : s);
 }
 
-hipError_t launch_epilogue(const EpiArgs& a, hipStream_t s) {
-    const int nblk = (a.N + EPI_THREADS - 1) / EPI_THREADS;
-    if (nblk > 0) hipLaunchKernelGGL(k_epilogue, dim3(nblk), dim3(EPI_THREADS), 0, s, a);
-    if (a.grad_camera) hipLaunchKernelGGL(k_cam_finalize, dim3(1), dim3(FIN_THREADS), 0, s, a, nblk);
+hipError_t launch_epilogue(const BatchDev& b, int total_epi, hipStream_t s) {
+    if (total_epi > 0) hipLaunchKernelGGL(k_epilogue, dim3(total_epi), dim3(EPI_THREADS), 0, s, b);
+    if (b.n_items > 0) hipLaunchKernelGGL(k_cam_finalize, dim3(b.n_items), dim3(FIN_THREADS), 0, s, b);
     return hipGetLastError();
 }
 

@@ -33,49 +33,88 @@ __device__ __forceinline__ bool load_kernel(const float* __restrict__ means, con
     return ok;
 }
 
-__global__ void k_prep_keys(const float* __restrict__ means, const float* __restrict__ covs, int N, CamDev cam,
-                            double rad2, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                            int* __restrict__ status) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
+// Sort key of a kernel: the item in the high `ib` bits, then the top bits of
+// the depth bound's order key.  Within an item the order is by depth bucket;
+// bucket_floor gives the smallest depth bound of a bucket, which is what the
+// early exit compares against (every later kernel of the item has a bound at
+// least that large).  With ib = 0 the bucket is the bound itself.
+__device__ __forceinline__ uint32_t batch_key(uint32_t key32, int item, int ib) {
+    return ib ? (((uint32_t)item << (32 - ib)) | (key32 >> ib)) : key32;
+}
+
+__device__ __forceinline__ float bucket_floor(uint32_t key, int ib) {
+    const uint32_t ok = key << ib;            // depth prefix, low bits cleared
+    const uint32_t u = (ok & 0x80000000u) ? (ok & 0x7FFFFFFFu) : ~ok;
+    return __uint_as_float(u);
+}
+
+__device__ __forceinline__ int item_of_block(const int* __restrict__ map, int n_items) {
+    return n_items == 1 ? 0 : map[blockIdx.x];
+}
+
+__global__ __launch_bounds__(PREP_THREADS) void k_prep_keys(BatchDev B, uint32_t* __restrict__ keys,
+                                                             uint32_t* __restrict__ vals) {
+    const int item = item_of_block(B.pblk_item, B.n_items);
+    const ItemDev& it = B.items[item];
+    const int n = (blockIdx.x - it.pblk_start) * PREP_THREADS + threadIdx.x;
+    if (n >= it.t.N) return;
     double M0[3], Sig[6], S0[6];
     uint32_t key = KEY_CULLED;
-    const bool finite = load_kernel(means, covs, n, M0, Sig);
+    const bool finite = load_kernel(it.means, it.covs, n, M0, Sig);
+    int st = 0;
     if (!finite) {
-        atomicOr(status, ST_NONFINITE);
+        st = ST_NONFINITE;
     } else if (!spd_inverse6(Sig, S0)) {
-        atomicOr(status, ST_NOTSPD);
+        st = ST_NOTSPD;
     } else {
+        const CamDev& cam = it.cam;
         const double r0 = cam.R[6], r1 = cam.R[7], r2 = cam.R[8];
         const double Mz = r0 * M0[0] + r1 * M0[1] + r2 * M0[2] + (double)cam.T[2];
         const double Szz = r0 * (r0 * Sig[0] + r1 * Sig[1] + r2 * Sig[2]) +
                            r1 * (r0 * Sig[1] + r1 * Sig[3] + r2 * Sig[4]) +
                            r2 * (r0 * Sig[2] + r1 * Sig[4] + r2 * Sig[5]);
-        const double zhi = Mz + sqrt(rad2 * Szz);
-        if (zhi > 0.0) key = float_order_key(__double2float_rd(depth_bound(Mz, Szz, rad2, cam.F)));
+        const double zhi = Mz + sqrt(it.t.rad2 * Szz);
+        if (zhi > 0.0) key = float_order_key(__double2float_rd(depth_bound(Mz, Szz, it.t.rad2, cam.F)));
     }
-    keys[n] = key;
-    vals[n] = (uint32_t)n;
+    if (st) {
+        atomicOr(it.status, st);
+        atomicOr(&B.hdr->status, st);
+    }
+    keys[it.kern_start + n] = batch_key(key, item, B.item_bits);
+    vals[it.kern_start + n] = (uint32_t)n;
 }
 
-__global__ void k_prep_records(const float* __restrict__ means, const float* __restrict__ covs, int N, CamDev cam,
-                               double rad2, const uint32_t* __restrict__ skeys, const uint32_t* __restrict__ svals,
-                               CullRec* __restrict__ cull, TraceRec* __restrict__ rec, GeoRec* __restrict__ geo) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= N) return;
+// One thread per sorted position r: the item comes from the key, the
+// kernel's item-local index from the value, its item-local rank is
+// r - kern_start.
+__global__ __launch_bounds__(PREP_THREADS) void k_prep_records(BatchDev B, int total,
+                                                                const uint32_t* __restrict__ skeys,
+                                                                const uint32_t* __restrict__ svals,
+                                                                CullRec* __restrict__ cull, TraceRec* __restrict__ rec,
+                                                                GeoRec* __restrict__ geo) {
+    const int r = blockIdx.x * PREP_THREADS + threadIdx.x;
+    if (r >= total) return;
+    const int ib = B.item_bits;
+    const uint32_t key = skeys[r];
+    const int item = ib ? (int)(key >> (32 - ib)) : 0;
+    const ItemDev& it = B.items[item];
+    const uint32_t dmask = ib ? ((1u << (32 - ib)) - 1u) : 0xFFFFFFFFu;
+    const bool culled = (key & dmask) == dmask;
     const uint32_t n = svals[r];
     TraceRec tr = {};
     tr.idx = n;
-    tr.rank = (uint32_t)r;
+    tr.rank = (uint32_t)(r - it.kern_start);
     tr.tlo = INFINITY;
     CullRec cr;
     cr.i0 = 1; cr.i1 = 0; cr.j0 = 1; cr.j1 = 0;
     cr.tlo = INFINITY;
     cr.pad = 0;
     GeoRec g = {};
-    if (skeys[r] != KEY_CULLED) {
+    if (!culled) {
+        const CamDev& cam = it.cam;
+        const double rad2 = it.t.rad2;
         double M0[3], Sig[6], S0[6];
-        load_kernel(means, covs, (int)n, M0, Sig);
+        load_kernel(it.means, it.covs, (int)n, M0, Sig);
         spd_inverse6(Sig, S0);
         double R[9];
         for (int e = 0; e < 9; ++e) R[e] = (double)cam.R[e];
@@ -99,7 +138,9 @@ __global__ void k_prep_records(const float* __restrict__ means, const float* __r
         tr.B1 = w1;
         tr.B2 = w2 * F;
         tr.c = M[0] * w0 + M[1] * w1 + M[2] * w2;
-        const float tlo = __double2float_rd(depth_bound(M[2], Sc[5], rad2, F));
+        // the bucket's floor: monotone along the sorted order, and no larger
+        // than this kernel's own bound
+        const float tlo = bucket_floor(key, ib);
         tr.tlo = tlo;
         cr.tlo = tlo;
         for (int d = 0; d < 3; ++d) g.M[d] = M[d];
@@ -236,53 +277,65 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, size_t n, uint32_t v) {
     if (i < n) p[i] = v;
 }
 
-// zero three float ranges in one launch
-__global__ void k_zero3(float* __restrict__ a, size_t na, float* __restrict__ b, size_t nb, float* __restrict__ c,
-                        size_t nc) {
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < na) { a[i] = 0.f; return; }
-    i -= na;
-    if (i < nb) { b[i] = 0.f; return; }
-    i -= nb;
-    if (i < nc) c[i] = 0.f;
+// One block per item: its table record (from the arguments or already in the
+// table), its ranges of the block -> item maps, its status word.
+__global__ __launch_bounds__(256) void k_init(InitPack P, int first, int from_args, ItemDev* __restrict__ table,
+                                              int* __restrict__ tile_item, int* __restrict__ pblk_item,
+                                              int* __restrict__ epi_item, WsHeader* __restrict__ hdr,
+                                              int clear_status, int clear_header) {
+    const int b = blockIdx.x, item = first + b, tid = threadIdx.x;
+    if (from_args) {
+        static_assert(sizeof(ItemDev) % 4 == 0, "ItemDev is a whole number of words");
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(&P.it[b]);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(&table[item]);
+        for (int w = tid; w < (int)(sizeof(ItemDev) / 4); w += blockDim.x) dst[w] = src[w];
+    }
+    const ItemDev& it = from_args ? P.it[b] : table[item];
+    for (int t = tid; t < it.t.n_tiles; t += blockDim.x) tile_item[it.tile_start + t] = item;
+    for (int t = tid; t < it.n_pblk; t += blockDim.x) pblk_item[it.pblk_start + t] = item;
+    for (int t = tid; t < it.n_epi; t += blockDim.x) epi_item[it.epi_start + t] = item;
+    if (tid == 0 && clear_status) {
+        *it.status = 0;
+        if (clear_header && b == 0) hdr->status = 0;
+    }
 }
 
 // ------------------------------------------------------------- launchers
-void launch_zero3(float* a, size_t na, float* b, size_t nb, float* c, size_t nc, hipStream_t s) {
-    const size_t n = na + nb + nc;
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_zero3, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, na, b, nb, c, nc);
-}
-
 void launch_fill_u32(void* p, size_t n, uint32_t v, hipStream_t s) {
     if (n == 0) return;
     const size_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)p, n, v);
 }
 
-void launch_prep(const float* means, const float* covs, int N, const CamDev& cam, double rad2, const WsPtrs& w,
-                 hipStream_t s) {
-    if (N <= 0) return;
-    const int blocks = (N + 255) / 256;
-    hipLaunchKernelGGL(k_prep_keys, dim3(blocks), dim3(256), 0, s, means, covs, N, cam, rad2, w.keys, w.vals,
-                       &w.hdr->status);
+void launch_init(const InitPack& pack, int first, int count, bool from_args, ItemDev* table, int* tile_item,
+                 int* pblk_item, int* epi_item, WsHeader* hdr, bool clear_status, bool clear_header, hipStream_t s) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_init, dim3(count), dim3(256), 0, s, pack, first, from_args ? 1 : 0, table, tile_item,
+                       pblk_item, epi_item, hdr, clear_status ? 1 : 0, clear_header ? 1 : 0);
+}
+
+void launch_prep(const BatchDev& b, int total_pblk, int total_kern, uint32_t* keys, uint32_t* vals, uint32_t* keys2,
+                 uint32_t* vals2, uint32_t* hist, CullRec* cull, TraceRec* rec, GeoRec* geo, hipStream_t s) {
+    if (total_kern <= 0) return;
+    hipLaunchKernelGGL(k_prep_keys, dim3(total_pblk), dim3(PREP_THREADS), 0, s, b, keys, vals);
     // four stable 8-bit passes: keys/vals -> keys2/vals2 -> keys/vals -> ...
+    const int N = total_kern;
     const int nblk = sort_blocks(N);
-    uint32_t* kin = w.keys;
-    uint32_t* vin = w.vals;
-    uint32_t* kout = w.keys2;
-    uint32_t* vout = w.vals2;
+    uint32_t* kin = keys;
+    uint32_t* vin = vals;
+    uint32_t* kout = keys2;
+    uint32_t* vout = vals2;
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 8 * pass;
-        hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(SORT_THREADS), 0, s, kin, N, shift, w.hist, nblk);
-        hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, w.hist, nblk * 256);
+        hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(SORT_THREADS), 0, s, kin, N, shift, hist, nblk);
+        hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, hist, nblk * 256);
         hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(SORT_THREADS), 0, s, kin, vin, kout, vout, N, shift,
-                           w.hist, nblk);
+                           hist, nblk);
         uint32_t* t = kin; kin = kout; kout = t;
         t = vin; vin = vout; vout = t;
     }
-    hipLaunchKernelGGL(k_prep_records, dim3(blocks), dim3(256), 0, s, means, covs, N, cam, rad2, kin, vin, w.cull,
-                       w.rec, w.geo);
+    const int blocks = (N + PREP_THREADS - 1) / PREP_THREADS;
+    hipLaunchKernelGGL(k_prep_records, dim3(blocks), dim3(PREP_THREADS), 0, s, b, N, kin, vin, cull, rec, geo);
 }
 
 }  // namespace voge

@@ -401,15 +401,6 @@ size_t bwd_lds_bytes(int hcap, int KB) {
     return table > partials ? table : partials;
 }
 
-// One (pixel, kernel) pair of a tile, stored in kernel-sorted order.
-struct __align__(16) PairRec {
-    float dq, dl, da, w;   // dL/dq, dL/dl (D' units), dL/da, W
-    double l;              // depth l (D' units)
-    int pt;                // pixel within the tile (lane id)
-    int rank;              // kernel rank
-};
-static_assert(sizeof(PairRec) == 32, "PairRec is 32 bytes");
-
 constexpr int RED_CH = 8;              // attribute channels per reduction pass
 constexpr int RED_NV = 9 + RED_CH;     // values per partial sum
 
@@ -423,8 +414,7 @@ __device__ __forceinline__ void flush_values(const TraceArgs& A, int rank, const
 #pragma unroll
         for (int q = 0; q < 6; ++q) unsafeAtomicAdd(&A.gS[(size_t)rank * 6 + q], v[3 + q]);
     }
-    const size_t idx = A.rec[rank].idx;
-    for (int q = 0; q < nc; ++q) unsafeAtomicAdd(&A.grad_attrs[idx * A.C + c0 + q], v[9 + q]);
+    for (int q = 0; q < nc; ++q) unsafeAtomicAdd(&A.gA[(size_t)rank * A.C + c0 + q], v[9 + q]);
 }
 
 // Backward, pixel phase: per-pair scalars (dq, dl, da, W) into the scratch list.
@@ -569,7 +559,6 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
     const int keff = P.valid ? A.keff[P.q] : 0;
     const size_t p = (size_t)P.pi * A.W + P.pj;
     const double* pl = A.kl_l + P.q;
-    const int* pi = A.kl_i + P.q;
     float4* pbw = A.bw + P.q;
     const float* Gp = A.grad_image + p * C;
     PairRec* tile_pairs = A.pairs + (size_t)tile * TILE_THREADS * A.K;
@@ -651,7 +640,6 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
                 // table full: this pair goes straight to global memory
                 const size_t o = (size_t)k * S;
                 const int rank = A.kl_r[P.q + o];
-                const int idx = pi[o];
                 const float4 sc = pbw[o];
                 double out[9];
                 pair_chain(A.geo[rank], P.u, P.v, (double)A.F, pl[o], sc.x, sc.y, sc.z, out, gD);
@@ -659,7 +647,7 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
                 for (int e = 0; e < 3; ++e) unsafeAtomicAdd(&A.gM[(size_t)rank * 3 + e], (float)out[e]);
 #pragma unroll
                 for (int e = 0; e < 6; ++e) unsafeAtomicAdd(&A.gS[(size_t)rank * 6 + e], (float)out[3 + e]);
-                for (int c = 0; c < C; ++c) unsafeAtomicAdd(&A.grad_attrs[(size_t)idx * C + c], sc.w * Gp[c]);
+                for (int c = 0; c < C; ++c) unsafeAtomicAdd(&A.gA[(size_t)rank * C + c], sc.w * Gp[c]);
             }
         }
     }
@@ -780,29 +768,43 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
 }
 
 // ------------------------------------------------------------------ kernels
-template <int KB>
-__global__ __launch_bounds__(TILE_THREADS) void k_select(TraceArgs A) {
-    const int tile = tile_of_block();
-    select_body<KB>(A, tile);
+// A workgroup takes a tile of the group, finds the tile's item and renders
+// the item-local tile with the item's view.
+struct TileRef {
+    const TraceArgs* A;
+    int tile;
+};
+
+__device__ __forceinline__ TileRef tile_ref(const GroupDev& g) {
+    const int gt = g.tile0 + tile_of_block();
+    const int item = g.single >= 0 ? g.single : g.tile_item[gt];
+    const ItemDev& it = g.items[item];
+    return {&it.t, gt - it.tile_start};
 }
 
 template <int KB>
-__global__ __launch_bounds__(TILE_THREADS) void k_blend(TraceArgs A) {
-    const int tile = tile_of_block();
-    blend_body<KB>(A, tile);
+__global__ __launch_bounds__(TILE_THREADS) void k_select(GroupDev g) {
+    const TileRef t = tile_ref(g);
+    select_body<KB>(*t.A, t.tile);
 }
 
 template <int KB>
-__global__ __launch_bounds__(TILE_THREADS) void k_bwd_pix(TraceArgs A) {
-    const int tile = tile_of_block();
-    bwd_pix_body<KB>(A, tile);
+__global__ __launch_bounds__(TILE_THREADS) void k_blend(GroupDev g) {
+    const TileRef t = tile_ref(g);
+    blend_body<KB>(*t.A, t.tile);
 }
 
 template <int KB>
-__global__ __launch_bounds__(TILE_THREADS) void k_bwd_red(TraceArgs A, int hcap) {
+__global__ __launch_bounds__(TILE_THREADS) void k_bwd_pix(GroupDev g) {
+    const TileRef t = tile_ref(g);
+    bwd_pix_body<KB>(*t.A, t.tile);
+}
+
+template <int KB>
+__global__ __launch_bounds__(TILE_THREADS) void k_bwd_red(GroupDev g, int hcap) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int tile = tile_of_block();
-    bwd_red_body<KB>(A, hcap, tile, smem);
+    const TileRef t = tile_ref(g);
+    bwd_red_body<KB>(*t.A, hcap, t.tile, smem);
 }
 
 // Diagnostics: the device Phi on an array.
@@ -826,35 +828,36 @@ int table_capacity(int C) {
 }
 
 template <int KB>
-static hipError_t run_kb(int which, const TraceArgs& a, hipStream_t s) {
-    const int nt = a.n_tiles;
+static hipError_t run_kb(int which, const GroupDev& g, hipStream_t s) {
+    const int nt = g.n_tiles;
+    if (nt <= 0) return hipSuccess;
     if (which == 0) {
-        hipLaunchKernelGGL(k_select<KB>, dim3(nt), dim3(TILE_THREADS), 0, s, a);
+        hipLaunchKernelGGL(k_select<KB>, dim3(nt), dim3(TILE_THREADS), 0, s, g);
     } else if (which == 1) {
-        hipLaunchKernelGGL(k_blend<KB>, dim3(nt), dim3(TILE_THREADS), 0, s, a);
+        hipLaunchKernelGGL(k_blend<KB>, dim3(nt), dim3(TILE_THREADS), 0, s, g);
     } else if (which == 2) {
-        hipLaunchKernelGGL(k_bwd_pix<KB>, dim3(nt), dim3(TILE_THREADS), 0, s, a);
+        hipLaunchKernelGGL(k_bwd_pix<KB>, dim3(nt), dim3(TILE_THREADS), 0, s, g);
     } else {
-        const int hcap = table_capacity(a.C);
-        hipLaunchKernelGGL(k_bwd_red<KB>, dim3(nt), dim3(TILE_THREADS), bwd_lds_bytes(hcap, KB), s, a, hcap);
+        const int hcap = table_capacity(0);
+        hipLaunchKernelGGL(k_bwd_red<KB>, dim3(nt), dim3(TILE_THREADS), bwd_lds_bytes(hcap, KB), s, g, hcap);
     }
     return hipGetLastError();
 }
 
-static hipError_t dispatch(int which, const TraceArgs& a, hipStream_t s) {
-    switch (pick_kbuf(a.K)) {
-        case 8: return run_kb<8>(which, a, s);
-        case 16: return run_kb<16>(which, a, s);
-        case 20: return run_kb<20>(which, a, s);
-        case 32: return run_kb<32>(which, a, s);
-        default: return run_kb<64>(which, a, s);
+static hipError_t dispatch(int which, const GroupDev& g, int kb, hipStream_t s) {
+    switch (kb) {
+        case 8: return run_kb<8>(which, g, s);
+        case 16: return run_kb<16>(which, g, s);
+        case 20: return run_kb<20>(which, g, s);
+        case 32: return run_kb<32>(which, g, s);
+        default: return run_kb<64>(which, g, s);
     }
 }
 
-hipError_t launch_select(const TraceArgs& a, hipStream_t s) { return dispatch(0, a, s); }
-hipError_t launch_blend(const TraceArgs& a, hipStream_t s) { return dispatch(1, a, s); }
-hipError_t launch_bwd(const TraceArgs& a, hipStream_t s) { return dispatch(2, a, s); }
-hipError_t launch_bwd_reduce(const TraceArgs& a, hipStream_t s) { return dispatch(3, a, s); }
+hipError_t launch_select(const GroupDev& g, int kb, hipStream_t s) { return dispatch(0, g, kb, s); }
+hipError_t launch_blend(const GroupDev& g, int kb, hipStream_t s) { return dispatch(1, g, kb, s); }
+hipError_t launch_bwd(const GroupDev& g, int kb, hipStream_t s) { return dispatch(2, g, kb, s); }
+hipError_t launch_bwd_reduce(const GroupDev& g, int kb, hipStream_t s) { return dispatch(3, g, kb, s); }
 
 hipError_t launch_phi(const float* x, float* y, int n, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(k_phi, dim3((n + 255) / 256), dim3(256), 0, s, x, y, n);

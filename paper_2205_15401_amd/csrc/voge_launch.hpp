@@ -1,117 +1,162 @@
-// voge_launch.hpp -- host-side launchers of the libvoge kernels and the
-// workspace slices they use.  Internal to the library.
+// voge_launch.hpp -- host-side launchers of the libvoge kernels, the per-item
+// records they read, and the workspace slices they use.  Internal to the
+// library.
+//
+// Every call renders a batch of items (a single-camera call is a batch of
+// one).  The items' arrays are concatenated in one workspace: kernel records
+// in item order, screen tiles in item order, kept lists per item.  Each item's
+// record (ItemDev, in the workspace) holds a TraceArgs view whose pointers are
+// already offset to that item's slices, so a workgroup finds its item once and
+// then works in item-local tile and rank numbers.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "voge_internal.hpp"
 
 namespace voge {
 
-struct PairRec;
-
-// Device pointers into one caller-owned workspace (see plan_workspace).
-struct WsPtrs {
-    WsHeader* hdr;
-    uint32_t *keys, *vals, *keys2, *vals2, *hist;
-    CullRec* cull;
-    TraceRec* rec;
-    GeoRec* geo;
-    float* gM;        // [N][3] camera-space centre gradients, depth-bound order
-    float* gS;        // [N][6] camera-space symmetric inverse-covariance gradients
-    double* tileD;    // [n_tiles][3] per-tile sums of dL/dD'
-    double* camP;     // [n_epi_blocks][12] per-block camera gradient partials
-    // per-pixel kept lists, slot-major: [K][S] with S = n_tiles * 256
-    int32_t* keff;    // [S]
-    double* kl_l;     // depth l (D' units)
-    float* kl_m;      // e^q
-    float* kl_s;      // sqrt(a)
-    float* kl_T;      // transmittance T(l_k)
-    int32_t* kl_r;    // rank (depth-bound order)
-    int32_t* kl_i;    // original kernel index
-    float4* bw;       // backward scratch: per-slot sums over the pair loop
-    PairRec* pairs;   // backward scratch: per-tile pair records, kernel-sorted [tiles][256 * K]
-};
-
-struct Plan {
-    size_t off_keys, off_vals, off_keys2, off_vals2, off_hist, off_cull, off_rec, off_geo;
-    size_t off_keff, off_kl_l, off_kl_m, off_kl_s, off_kl_T, off_kl_r, off_kl_i;
-    size_t off_gM, off_gS, off_tileD, off_camP, off_bw, off_pairs;
-    size_t fwd_bytes, bwd_bytes;
-    size_t S;          // list stride: n_tiles * 256
-    int n_tiles, n_epi_blocks, sort_blocks;
-};
-
-Plan plan_workspace(int N, int C, int H, int W, int K);
-WsPtrs carve(void* base, const Plan& p, bool with_backward);
-int sort_blocks(int N);
-
 constexpr int EPI_THREADS = 256;
+constexpr int PREP_THREADS = 256;
+constexpr int MAX_BATCH = 4096;          // items per call
+constexpr int INIT_ITEMS = 4;            // item records carried by one init launch's arguments
 
-void launch_fill_u32(void* p, size_t n, uint32_t v, hipStream_t s);
-void launch_zero3(float* a, size_t na, float* b, size_t nb, float* c, size_t nc, hipStream_t s);
-void launch_prep(const float* means, const float* covs, int N, const CamDev& cam, double rad2, const WsPtrs& w,
-                 hipStream_t s);
-
+// One item's view of the workspace, as the trace kernels see it.  Ranks and
+// tiles are item-local; every pointer is offset to the item's slice.
 struct TraceArgs {
-    WsHeader* hdr;             // status word and tile queue
-    int n_cu;                  // compute units (persistent grid size)
     const CullRec* cull;
     const TraceRec* rec;
     const GeoRec* geo;
     int N, H, W, K, C;
     int n_tiles;
-    size_t S;                  // list stride
+    size_t S;                  // list stride: n_tiles * 256
     float F, cx, cy;
     double rad2;               // 2 ln(1/eta) = -2 ln(eta)
     const float* attrs;
-    // kept lists
-    int32_t* keff;
-    double* kl_l;
-    float* kl_m;
-    float* kl_s;
-    float* kl_T;
-    int32_t* kl_r;
-    int32_t* kl_i;
-    // forward outputs
+    // kept lists, slot-major [K][S]
+    int32_t* keff;             // [S]
+    double* kl_l;              // depth l (D' units)
+    float* kl_m;               // e^q
+    float* kl_s;               // sqrt(a)
+    float* kl_T;               // transmittance T(l_k)
+    int32_t* kl_r;             // rank (depth-bound order)
+    int32_t* kl_i;             // original kernel index
+    // forward outputs (caller's; any may be null except where stated)
     float* image;
     float* wsum;
     int32_t* kept;
-    // backward inputs / outputs
+    // backward
     const float* grad_image;
-    float* grad_attrs;
-    float* gM;
-    float* gS;
-    double* tileD;
-    float4* bw;
-    PairRec* pairs;
+    float* gA;                 // [N][C] attribute gradients in rank order
+    float* gM;                 // [N][3] camera-space centre gradients, rank order
+    float* gS;                 // [N][6] camera-space inverse-covariance gradients
+    double* tileD;             // [n_tiles][3] per-tile sums of dL/dD'
+    float4* bw;                // per-slot pair-loop sums, slot-major like the lists
+    PairRec* pairs;            // per-tile pair records, kernel-sorted [tiles][256 * K]
 };
 
-int pick_kbuf(int K);        // compiled K-buffer depth for a requested K
-int table_capacity(int C);   // entries of the per-tile gradient table
-size_t bwd_lds_bytes(int hcap, int KB);
-hipError_t launch_select(const TraceArgs& a, hipStream_t s);
-hipError_t launch_blend(const TraceArgs& a, hipStream_t s);
-hipError_t launch_bwd(const TraceArgs& a, hipStream_t s);          // pixel phase
-hipError_t launch_bwd_reduce(const TraceArgs& a, hipStream_t s);   // tile reduction
-hipError_t launch_phi(const float* x, float* y, int n, hipStream_t s);
-
-struct EpiArgs {
+// Per-item record in the workspace.
+struct ItemDev {
+    TraceArgs t;
     const float* means;
     const float* covs;
-    const TraceRec* rec;
-    int N, C;
-    CamDev cam;
-    const float* gM;
-    const float* gS;
-    const double* tileD;
-    int n_tiles;
-    double* camP;
-    float* grad_means;
+    float* grad_means;         // caller's outputs
     float* grad_covs;
+    float* grad_attrs;
     float* grad_camera;        // 15 floats or null
+    double* camP;              // [n_epi][12] per-block camera partials
+    int* status;               // this item's device status word
+    CamDev cam;
+    int kern_start;            // first global kernel slot
+    int tile_start;            // first global tile
+    int pblk_start, n_pblk;    // prep blocks (PREP_THREADS kernels each)
+    int epi_start, n_epi;      // epilogue blocks (EPI_THREADS kernels each)
 };
-hipError_t launch_epilogue(const EpiArgs& a, hipStream_t s);
+
+// Batch-wide arguments of the per-kernel launches.
+struct BatchDev {
+    const ItemDev* items;      // [n_items], table order
+    int n_items;
+    const int* pblk_item;      // [total prep blocks] -> item
+    const int* epi_item;       // [total epilogue blocks] -> item
+    int item_bits;             // high bits of a sort key that hold the item
+    WsHeader* hdr;
+};
+
+// One launch over the tiles of a group of items that share a K-buffer depth.
+struct GroupDev {
+    const ItemDev* items;
+    const int* tile_item;      // [total tiles] -> item
+    int single;                // the group's item when it has only one, else -1
+    int tile0, n_tiles;        // the group's global tiles
+};
+
+// Host-side plan of a batch: sizes, table order and workspace offsets.
+struct ItemShape {
+    int N, C, H, W, K;
+};
+
+struct ItemPlan {
+    int caller;                // index in the caller's array
+    int kb;                    // K-buffer depth
+    ItemShape s;
+    int n_tiles;
+    size_t S;
+    int kern_start, tile_start, pblk_start, n_pblk, epi_start, n_epi;
+    size_t list_off;           // element offset of the kept lists
+    size_t attr_off;           // element offset of the attribute gradients
+};
+
+struct GroupPlan {
+    int kb;
+    int first_item, n_items;
+    int tile0, n_tiles;
+};
+
+struct BatchPlan {
+    std::vector<ItemPlan> items;     // table order (grouped by K-buffer depth)
+    std::vector<GroupPlan> groups;
+    int total_kern = 0, total_tiles = 0, total_pblk = 0, total_epi = 0;
+    size_t total_list = 0, total_attr = 0;
+    int item_bits = 0, sort_blocks = 0;
+    size_t off_items, off_tile_item, off_pblk_item, off_epi_item;
+    size_t off_keys, off_vals, off_keys2, off_vals2, off_hist, off_cull, off_rec, off_geo;
+    size_t off_keff, off_kl_l, off_kl_m, off_kl_s, off_kl_T, off_kl_r, off_kl_i;
+    size_t off_grads, off_tileD, off_camP, off_bw, off_pairs;
+    size_t fwd_bytes, bwd_bytes;
+};
+
+// Fixed workspace prefix: header, then one status word per caller item.
+constexpr size_t OFF_STATUS = 256;
+constexpr size_t PREFIX_BYTES = OFF_STATUS + sizeof(int) * MAX_BATCH;
+
+int pick_kbuf(int K);        // compiled K-buffer depth for a requested K
+int sort_blocks(int N);
+int table_capacity(int C);   // entries of the per-tile gradient table
+size_t bwd_lds_bytes(int hcap, int KB);
+
+// Items first .. first+count-1: writes their table records from the launch
+// arguments (from_args, count <= INIT_ITEMS) or reads them from the table,
+// fills the block -> item maps and (clear_status) clears their status words
+// and, with clear_header, the header's.
+struct InitPack {
+    ItemDev it[INIT_ITEMS];
+};
+void launch_init(const InitPack& pack, int first, int count, bool from_args, ItemDev* table, int* tile_item,
+                 int* pblk_item, int* epi_item, WsHeader* hdr, bool clear_status, bool clear_header, hipStream_t s);
+
+void launch_fill_u32(void* p, size_t n, uint32_t v, hipStream_t s);
+void launch_prep(const BatchDev& b, int total_pblk, int total_kern, uint32_t* keys, uint32_t* vals, uint32_t* keys2,
+                 uint32_t* vals2, uint32_t* hist, CullRec* cull, TraceRec* rec, GeoRec* geo, hipStream_t s);
+
+hipError_t launch_select(const GroupDev& g, int kb, hipStream_t s);
+hipError_t launch_blend(const GroupDev& g, int kb, hipStream_t s);
+hipError_t launch_bwd(const GroupDev& g, int kb, hipStream_t s);          // pixel phase
+hipError_t launch_bwd_reduce(const GroupDev& g, int kb, hipStream_t s);   // tile reduction
+hipError_t launch_phi(const float* x, float* y, int n, hipStream_t s);
+hipError_t launch_epilogue(const BatchDev& b, int total_epi, hipStream_t s);
 
 }  // namespace voge

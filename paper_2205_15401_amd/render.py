@@ -191,3 +191,80 @@ def render(means: torch.Tensor, covs: torch.Tensor, attrs: torch.Tensor,
     else:
         cam_vec = camera
     return _Render.apply(means, covs, attrs, cam_vec, height, width, K, eta)
+
+
+class Batch:
+    """A fixed batch of renders: many cameras and scenes in one call of
+    ``voge_render_batch``, with every output and the workspace allocated once.
+
+    ``scenes`` is a list of (means [N,3], covs [N,6], attrs [N,C]) device
+    tensors (one entry may serve many items), ``items`` a list of
+    (scene index, VogeCamera, K, eta).  ``run`` renders all items; outputs
+    live in ``images``, ``wsums``, ``kepts`` and, with a backward, in
+    ``grad_means``, ``grad_covs``, ``grad_attrs`` and ``grad_cameras``
+    (per item; gradients are per item, not summed over items of one scene).
+    """
+
+    def __init__(self, scenes, items, device: torch.device, backward: bool = False, with_wsum: bool = False,
+                 with_kept: bool = False, with_camera: bool = False):
+        for m, c, a in scenes:
+            _check_inputs(m, c, a)
+        self.device = device
+        self.scenes = scenes
+        self.n = len(items)
+        if not 1 <= self.n <= nat.VOGE_MAX_BATCH:
+            raise ValueError(f"a batch holds 1 to {nat.VOGE_MAX_BATCH} items")
+        self.backward = backward
+        self.arr = (nat.VogeItem * self.n)()
+        self.images, self.wsums, self.kepts = [], [], []
+        self.grad_images, self.grad_means, self.grad_covs, self.grad_attrs, self.grad_cameras = [], [], [], [], []
+        self.scene_of = []
+        f32 = dict(dtype=torch.float32, device=device)
+        for i, (si, cam, K, eta) in enumerate(items):
+            m, c, a = scenes[si]
+            N, C, H, W = m.shape[0], a.shape[1], cam.height, cam.width
+            it = self.arr[i]
+            it.means, it.covs, it.attrs = _ptr(m), _ptr(c), _ptr(a)
+            it.N, it.C = N, C
+            it.camera = cam
+            it.params = params_struct(K, eta)
+            img = torch.empty((H, W, C), **f32)
+            self.images.append(img)
+            it.image = _ptr(img)
+            if with_wsum:
+                self.wsums.append(torch.empty((H, W), **f32))
+                it.wsum = _ptr(self.wsums[-1])
+            if with_kept:
+                self.kepts.append(torch.empty((H, W, K), dtype=torch.int32, device=device))
+                it.kept = _ptr(self.kepts[-1])
+            if backward:
+                g = torch.zeros((H, W, C), **f32)
+                self.grad_images.append(g)
+                it.grad_image = _ptr(g)
+                for lst, shape in ((self.grad_means, (N, 3)), (self.grad_covs, (N, 6)), (self.grad_attrs, (N, C))):
+                    lst.append(torch.empty(shape, **f32))
+                it.grad_means, it.grad_covs, it.grad_attrs = (_ptr(self.grad_means[-1]), _ptr(self.grad_covs[-1]),
+                                                              _ptr(self.grad_attrs[-1]))
+                if with_camera:
+                    self.grad_cameras.append(torch.empty(15, **f32))
+                    it.grad_camera = _ptr(self.grad_cameras[-1])
+            self.scene_of.append(si)
+        self.ws_bytes = nat.voge_batch_workspace_size(self.arr, backward)
+        self.workspace = new_workspace(self.ws_bytes, device)
+
+    def set_grad_image(self, i: int, g: torch.Tensor) -> None:
+        self.grad_images[i].copy_(g)
+
+    def run(self, forward: bool = True, backward: bool = False, reuse: bool = False, graph: bool = False,
+            stream: Optional[int] = None) -> None:
+        """One call of voge_render_batch on ``stream`` (default: torch's current stream)."""
+        flags = (nat.VOGE_FORWARD if forward else 0) | (nat.VOGE_BACKWARD if backward else 0)
+        flags |= (nat.VOGE_REUSE_PREP if reuse else 0) | (nat.VOGE_GRAPH if graph else 0)
+        if backward and not self.backward:
+            raise ValueError("this batch was built without a backward")
+        s = _stream(self.device) if stream is None else stream
+        nat.voge_render_batch(context(self.device), self.arr, flags, _ptr(self.workspace), self.ws_bytes, s)
+
+    def status(self):
+        """Per-item device status words (synchronises)."""
+        return nat.voge_batch_status(_ptr(self.workspace), self.n, _stream(self.device))

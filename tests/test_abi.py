@@ -5,6 +5,7 @@ import ctypes
 import glob
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -43,7 +44,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_version(lib):
-    assert nat.voge_version() == 10000
+    assert nat.voge_version() == 10100
 
 
 def cam(h=64, w=64, f=64.0):
@@ -105,3 +106,69 @@ def test_bad_eta_is_rejected_before_any_device_work(lib):
             nat.voge_render_forward(fake_ctx, None, None, None, 0, 3, cam(), par(20, eta), 1, None, None, 256,
                                     1 << 20, None)
         assert e.value.code == nat.VOGE_EINVAL
+
+
+def item(N=100, C=3, h=64, w=64, K=20, eta=0.01, image=1, grads=False):
+    it = nat.VogeItem()
+    it.means = it.covs = it.attrs = 256 if N > 0 else None
+    it.N, it.C = N, C
+    it.camera = cam(h, w, float(w))
+    it.params = par(K, eta)
+    it.image = image
+    if grads:
+        it.grad_image = it.grad_means = it.grad_covs = it.grad_attrs = 256
+    return it
+
+
+def test_item_struct_matches_the_header(tmp_path):
+    """The ctypes mirror of voge_item_t has the C compiler's size and offsets."""
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "voge.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(voge_item_t),'
+                   ' offsetof(voge_item_t, camera), offsetof(voge_item_t, params),'
+                   ' offsetof(voge_item_t, image), offsetof(voge_item_t, grad_camera)); return 0;}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    I = nat.VogeItem
+    assert got == [ctypes.sizeof(I), I.camera.offset, I.params.offset, I.image.offset, I.grad_camera.offset]
+
+
+def test_batch_workspace_is_no_larger_than_separate_workspaces(lib):
+    a, b = item(100, 3, 64, 64, 8), item(5000, 16, 256, 128, 32)
+    for bwd in (False, True):
+        sa = nat.voge_batch_workspace_size([a], bwd)
+        sb = nat.voge_batch_workspace_size([b], bwd)
+        sab = nat.voge_batch_workspace_size([a, b], bwd)
+        assert max(sa, sb) < sab <= sa + sb
+        # a single item sizes like the single-camera call
+        assert sa == nat.voge_workspace_size(100, 3, cam(64, 64, 64.0), par(8), bwd)
+    assert nat.voge_batch_workspace_size([a, b], False) < nat.voge_batch_workspace_size([a, b], True)
+
+
+def test_batch_rejects_bad_arguments_on_the_host(lib):
+    fake_ctx = ctypes.c_void_p(1).value
+    ok = [item(), item(50, 4, 32, 48, 8)]
+
+    def rejected(items, flags, ws=256, stream=None):
+        with pytest.raises(nat.VogeError) as e:
+            nat.voge_render_batch(fake_ctx, items, flags, ws, 1 << 30, stream)
+        assert e.value.code == nat.VOGE_EINVAL
+        return nat.voge_last_error()
+
+    rejected(ok, 0)                                                     # neither forward nor backward
+    rejected(ok, 64)                                                    # unknown flag
+    rejected(ok, nat.VOGE_FORWARD | nat.VOGE_REUSE_PREP)
+    rejected(ok, nat.VOGE_FORWARD | nat.VOGE_GRAPH)                     # graph mode on the null stream
+    rejected(ok, nat.VOGE_FORWARD, ws=0)
+    rejected(ok, nat.VOGE_FORWARD, ws=300)                              # misaligned workspace
+    assert "item 1" in rejected([item(), item(image=None)], nat.VOGE_FORWARD)
+    assert "item 0" in rejected([item(grads=False)], nat.VOGE_BACKWARD)
+    assert "item 1" in rejected([item(), item(K=65)], nat.VOGE_FORWARD)
+    assert "item 0" in rejected([item(eta=1.5)], nat.VOGE_FORWARD)
+    with pytest.raises(nat.VogeError):
+        nat.voge_batch_workspace_size([], False)
+    with pytest.raises(nat.VogeError):
+        nat.voge_batch_status(256, 0, None)
+    with pytest.raises(nat.VogeError):
+        nat.voge_batch_status(256, nat.VOGE_MAX_BATCH + 1, None)
