@@ -222,7 +222,7 @@ BatchPlan plan_batch(const ItemShape* shapes, int n) {
     p.off_vals = take(4 * nk);
     p.off_keys2 = take(4 * nk);
     p.off_vals2 = take(4 * nk);
-    p.off_hist = take(4 * 256 * (size_t)p.sort_blocks);
+    p.off_hist = take(4 * 256 * ((size_t)p.sort_blocks + 1));     // block counts per digit, then digit totals
     p.off_cull = take(sizeof(CullRec) * nk);
     p.off_rec = take(sizeof(TraceRec) * nk);
     p.off_geo = take(sizeof(GeoRec) * nk);

@@ -25,7 +25,7 @@ __device__ __forceinline__ double wave_sum_d(double x) {
 __global__ __launch_bounds__(EPI_THREADS) void k_epilogue(BatchDev B) {
     __shared__ double s_red[EPI_THREADS / WAVE][12];
     const int item = B.n_items == 1 ? 0 : B.epi_item[blockIdx.x];
-    const ItemDev& it = B.items[item];
+    const ItemDev it = B.items[item];     // a copy, read before any store
     const TraceArgs& A = it.t;
     const int lb = blockIdx.x - it.epi_start;
     const int r = lb * EPI_THREADS + threadIdx.x;

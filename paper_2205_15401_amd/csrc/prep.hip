@@ -202,46 +202,71 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const uint32_t* __re
     hist[(size_t)tid * nblk + blockIdx.x] = cnt[tid];
 }
 
-// exclusive scan of n counters, one block of 1024 threads: each thread scans
-// a contiguous run serially, then the run totals are scanned in LDS
-__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t* __restrict__ hist, int n) {
-    __shared__ uint32_t buf[1024];
+// Per digit d (one workgroup each): exclusive scan of the block counts
+// hist[d][0..nblk) in place, and the digit's total in tot[d].
+constexpr int SCAN_THREADS = 256;
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_sort_scan(uint32_t* __restrict__ hist, uint32_t* __restrict__ tot,
+                                                             int nblk) {
+    __shared__ uint32_t buf[SCAN_THREADS];
     const int tid = threadIdx.x;
-    const int per = (n + 1023) / 1024;
-    const int b0 = tid * per;
-    uint32_t run = 0;
-    for (int j = 0; j < per; ++j)
-        if (b0 + j < n) run += hist[b0 + j];
-    buf[tid] = run;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t y = tid >= off ? buf[tid - off] : 0u;
-        __syncthreads();
-        buf[tid] += y;
-        __syncthreads();
-    }
-    uint32_t base = buf[tid] - run;
-    for (int j = 0; j < per; ++j) {
-        if (b0 + j < n) {
-            const uint32_t x = hist[b0 + j];
-            hist[b0 + j] = base;
-            base += x;
+    uint32_t* h = hist + (size_t)blockIdx.x * nblk;
+    uint32_t carry = 0;
+    for (int c0 = 0; c0 < nblk; c0 += SCAN_THREADS * 8) {
+        // each lane owns 8 consecutive counts of this chunk
+        const int b0 = c0 + tid * 8;
+        uint32_t v[8];
+        uint32_t run = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            v[j] = b0 + j < nblk ? h[b0 + j] : 0u;
+            run += v[j];
         }
+        buf[tid] = run;
+        __syncthreads();
+        for (int off = 1; off < SCAN_THREADS; off <<= 1) {
+            const uint32_t y = tid >= off ? buf[tid - off] : 0u;
+            __syncthreads();
+            buf[tid] += y;
+            __syncthreads();
+        }
+        uint32_t base = carry + buf[tid] - run;
+        const uint32_t chunk_total = buf[SCAN_THREADS - 1];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (b0 + j < nblk) h[b0 + j] = base;
+            base += v[j];
+        }
+        carry += chunk_total;
+        __syncthreads();
     }
+    if (tid == 0) tot[blockIdx.x] = carry;
 }
 
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(const uint32_t* __restrict__ kin,
                                                                 const uint32_t* __restrict__ vin,
                                                                 uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                                 int N, int shift, const uint32_t* __restrict__ hist,
-                                                                int nblk) {
+                                                                const uint32_t* __restrict__ tot, int nblk) {
+    static_assert(SORT_THREADS == 256, "one lane per digit");
     __shared__ uint32_t offs[256];
     __shared__ uint32_t wcnt[SORT_THREADS / WAVE][256];
-    const int tid = threadIdx.x, wave = tid / WAVE, lane = tid % WAVE;
-    offs[tid] = hist[(size_t)tid * nblk + blockIdx.x];
+    const int tid = threadIdx.x, wave = tid / WAVE;
+    // digit bases: exclusive scan of the digit totals
+    const uint32_t t = tot[tid];
+    offs[tid] = t;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint32_t y = tid >= off ? offs[tid - off] : 0u;
+        __syncthreads();
+        offs[tid] += y;
+        __syncthreads();
+    }
+    const uint32_t dbase = offs[tid] - t;
+    __syncthreads();
+    offs[tid] = dbase + hist[(size_t)tid * nblk + blockIdx.x];
     const int base = blockIdx.x * SORT_TILE;
     const uint64_t lt = lanemask_lt();
-    (void)lane;
     for (int it = 0; it < SORT_ROUNDS; ++it) {
         const int i = base + it * SORT_THREADS + tid;
         const bool valid = i < N;
@@ -328,9 +353,10 @@ void launch_prep(const BatchDev& b, int total_pblk, int total_kern, uint32_t* ke
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 8 * pass;
         hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(SORT_THREADS), 0, s, kin, N, shift, hist, nblk);
-        hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, hist, nblk * 256);
+        hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(SCAN_THREADS), 0, s, hist, hist + (size_t)256 * nblk,
+                           nblk);
         hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(SORT_THREADS), 0, s, kin, vin, kout, vout, N, shift,
-                           hist, nblk);
+                           hist, hist + (size_t)256 * nblk, nblk);
         uint32_t* t = kin; kin = kout; kout = t;
         t = vin; vin = vout; vout = t;
     }

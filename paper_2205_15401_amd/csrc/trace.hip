@@ -769,42 +769,44 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
 
 // ------------------------------------------------------------------ kernels
 // A workgroup takes a tile of the group, finds the tile's item and renders
-// the item-local tile with the item's view.
-struct TileRef {
-    const TraceArgs* A;
-    int tile;
-};
-
-__device__ __forceinline__ TileRef tile_ref(const GroupDev& g) {
+// the item-local tile with a copy of the item's view.  The copy is read
+// before the kernel's first store, so the compiler keeps the fields in scalar
+// registers instead of re-reading the table after each store.
+__device__ __forceinline__ TraceArgs item_view(const GroupDev& g, int& tile) {
     const int gt = g.tile0 + tile_of_block();
     const int item = g.single >= 0 ? g.single : g.tile_item[gt];
-    const ItemDev& it = g.items[item];
-    return {&it.t, gt - it.tile_start};
+    const ItemDev* it = g.items + item;
+    tile = gt - it->tile_start;
+    return it->t;
 }
 
 template <int KB>
 __global__ __launch_bounds__(TILE_THREADS) void k_select(GroupDev g) {
-    const TileRef t = tile_ref(g);
-    select_body<KB>(*t.A, t.tile);
+    int tile;
+    const TraceArgs A = item_view(g, tile);
+    select_body<KB>(A, tile);
 }
 
 template <int KB>
 __global__ __launch_bounds__(TILE_THREADS) void k_blend(GroupDev g) {
-    const TileRef t = tile_ref(g);
-    blend_body<KB>(*t.A, t.tile);
+    int tile;
+    const TraceArgs A = item_view(g, tile);
+    blend_body<KB>(A, tile);
 }
 
 template <int KB>
 __global__ __launch_bounds__(TILE_THREADS) void k_bwd_pix(GroupDev g) {
-    const TileRef t = tile_ref(g);
-    bwd_pix_body<KB>(*t.A, t.tile);
+    int tile;
+    const TraceArgs A = item_view(g, tile);
+    bwd_pix_body<KB>(A, tile);
 }
 
 template <int KB>
 __global__ __launch_bounds__(TILE_THREADS) void k_bwd_red(GroupDev g, int hcap) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const TileRef t = tile_ref(g);
-    bwd_red_body<KB>(*t.A, hcap, t.tile, smem);
+    int tile;
+    const TraceArgs A = item_view(g, tile);
+    bwd_red_body<KB>(A, hcap, tile, smem);
 }
 
 // Diagnostics: the device Phi on an array.
