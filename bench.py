@@ -11,7 +11,10 @@ input already resident in device memory:
   per-call  256 voge_render_forward + voge_render_backward pairs per step
 
 and, as context, the single 512x512 image of the 10,000-kernel torus
-(16 channels) per call.  Prints ONE JSON line on stdout:
+(16 channels) per call, and the serving loop on a request mix (resident
+scenes of 10k-200k kernels, 128^2-1024^2 images, half gradient requests,
+Poisson arrivals at a fraction of the one-at-a-time capacity).  Prints ONE
+JSON line on stdout:
 
   value         Mrays/s of the batched forward + backward
   latency_ms    p50 / p99 of the batched step (one request = one batch)
@@ -281,6 +284,74 @@ def bench_torus(args, torch, dev):
             "latency_ms": {"p50": pct(per, 50), "p99": pct(per, 99)}}
 
 
+def bench_serving(args, torch, dev):
+    """Serving: 6 resident scenes (10k-200k kernels), requests of 128^2 to
+    1024^2 from random poses, K = 20, half of them gradient requests.  The
+    per-call capacity (requests served one at a time, back to back) sets the
+    Poisson arrival rate; the continuous-batching server and a one-at-a-time
+    server then serve the same arrival trace."""
+    import numpy as np
+    from paper_2205_15401_amd import scenes as S
+    from paper_2205_15401_amd.serving import GpuExecutor, Request, Server, latency_stats, serve_trace
+
+    scenes = S.serving_scenes()
+    dsc = [tuple(torch.from_numpy(x).to(dev) for x in (sc.means, sc.covs, sc.attrs)) for sc in scenes]
+    n_cap, n_warm, n_timed = args.serving_capacity_requests, args.serving_warmup, args.serving_requests
+    desc = S.serving_requests(6, n_cap + n_warm + n_timed, len(scenes))
+    grads = {}
+    gen = torch.Generator(device=dev)
+    for i, d in enumerate(desc):
+        if d["backward"]:
+            gen.manual_seed(d["grad_seed"])
+            h, w = d["camera"].height, d["camera"].width
+            grads[i] = torch.randn((h, w, 3), generator=gen, device=dev)
+    torch.cuda.synchronize()
+
+    def make(idx, arrivals):
+        return [Request(scene=desc[i]["scene"], camera=desc[i]["camera"], backward=desc[i]["backward"],
+                        grad_image=grads.get(i), arrival=a) for i, a in zip(idx, arrivals)]
+
+    budget = int(args.serving_budget_gb * (1 << 30))
+    # capacity: one request at a time, all queued at once
+    one = GpuExecutor(dsc, dev, n_slots=1)
+    warm = make(range(min(20, n_cap)), [0.0] * min(20, n_cap))
+    serve_trace(Server(one, budget, max_batch_items=1), warm)
+    cap_reqs = make(range(n_cap), [0.0] * n_cap)
+    t_cap = serve_trace(Server(one, budget, max_batch_items=1), cap_reqs)
+    capacity = n_cap / t_cap
+    rays_cap = sum(r.rays for r in cap_reqs) / t_cap
+    log(f"[bench] serving capacity one at a time: {capacity:.1f} req/s, {rays_cap / 1e6:.1f} Mrays/s")
+    out = {"scenes": [sc.n for sc in scenes], "image_sizes": [128, 256, 512, 1024], "backward_fraction": 0.5,
+           "K": 20, "budget_gb": args.serving_budget_gb, "per_call_capacity_req_s": round(capacity, 2),
+           "per_call_capacity_mrays_s": round(rays_cap / 1e6, 3), "loads": []}
+    rng = np.random.default_rng(8)
+    idx = list(range(n_cap, n_cap + n_warm + n_timed))
+    for load in args.serving_loads:
+        lam = load * capacity
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, len(idx)))
+        res = {"load": load, "offered_req_s": round(lam, 2)}
+        for name, ex, items in (("batched", GpuExecutor(dsc, dev, n_slots=2), args.serving_batch_items),
+                                ("one_at_a_time", one, 1)):
+            reqs = make(idx, arrivals)
+            srv = Server(ex, budget, max_batch_items=items)
+            elapsed = serve_trace(srv, reqs)
+            timed = reqs[n_warm:]
+            bad = [r for r in reqs if r.error or r.status]
+            if bad:
+                log(f"[bench] serving {name}: {len(bad)} requests failed: {bad[0].error} status {bad[0].status}")
+            span = max(r.done for r in timed) - min(r.arrival for r in timed)
+            st = latency_stats(timed)
+            res[name] = {"p50_ms": st.get("p50_ms"), "p99_ms": st.get("p99_ms"), "mean_ms": st.get("mean_ms"),
+                         "delivered_req_s": round(len(timed) / span, 2),
+                         "delivered_mrays_s": round(sum(r.rays for r in timed) / span / 1e6, 3),
+                         "batches": srv.batches, "peak_transient_gb": round(srv.peak_bytes / (1 << 30), 3)}
+            log(f"[bench] serving load {load} {name}: p50 {st.get('p50_ms')} ms, p99 {st.get('p99_ms')} ms, "
+                f"{res[name]['delivered_mrays_s']} Mrays/s, {srv.batches} batches")
+        out["loads"].append(res)
+    out["requests"] = {"capacity": n_cap, "warmup": n_warm, "timed": n_timed}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -290,6 +361,12 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--torus-steps", type=int, default=50, help="timed steps of the single 512x512 image")
     ap.add_argument("--cpu-sample", type=int, default=262144, help="rays for the oracle baseline (0 = skip)")
+    ap.add_argument("--serving-requests", type=int, default=600, help="timed requests per load (0 = skip serving)")
+    ap.add_argument("--serving-warmup", type=int, default=100)
+    ap.add_argument("--serving-capacity-requests", type=int, default=200)
+    ap.add_argument("--serving-loads", type=lambda t: [float(x) for x in t.split(",")], default=[0.7])
+    ap.add_argument("--serving-batch-items", type=int, default=64)
+    ap.add_argument("--serving-budget-gb", type=float, default=64.0)
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="after timing, copy this many bytes device-to-device once (a plain copy kernel of "
                          "known size that scales the HBM byte counters of a profile)")
@@ -308,6 +385,7 @@ def main():
     dev = torch.device("cuda:0")
     r = bench_poses(args, torch, dev)
     single = bench_torus(args, torch, dev) if args.torus_steps > 0 else None
+    serving = bench_serving(args, torch, dev) if args.serving_requests > 0 else None
     if args.calibrate_copy > 0:
         n4 = args.calibrate_copy // 4
         src = torch.ones(n4, dtype=torch.float32, device=dev)
@@ -355,6 +433,7 @@ def main():
                      "render_latency_ms": {"p50": pct(r["per_render"], 50), "p99": pct(r["per_render"], 99)}},
         "batched_vs_per_call": round(r["eager_value"] / r["per_call_value"], 3),
         "single_image": single,
+        "serving": serving,
         "phases_us": {k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in r["phases"].items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
