@@ -148,12 +148,17 @@ __device__ __forceinline__ int wave_max_keff(int keff) {
 template <int KB>
 __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
     __shared__ StagedRec s_rec[TILE_THREADS];
+    __shared__ uint8_t s_wl[TILE_THREADS / WAVE][TILE_THREADS];   // per-wave candidate lists, depth order
     __shared__ int s_wcnt[TILE_THREADS / WAVE];
-    const int tid = threadIdx.x, wave = tid / WAVE, lane = tid % WAVE;
+    const int tid = threadIdx.x, lane = tid % WAVE;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);   // uniform in the wave
     const int ntx = (A.W + TILE - 1) / TILE;
     const PixelCtx P = pixel_of(tile, ntx, A.H, A.W, A.cx, A.cy);
     const int ti0 = (tile / ntx) * TILE, tj0 = (tile % ntx) * TILE;
     const int ti1 = ti0 + TILE - 1, tj1 = tj0 + TILE - 1;
+    // this wave's 8x8 block
+    const int bi0 = ti0 + (wave >> 1) * 8, bj0 = tj0 + (wave & 1) * 8;
+    const uint64_t lt = lanemask_lt();
 
     uint64_t key[KB];
 #pragma unroll
@@ -179,7 +184,7 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
         }
         if (hit) {
             const TraceRec& g = A.rec[r];
-            StagedRec& d = s_rec[off + __popcll(m & lanemask_lt())];
+            StagedRec& d = s_rec[off + __popcll(m & lt)];
             d.A0 = g.A0; d.A1 = g.A1; d.A2 = g.A2; d.A3 = g.A3; d.A4 = g.A4; d.A5 = g.A5;
             d.B0 = g.B0; d.B1 = g.B1; d.B2 = g.B2; d.c = g.c;
             d.tlo = c.tlo;
@@ -187,9 +192,26 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
             d.i0 = c.i0; d.i1 = c.i1; d.j0 = c.j0; d.j1 = c.j1;
         }
         __syncthreads();
-        for (int ci = 0; ci < total; ++ci) {
+        // the staged candidates whose screen box meets this wave's block, in
+        // order (a wave-local compaction; only this wave reads its list)
+        int mine = 0;
+        for (int s0 = 0; s0 < total; s0 += WAVE) {
+            const int sidx = s0 + lane;
+            bool h = false;
+            if (sidx < total) {
+                const StagedRec& R = s_rec[sidx];
+                h = R.i0 <= bi0 + 7 && R.i1 >= bi0 && R.j0 <= bj0 + 7 && R.j1 >= bj0;
+            }
+            const uint64_t mm = __ballot(h);
+            if (h) s_wl[wave][mine + __popcll(mm & lt)] = (uint8_t)sidx;
+            mine += __popcll(mm);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int ci = 0; ci < mine; ++ci) {
             if (__all(done)) break;
-            const StagedRec& R = s_rec[ci];
+            const StagedRec& R = s_rec[s_wl[wave][ci]];
             if (!done && kth != ~0ull && (double)R.tlo > key_upper_l(kth)) done = true;
             if (!done) {
                 double l, q2, a;
@@ -780,8 +802,14 @@ __device__ __forceinline__ TraceArgs item_view(const GroupDev& g, int& tile) {
     return it->t;
 }
 
+// Waves per SIMD the select kernel must fit (a register cap for the
+// compiler): the K-buffer of 32 keys would otherwise take 173 VGPRs and drop
+// to two waves.
 template <int KB>
-__global__ __launch_bounds__(TILE_THREADS) void k_select(GroupDev g) {
+constexpr int select_waves() { return KB == 32 ? 3 : 1; }
+
+template <int KB>
+__global__ __launch_bounds__(TILE_THREADS, select_waves<KB>()) void k_select(GroupDev g) {
     int tile;
     const TraceArgs A = item_view(g, tile);
     select_body<KB>(A, tile);
