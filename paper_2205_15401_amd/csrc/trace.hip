@@ -92,16 +92,24 @@ __device__ __forceinline__ void trace_one(const Rec& R, double u, double v, doub
     q2 = fma(-b, l, R.c);
 }
 
-// A candidate staged in LDS: the trace coefficients with its screen bounds.
-struct __align__(16) StagedRec {
-    double A0, A1, A2, A3, A4, A5;
-    double B0, B1, B2;
-    double c;
-    float tlo;
-    uint32_t rank;
-    int16_t i0, i1, j0, j1;
-};
-static_assert(sizeof(StagedRec) == 96, "StagedRec is 96 bytes");
+// The trace records as constant memory: the records do not change while
+// the trace kernels run, and a uniform index into this address space is
+// read with scalar loads into scalar registers.
+typedef const __attribute__((address_space(4))) TraceRec* ConstRecPtr;
+
+__device__ __forceinline__ ConstRecPtr const_rec(const TraceRec* p) {
+    return (ConstRecPtr)(uintptr_t)p;
+}
+
+// The fields the trace needs, read through the constant-space pointer.
+__device__ __forceinline__ TraceRec load_rec(ConstRecPtr p) {
+    TraceRec r;
+    r.A0 = p->A0; r.A1 = p->A1; r.A2 = p->A2; r.A3 = p->A3; r.A4 = p->A4; r.A5 = p->A5;
+    r.B0 = p->B0; r.B1 = p->B1; r.B2 = p->B2; r.c = p->c;
+    r.tlo = p->tlo;
+    r.idx = 0; r.rank = 0; r.pad = 0;
+    return r;
+}
 
 __device__ __forceinline__ double key_upper_l(uint64_t key) {
     return __longlong_as_double((long long)(key | RANK_MASK));
@@ -145,79 +153,53 @@ __device__ __forceinline__ int wave_max_keff(int keff) {
 }
 
 // ------------------------------------------------------------------ select
+// Each wave owns one 8x8 block of the tile and works alone (no workgroup
+// barriers: waves with fewer candidates do not wait for the others).  It
+// scans the depth-ordered cull records 64 at a time, compacts those whose
+// screen box meets its block into a wave-private list, and traces them in
+// order; the records of listed candidates come through the scalar cache.
 template <int KB>
 __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
-    __shared__ StagedRec s_rec[TILE_THREADS];
-    __shared__ uint8_t s_wl[TILE_THREADS / WAVE][TILE_THREADS];   // per-wave candidate lists, depth order
-    __shared__ int s_wcnt[TILE_THREADS / WAVE];
+    __shared__ int s_list[TILE_THREADS / WAVE][WAVE];
     const int tid = threadIdx.x, lane = tid % WAVE;
     const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);   // uniform in the wave
     const int ntx = (A.W + TILE - 1) / TILE;
     const PixelCtx P = pixel_of(tile, ntx, A.H, A.W, A.cx, A.cy);
-    const int ti0 = (tile / ntx) * TILE, tj0 = (tile % ntx) * TILE;
-    const int ti1 = ti0 + TILE - 1, tj1 = tj0 + TILE - 1;
-    // this wave's 8x8 block
-    const int bi0 = ti0 + (wave >> 1) * 8, bj0 = tj0 + (wave & 1) * 8;
+    const int bi0 = (tile / ntx) * TILE + (wave >> 1) * 8;            // this wave's block
+    const int bj0 = (tile % ntx) * TILE + (wave & 1) * 8;
     const uint64_t lt = lanemask_lt();
+    int* list = s_list[wave];
 
     uint64_t key[KB];
 #pragma unroll
     for (int s = 0; s < KB; ++s) key[s] = ~0ull;
-    uint64_t kth = ~0ull;                       // the K-th smallest key so far
+    uint64_t kth = ~0ull;                        // the K-th smallest key so far
     bool done = !P.valid;
     CullRec nxt;
-    if (tid < A.N) nxt = A.cull[tid];
-    for (int base = 0; base < A.N; base += TILE_THREADS) {
-        const int r = base + tid;
+    if (lane < A.N) nxt = A.cull[lane];
+    for (int base = 0; base < A.N; base += WAVE) {
+        const int r = base + lane;
         const CullRec c = nxt;
-        if (r + TILE_THREADS < A.N) nxt = A.cull[r + TILE_THREADS];   // prefetch the next chunk
-        const bool hit = r < A.N && c.i0 <= ti1 && c.i1 >= ti0 && c.j0 <= tj1 && c.j1 >= tj0;
+        if (r + WAVE < A.N) nxt = A.cull[r + WAVE];                  // prefetch the next step
+        const bool hit = r < A.N && c.i0 <= bi0 + 7 && c.i1 >= bi0 && c.j0 <= bj0 + 7 && c.j1 >= bj0;
         const uint64_t m = __ballot(hit);
-        if (lane == 0) s_wcnt[wave] = __popcll(m);
-        __syncthreads();
-        int off = 0, total = 0;
-#pragma unroll
-        for (int w = 0; w < TILE_THREADS / WAVE; ++w) {
-            const int cw = s_wcnt[w];
-            off += w < wave ? cw : 0;
-            total += cw;
-        }
-        if (hit) {
-            const TraceRec& g = A.rec[r];
-            StagedRec& d = s_rec[off + __popcll(m & lt)];
-            d.A0 = g.A0; d.A1 = g.A1; d.A2 = g.A2; d.A3 = g.A3; d.A4 = g.A4; d.A5 = g.A5;
-            d.B0 = g.B0; d.B1 = g.B1; d.B2 = g.B2; d.c = g.c;
-            d.tlo = c.tlo;
-            d.rank = (uint32_t)r;
-            d.i0 = c.i0; d.i1 = c.i1; d.j0 = c.j0; d.j1 = c.j1;
-        }
-        __syncthreads();
-        // the staged candidates whose screen box meets this wave's block, in
-        // order (a wave-local compaction; only this wave reads its list)
-        int mine = 0;
-        for (int s0 = 0; s0 < total; s0 += WAVE) {
-            const int sidx = s0 + lane;
-            bool h = false;
-            if (sidx < total) {
-                const StagedRec& R = s_rec[sidx];
-                h = R.i0 <= bi0 + 7 && R.i1 >= bi0 && R.j0 <= bj0 + 7 && R.j1 >= bj0;
-            }
-            const uint64_t mm = __ballot(h);
-            if (h) s_wl[wave][mine + __popcll(mm & lt)] = (uint8_t)sidx;
-            mine += __popcll(mm);
-        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");   // earlier reads of the list are done
+        __builtin_amdgcn_wave_barrier();
+        if (hit) list[__popcll(m & lt)] = r;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int ci = 0; ci < mine; ++ci) {
+        const int n = __popcll(m);
+        for (int ci = 0; ci < n; ++ci) {
             if (__all(done)) break;
-            const StagedRec& R = s_rec[s_wl[wave][ci]];
+            const int rank = __builtin_amdgcn_readfirstlane(list[ci]);
+            const TraceRec R = load_rec(const_rec(A.rec) + rank);
             if (!done && kth != ~0ull && (double)R.tlo > key_upper_l(kth)) done = true;
             if (!done) {
                 double l, q2, a;
                 trace_one(R, P.u, P.v, l, q2, a);
                 if (q2 < A.rad2 && l > 0.0) {
-                    const uint64_t nk = ((uint64_t)__double_as_longlong(l) & ~RANK_MASK) | (uint64_t)R.rank;
+                    const uint64_t nk = ((uint64_t)__double_as_longlong(l) & ~RANK_MASK) | (uint64_t)rank;
                     if (nk < kth) {
                         kbuf_insert<KB>(key, nk);
                         kth = kth_key<KB>(key, A.K);
@@ -225,11 +207,15 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
                 }
             }
         }
-        // every pixel done against the next chunk's first bound ends the tile
-        const int nb = base + TILE_THREADS;
+        // the block is done when every pixel is, or holds K kernels nearer
+        // than the next record's depth bound (lane 0 prefetched that record)
+        const int nb = base + WAVE;
         bool fin = done;
-        if (!fin && nb < A.N) fin = kth != ~0ull && (double)A.cull[nb].tlo > key_upper_l(kth);
-        if (__syncthreads_and(fin ? 1 : 0)) break;
+        if (!fin && nb < A.N) {
+            const float next_tlo = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(nxt.tlo)));
+            fin = kth != ~0ull && (double)next_tlo > key_upper_l(kth);
+        }
+        if (__all(fin)) break;
     }
 
     // write the kept list: FP64 depth, e^q, sqrt(a), rank, original index
@@ -803,8 +789,7 @@ __device__ __forceinline__ TraceArgs item_view(const GroupDev& g, int& tile) {
 }
 
 // Waves per SIMD the select kernel must fit (a register cap for the
-// compiler): the K-buffer of 32 keys would otherwise take 173 VGPRs and drop
-// to two waves.
+// compiler): three at a K-buffer of 32 keys, which would otherwise drop to two.
 template <int KB>
 constexpr int select_waves() { return KB == 32 ? 3 : 1; }
 
