@@ -124,14 +124,24 @@ __device__ __forceinline__ uint64_t kth_key(const uint64_t (&key)[KB], int K) {
     return kk;
 }
 
+// Insertion of a key into the sorted K-buffer (a compare-exchange network)
+// over slots 0..ub only, ub being a wave-uniform bound of the filled slots:
+// slots past a lane's fill count hold the empty key, so the new key settles
+// at or before the first of them.  Groups of four slots under uniform
+// branches.
 template <int KB>
-__device__ __forceinline__ void kbuf_insert(uint64_t (&key)[KB], uint64_t nk) {
+__device__ __forceinline__ void kbuf_insert_upto(uint64_t (&key)[KB], uint64_t nk, int ub) {
 #pragma unroll
-    for (int s = 0; s < KB; ++s) {
-        const uint64_t cur = key[s];
-        const bool lt = nk < cur;
-        key[s] = lt ? nk : cur;
-        nk = lt ? cur : nk;
+    for (int s0 = 0; s0 < KB; s0 += 4) {
+        if (s0 <= ub) {
+#pragma unroll
+            for (int s = s0; s < s0 + 4 && s < KB; ++s) {
+                const uint64_t cur = key[s];
+                const bool lt = nk < cur;
+                key[s] = lt ? nk : cur;
+                nk = lt ? cur : nk;
+            }
+        }
     }
 }
 
@@ -174,6 +184,7 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
 #pragma unroll
     for (int s = 0; s < KB; ++s) key[s] = ~0ull;
     uint64_t kth = ~0ull;                        // the K-th smallest key so far
+    int nkey = 0;                                // filled slots (saturates at KB)
     bool done = !P.valid;
     CullRec nxt;
     if (lane < A.N) nxt = A.cull[lane];
@@ -195,15 +206,24 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
             const int rank = __builtin_amdgcn_readfirstlane(list[ci]);
             const TraceRec R = load_rec(const_rec(A.rec) + rank);
             if (!done && kth != ~0ull && (double)R.tlo > key_upper_l(kth)) done = true;
+            bool ins = false;
+            uint64_t nk = 0;
             if (!done) {
                 double l, q2, a;
                 trace_one(R, P.u, P.v, l, q2, a);
                 if (q2 < A.rad2 && l > 0.0) {
-                    const uint64_t nk = ((uint64_t)__double_as_longlong(l) & ~RANK_MASK) | (uint64_t)rank;
-                    if (nk < kth) {
-                        kbuf_insert<KB>(key, nk);
-                        kth = kth_key<KB>(key, A.K);
-                    }
+                    nk = ((uint64_t)__double_as_longlong(l) & ~RANK_MASK) | (uint64_t)rank;
+                    ins = nk < kth;
+                }
+            }
+            if (__any(ins)) {
+                int ub = nkey;
+                for (int off = WAVE / 2; off > 0; off >>= 1) ub = max(ub, __shfl_xor(ub, off));
+                ub = __builtin_amdgcn_readfirstlane(ub);
+                if (ins) {
+                    kbuf_insert_upto<KB>(key, nk, ub);
+                    nkey = min(nkey + 1, KB);
+                    kth = nkey >= A.K ? kth_key<KB>(key, A.K) : ~0ull;
                 }
             }
         }
