@@ -186,6 +186,12 @@ def bench_poses(args, torch, dev):
     total_g, per_g = timer.run(lambda: batch.run(forward=True, backward=True, graph=True, stream=s), args.steps,
                                args.warmup)
     total_e, per_e = timer.run(lambda: batch.run(forward=True, backward=True, stream=s), args.steps, args.warmup)
+    # autotuned execution choices (timed on this batch by the library)
+    tune = batch.tune(forward=True, backward=True, trials=3, stream=s)
+    total_t, per_t = timer.run(lambda: batch.run(forward=True, backward=True, tuned=True, stream=s), args.steps,
+                               args.warmup)
+    log(f"[bench] autotuner: graph={tune.graph} order={tune.order} ({tune.best_ms:.3f} ms vs default "
+        f"{tune.default_ms:.3f} ms); tuned {total_t / args.steps:.3f} ms/step")
     st = batch.status()
     if any(st):
         log(f"[bench] device status {st}")
@@ -211,17 +217,19 @@ def bench_poses(args, torch, dev):
             if record is not None:
                 record[i + 1].record(side)
 
-    total_p, _ = timer.run(step_per_call, args.per_call_steps, 1)
-    ms_p = total_p / args.per_call_steps
-    # per-render latency of the per-call mode
-    for _ in range(2):
-        evs = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
-        torch.cuda.synchronize()
-        evs[0].record(side)
-        step_per_call(evs)
-        torch.cuda.synchronize()
-        per_render += [evs[i].elapsed_time(evs[i + 1]) for i in range(n)]
-    log(f"[bench] per-call {ms_p:.3f} ms/step ({rays / ms_p / 1e3:.1f} Mrays/s)")
+    ms_p = None
+    if args.per_call_steps > 0:
+        total_p, _ = timer.run(step_per_call, args.per_call_steps, 1)
+        ms_p = total_p / args.per_call_steps
+        # per-render latency of the per-call mode
+        for _ in range(2):
+            evs = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+            torch.cuda.synchronize()
+            evs[0].record(side)
+            step_per_call(evs)
+            torch.cuda.synchronize()
+            per_render += [evs[i].elapsed_time(evs[i + 1]) for i in range(n)]
+        log(f"[bench] per-call {ms_p:.3f} ms/step ({rays / ms_p / 1e3:.1f} Mrays/s)")
 
     # kernel phases of the batched step (eager, so each launch is timed on its stream)
     nat.voge_profile_enable(ctx, True)
@@ -236,7 +244,11 @@ def bench_poses(args, torch, dev):
     del ws
     return {
         "value": rays / ms_g / 1e3, "ms": ms_g, "per": per_g, "eager_value": rays / ms_e / 1e3, "eager_ms": ms_e,
-        "eager_per": per_e, "per_call_value": rays / ms_p / 1e3, "per_call_ms": ms_p, "per_render": per_render,
+        "eager_per": per_e, "per_call_value": rays / ms_p / 1e3 if ms_p else None, "per_call_ms": ms_p,
+        "per_render": per_render,
+        "tuned_value": rays / (total_t / args.steps) / 1e3, "tuned_ms": total_t / args.steps, "tuned_per": per_t,
+        "tune": {"graph": tune.graph, "order": tune.order, "best_ms": round(tune.best_ms, 4),
+                 "default_ms": round(tune.default_ms, 4)},
         "phases": phases, "rays": rays, "N": N, "C": C, "H": H, "W": W, "K": K, "eta": eta, "n": n, "jobs": jobs,
     }
 
@@ -355,16 +367,17 @@ def bench_serving(args, torch, dev):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20, help="timed batched steps (256 renders each)")
+    ap.add_argument("--steps", type=int, default=20,
+                    help="timed batched steps (256 renders each); 0 runs only the other parts (profiling)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--per-call-steps", type=int, default=3)
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--torus-steps", type=int, default=50, help="timed steps of the single 512x512 image")
-    ap.add_argument("--cpu-sample", type=int, default=262144, help="rays for the oracle baseline (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=1048576, help="rays for the oracle baseline (0 = skip)")
     ap.add_argument("--serving-requests", type=int, default=600, help="timed requests per load (0 = skip serving)")
     ap.add_argument("--serving-warmup", type=int, default=100)
     ap.add_argument("--serving-capacity-requests", type=int, default=200)
-    ap.add_argument("--serving-loads", type=lambda t: [float(x) for x in t.split(",")], default=[0.7])
+    ap.add_argument("--serving-loads", type=lambda t: [float(x) for x in t.split(",")], default=[0.5, 0.9, 1.2, 1.6])
     ap.add_argument("--serving-batch-items", type=int, default=64)
     ap.add_argument("--serving-budget-gb", type=float, default=64.0)
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -383,18 +396,28 @@ def main():
         log("no GPU visible")
         sys.exit(1)
     dev = torch.device("cuda:0")
+    def calibration_copy():
+        if args.calibrate_copy > 0:
+            n4 = args.calibrate_copy // 4
+            src = torch.ones(n4, dtype=torch.float32, device=dev)
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            log(f"[bench] calibration copy of {n4 * 4} bytes done")
+            del src, dst
+
+    if args.steps <= 0:
+        # profiling runs of the other parts only
+        single = bench_torus(args, torch, dev) if args.torus_steps > 0 else None
+        serving = bench_serving(args, torch, dev) if args.serving_requests > 0 else None
+        calibration_copy()
+        print(json.dumps({"metric": None, "value": None, "single_image": single, "serving": serving}), flush=True)
+        return
     r = bench_poses(args, torch, dev)
     single = bench_torus(args, torch, dev) if args.torus_steps > 0 else None
     serving = bench_serving(args, torch, dev) if args.serving_requests > 0 else None
-    if args.calibrate_copy > 0:
-        n4 = args.calibrate_copy // 4
-        src = torch.ones(n4, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"[bench] calibration copy of {n4 * 4} bytes done")
-        del src, dst
+    calibration_copy()
 
     opc_path = os.path.join(ROOT, "oracle", f"opcount_{POSES_NAME}.json")
     roofline = None
@@ -428,10 +451,14 @@ def main():
         "latency_ms": {"p50": pct(r["eager_per"], 50), "p99": pct(r["eager_per"], 99)},
         "batched_graph": {"value": round(r["value"], 3), "ms_per_step": round(r["ms"], 5),
                           "latency_ms": {"p50": pct(r["per"], 50), "p99": pct(r["per"], 99)}},
-        "per_call": {"value": round(r["per_call_value"], 3), "ms_per_step": round(r["per_call_ms"], 5),
-                     "steps": args.per_call_steps,
-                     "render_latency_ms": {"p50": pct(r["per_render"], 50), "p99": pct(r["per_render"], 99)}},
-        "batched_vs_per_call": round(r["eager_value"] / r["per_call_value"], 3),
+        "batched_tuned": {"value": round(r["tuned_value"], 3), "ms_per_step": round(r["tuned_ms"], 5),
+                          "latency_ms": {"p50": pct(r["tuned_per"], 50), "p99": pct(r["tuned_per"], 99)},
+                          "choice": r["tune"]},
+        "per_call": None if r["per_call_ms"] is None else {
+            "value": round(r["per_call_value"], 3), "ms_per_step": round(r["per_call_ms"], 5),
+            "steps": args.per_call_steps,
+            "render_latency_ms": {"p50": pct(r["per_render"], 50), "p99": pct(r["per_render"], 99)}},
+        "batched_vs_per_call": None if r["per_call_ms"] is None else round(r["eager_value"] / r["per_call_value"], 3),
         "single_image": single,
         "serving": serving,
         "phases_us": {k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in r["phases"].items()},

@@ -65,13 +65,15 @@ extern "C" {
 
 /* Call flags.  voge_render_backward takes VOGE_REUSE_PREP alone;
  * voge_render_batch takes VOGE_FORWARD and/or VOGE_BACKWARD, optionally with
- * VOGE_REUSE_PREP (backward only) and VOGE_GRAPH. */
+ * VOGE_REUSE_PREP (backward only), VOGE_GRAPH and VOGE_TUNED. */
 #define VOGE_REUSE_PREP 1     /* the workspace holds the preparation and kept
                                  lists of a forward of the same items          */
 #define VOGE_FORWARD 2        /* batch: render the images                      */
 #define VOGE_BACKWARD 4       /* batch: gradients of the images                */
 #define VOGE_GRAPH 8          /* batch: replay the call's launches from a HIP
                                  graph cached per shape (captured on first use) */
+#define VOGE_TUNED 16         /* batch: use the execution choices voge_tune_batch
+                                 found for these shapes (defaults if none)     */
 
 #define VOGE_MAX_BATCH 4096   /* items per voge_render_batch call              */
 
@@ -181,6 +183,36 @@ int voge_batch_workspace_size(const voge_item_t* items, int n_items, int with_ba
  * VOGE_EHIP. */
 int voge_render_batch(voge_ctx_t* ctx, const voge_item_t* items, int n_items, int flags, void* workspace,
                       size_t workspace_bytes, void* stream);
+
+/* Autotuner.  For the shapes of a batch (per item: image size, K, C and the
+ * bit length of N, in call order; plus the work flags and the device
+ * architecture) it times the execution choices -- launches issued one by one
+ * or replayed from a HIP graph, and the order in which workgroups take screen
+ * tiles (a contiguous band of tiles per XCD, for L2 locality, or every eighth
+ * tile per XCD, for balance) -- on the caller's batch, and keeps the fastest in
+ * the context for calls with VOGE_TUNED.  Results are those of
+ * voge_render_batch (the call renders the batch 1 + trials times per choice).
+ *   flags      as for voge_render_batch, without VOGE_GRAPH and VOGE_TUNED
+ *   trials     timed renders per choice (>= 1); graph choices need a non-null stream
+ *   result     optional: the choice kept and the mean times (ms) of it and of
+ *              the default (separate launches, banded order)
+ * Synchronises `stream`.  Errors as for voge_render_batch. */
+typedef struct voge_tune_result {
+    int32_t graph;            /* 1 if the kept choice replays a HIP graph      */
+    int32_t order;            /* 0 banded tiles per XCD, 1 plain tile order     */
+    double best_ms;
+    double default_ms;
+} voge_tune_result_t;
+
+int voge_tune_batch(voge_ctx_t* ctx, const voge_item_t* items, int n_items, int flags, void* workspace,
+                    size_t workspace_bytes, void* stream, int trials, voge_tune_result_t* result);
+
+/* Save the context's tuned choices to `path` (JSON lines: arch, key, graph,
+ * order, ms), or merge those of a file written by voge_tune_save; entries of
+ * another architecture are skipped on load.  Errors: VOGE_EINVAL (null
+ * arguments, unreadable or malformed file). */
+int voge_tune_save(voge_ctx_t* ctx, const char* path);
+int voge_tune_load(voge_ctx_t* ctx, const char* path);
 
 /* Per-item device status words (VOGE_STATUS_* bits) of the last batch (or
  * single render) on `workspace`, in the caller's item order.  Synchronises

@@ -24,13 +24,14 @@ VOGE_REUSE_PREP = 1
 VOGE_FORWARD = 2
 VOGE_BACKWARD = 4
 VOGE_GRAPH = 8
+VOGE_TUNED = 16
 VOGE_MAX_BATCH = 4096
 
 EXPORTS = [
     "voge_create", "voge_destroy", "voge_workspace_size", "voge_render_forward",
     "voge_render_backward", "voge_status", "voge_last_error", "voge_version", "voge_debug_phi",
     "voge_profile_enable", "voge_profile_read", "voge_batch_workspace_size", "voge_render_batch",
-    "voge_batch_status",
+    "voge_batch_status", "voge_tune_batch", "voge_tune_save", "voge_tune_load",
 ]
 
 
@@ -50,6 +51,11 @@ class VogeItem(ctypes.Structure):
                 ("image", ctypes.c_void_p), ("wsum", ctypes.c_void_p), ("kept", ctypes.c_void_p),
                 ("grad_image", ctypes.c_void_p), ("grad_means", ctypes.c_void_p), ("grad_covs", ctypes.c_void_p),
                 ("grad_attrs", ctypes.c_void_p), ("grad_camera", ctypes.c_void_p)]
+
+
+class VogeTuneResult(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_int32), ("order", ctypes.c_int32), ("best_ms", ctypes.c_double),
+                ("default_ms", ctypes.c_double)]
 
 
 class VogePhaseTime(ctypes.Structure):
@@ -93,6 +99,9 @@ def load(path: str = LIB_PATH):
         lib.voge_batch_workspace_size.argtypes = [ItemP, I, I, ctypes.POINTER(SZ)]
         lib.voge_render_batch.argtypes = [P, ItemP, I, I, P, SZ, P]
         lib.voge_batch_status.argtypes = [P, I, ctypes.POINTER(ctypes.c_int32), P]
+        lib.voge_tune_batch.argtypes = [P, ItemP, I, I, P, SZ, P, I, ctypes.POINTER(VogeTuneResult)]
+        lib.voge_tune_save.argtypes = [P, ctypes.c_char_p]
+        lib.voge_tune_load.argtypes = [P, ctypes.c_char_p]
         for name in EXPORTS:
             if name != "voge_last_error":
                 getattr(lib, name).restype = I
@@ -176,6 +185,22 @@ def voge_batch_status(workspace, n_items, stream):
     out = (ctypes.c_int32 * int(n_items))()
     _check(load().voge_batch_status(workspace, int(n_items), out, stream))
     return list(out)
+
+
+def voge_tune_batch(ctx, items, flags, workspace, workspace_bytes, stream, trials: int = 3) -> VogeTuneResult:
+    arr = items if isinstance(items, ctypes.Array) else item_array(items)
+    res = VogeTuneResult()
+    _check(load().voge_tune_batch(ctx, arr, len(arr), int(flags), workspace, int(workspace_bytes), stream,
+                                  int(trials), ctypes.byref(res)))
+    return res
+
+
+def voge_tune_save(ctx, path: str) -> int:
+    return _check(load().voge_tune_save(ctx, os.fsencode(path)))
+
+
+def voge_tune_load(ctx, path: str) -> int:
+    return _check(load().voge_tune_load(ctx, os.fsencode(path)))
 
 
 def voge_debug_phi(x, y, n, stream) -> int:

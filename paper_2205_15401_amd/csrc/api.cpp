@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -56,6 +58,10 @@ struct voge_ctx {
     std::mutex graph_mu;
     std::vector<GraphEntry> graphs;
     uint64_t tick = 0;
+    // autotuned execution choices per shape key
+    std::string arch;
+    std::mutex tune_mu;
+    std::map<std::string, std::pair<voge::ExecConfig, double>> tuned;
 };
 
 namespace {
@@ -400,13 +406,14 @@ voge::BatchDev batch_dev(const voge::BatchPlan& p, const BatchWs& w) {
     return b;
 }
 
-voge::GroupDev group_dev(const voge::GroupPlan& g, const BatchWs& w) {
+voge::GroupDev group_dev(const voge::GroupPlan& g, const BatchWs& w, const voge::ExecConfig& cfg) {
     voge::GroupDev d{};
     d.items = w.items;
     d.tile_item = w.tile_item;
     d.single = g.n_items == 1 ? g.first_item : -1;
     d.tile0 = g.tile0;
     d.n_tiles = g.n_tiles;
+    d.order = cfg.order;
     return d;
 }
 
@@ -416,8 +423,8 @@ int upload_items(voge_ctx_t* ctx, const std::vector<voge::ItemDev>& recs, const 
                  hipStream_t s);
 
 // All launches of a call after the table upload.
-int launch_compute(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, int flags, bool profile,
-                   hipStream_t s) {
+int launch_compute(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, int flags,
+                   const voge::ExecConfig& cfg, bool profile, hipStream_t s) {
     const voge::BatchDev b = batch_dev(p, w);
     auto scope = [&](const char* name) { return ProfScope(profile ? ctx : nullptr, name, s); };
     const bool fwd_part = (flags & VOGE_FORWARD) || !(flags & VOGE_REUSE_PREP);
@@ -431,12 +438,12 @@ int launch_compute(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, 
         {
             ProfScope ps = scope("select");
             for (const auto& g : p.groups)
-                if (int rc = hip_check(voge::launch_select(group_dev(g, w), g.kb, s), "select launch")) return rc;
+                if (int rc = hip_check(voge::launch_select(group_dev(g, w, cfg), g.kb, s), "select launch")) return rc;
         }
         {
             ProfScope ps = scope("blend");
             for (const auto& g : p.groups)
-                if (int rc = hip_check(voge::launch_blend(group_dev(g, w), g.kb, s), "blend launch")) return rc;
+                if (int rc = hip_check(voge::launch_blend(group_dev(g, w, cfg), g.kb, s), "blend launch")) return rc;
         }
     }
     if (flags & VOGE_BACKWARD) {
@@ -448,12 +455,12 @@ int launch_compute(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, 
         {
             ProfScope ps = scope("bwd");
             for (const auto& g : p.groups)
-                if (int rc = hip_check(voge::launch_bwd(group_dev(g, w), g.kb, s), "backward launch")) return rc;
+                if (int rc = hip_check(voge::launch_bwd(group_dev(g, w, cfg), g.kb, s), "backward launch")) return rc;
         }
         {
             ProfScope ps = scope("bwd_reduce");
             for (const auto& g : p.groups)
-                if (int rc = hip_check(voge::launch_bwd_reduce(group_dev(g, w), g.kb, s), "backward reduce launch"))
+                if (int rc = hip_check(voge::launch_bwd_reduce(group_dev(g, w, cfg), g.kb, s), "backward reduce launch"))
                     return rc;
         }
         {
@@ -464,11 +471,12 @@ int launch_compute(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, 
     return VOGE_OK;
 }
 
-std::vector<int64_t> graph_key(const voge::BatchPlan& p, const void* ws, int flags) {
+std::vector<int64_t> graph_key(const voge::BatchPlan& p, const void* ws, int flags, const voge::ExecConfig& cfg) {
     std::vector<int64_t> k;
-    k.reserve(3 + 5 * p.items.size());
+    k.reserve(4 + 5 * p.items.size());
     k.push_back((int64_t)reinterpret_cast<uintptr_t>(ws));
-    k.push_back(flags);
+    k.push_back(flags & (VOGE_FORWARD | VOGE_BACKWARD | VOGE_REUSE_PREP));
+    k.push_back(cfg.order);
     k.push_back((int64_t)p.items.size());
     for (const auto& it : p.items) {
         k.push_back(it.caller);
@@ -480,11 +488,40 @@ std::vector<int64_t> graph_key(const voge::BatchPlan& p, const void* ws, int fla
     return k;
 }
 
-int run_graph(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, int flags, hipStream_t s);
+int run_graph(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, int flags, const voge::ExecConfig& cfg,
+              hipStream_t s);
 
-// The whole call: checks, plan, table, launches.
+// The autotuner's key of a call: the device architecture, the work flags and
+// the items' shapes in call order (height x width, K, C and the bit length of
+// N), run-length coded.
+std::string shape_key(const voge_ctx_t* ctx, const voge_item_t* items, int n, int flags) {
+    std::string k = ctx->arch + ";f" + std::to_string(flags & (VOGE_FORWARD | VOGE_BACKWARD | VOGE_REUSE_PREP)) + ";";
+    std::string prev;
+    int run = 0;
+    auto flush = [&]() {
+        if (run > 0) k += prev + "*" + std::to_string(run) + ",";
+    };
+    for (int i = 0; i < n; ++i) {
+        int nb = 0;
+        while ((1LL << nb) <= (long long)items[i].N) ++nb;
+        const std::string sh = std::to_string(items[i].camera.height) + "x" + std::to_string(items[i].camera.width) +
+                               "/K" + std::to_string(items[i].params.K) + "/C" + std::to_string(items[i].C) + "/N" +
+                               std::to_string(nb);
+        if (sh != prev) {
+            flush();
+            prev = sh;
+            run = 0;
+        }
+        ++run;
+    }
+    flush();
+    return k;
+}
+
+// The whole call: checks, plan, table, launches.  `force` overrides the
+// execution choices (the autotuner's trials).
 int run_batch(voge_ctx_t* ctx, const voge_item_t* items, int n, int flags, void* workspace, size_t workspace_bytes,
-              hipStream_t s) {
+              hipStream_t s, const voge::ExecConfig* force = nullptr) {
     const bool backward = (flags & VOGE_BACKWARD) != 0;
     std::vector<voge::ItemShape> shapes(n);
     for (int i = 0; i < n; ++i) shapes[i] = shape_of(items[i]);
@@ -496,13 +533,26 @@ int run_batch(voge_ctx_t* ctx, const voge_item_t* items, int n, int flags, void*
     const BatchWs w = carve_batch(workspace, p);
     std::vector<voge::ItemDev> recs(n);
     for (int j = 0; j < n; ++j) recs[j] = item_record(p, j, items[p.items[j].caller], w, flags, backward);
+    voge::ExecConfig cfg;
+    if (force) {
+        cfg = *force;
+    } else {
+        if (flags & VOGE_TUNED) {
+            const std::string key = shape_key(ctx, items, n, flags);
+            std::lock_guard<std::mutex> g(ctx->tune_mu);
+            auto it = ctx->tuned.find(key);
+            if (it != ctx->tuned.end()) cfg = it->second.first;
+        }
+        if (flags & VOGE_GRAPH) cfg.graph = 1;
+    }
+    if (s == nullptr) cfg.graph = 0;       // graphs are captured on a non-null stream only
     const bool fwd_part = (flags & VOGE_FORWARD) || !(flags & VOGE_REUSE_PREP);
     {
         ProfScope ps(ctx, "upload", s);
         if (int rc = upload_items(ctx, recs, w, fwd_part, s)) return rc;
     }
-    if (flags & VOGE_GRAPH) return run_graph(ctx, p, w, flags, s);
-    return launch_compute(ctx, p, w, flags, true, s);
+    if (cfg.graph) return run_graph(ctx, p, w, flags, cfg, s);
+    return launch_compute(ctx, p, w, flags, cfg, true, s);
 }
 
 }  // namespace
@@ -544,8 +594,9 @@ int upload_items(voge_ctx_t* ctx, const std::vector<voge::ItemDev>& recs, const 
 
 // Replays the call's launches from a cached graph, capturing it on `s` the
 // first time this (workspace, flags, shapes) key is seen.
-int run_graph(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, int flags, hipStream_t s) {
-    const std::vector<int64_t> key = graph_key(p, w.base, flags);
+int run_graph(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, int flags, const voge::ExecConfig& cfg,
+              hipStream_t s) {
+    const std::vector<int64_t> key = graph_key(p, w.base, flags, cfg);
     std::lock_guard<std::mutex> g(ctx->graph_mu);
     GraphEntry* hit = nullptr;
     for (auto& e : ctx->graphs)
@@ -553,7 +604,7 @@ int run_graph(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, int f
     if (!hit) {
         if (int rc = hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture"))
             return rc;
-        const int rc_launch = launch_compute(ctx, p, w, flags, false, s);
+        const int rc_launch = launch_compute(ctx, p, w, flags, cfg, false, s);
         hipGraph_t graph = nullptr;
         const hipError_t e_end = hipStreamEndCapture(s, &graph);
         if (rc_launch) {
@@ -617,9 +668,13 @@ int voge_create(voge_ctx_t** ctx, int device) {
         return rc;
     DeviceGuard guard(device);
     if (!guard.ok) return fail(VOGE_EHIP, "cannot select the device");
+    hipDeviceProp_t prop;
+    if (int rc = hip_check(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties")) return rc;
     voge_ctx_t* c = new voge_ctx();
     c->device = device;
     c->n_cu = n_cu;
+    c->arch = prop.gcnArchName;
+    c->arch = c->arch.substr(0, c->arch.find(':'));
     c->stage_bytes = sizeof(voge::ItemDev) * (size_t)voge::MAX_BATCH;
     c->ring.resize(RING_SLOTS);
     for (auto& st : c->ring) {
@@ -735,7 +790,7 @@ int voge_render_batch(voge_ctx_t* ctx, const voge_item_t* items, int n_items, in
                       size_t workspace_bytes, void* stream) {
     if (!ctx) return fail(VOGE_EINVAL, "ctx is null");
     if (!items || n_items < 1 || n_items > voge::MAX_BATCH) return fail(VOGE_EINVAL, "n_items must be in [1, 4096]");
-    if (flags & ~(VOGE_FORWARD | VOGE_BACKWARD | VOGE_REUSE_PREP | VOGE_GRAPH))
+    if (flags & ~(VOGE_FORWARD | VOGE_BACKWARD | VOGE_REUSE_PREP | VOGE_GRAPH | VOGE_TUNED))
         return fail(VOGE_EINVAL, "unknown flags");
     if (!(flags & (VOGE_FORWARD | VOGE_BACKWARD))) return fail(VOGE_EINVAL, "VOGE_FORWARD or VOGE_BACKWARD is required");
     if ((flags & VOGE_REUSE_PREP) && (flags & VOGE_FORWARD))
@@ -746,6 +801,152 @@ int voge_render_batch(voge_ctx_t* ctx, const voge_item_t* items, int n_items, in
         if (int rc = validate_item(items[i], flags, i)) return rc;
     if (int rc = run_batch(ctx, items, n_items, flags, workspace, workspace_bytes, static_cast<hipStream_t>(stream)))
         return rc;
+    g_err.clear();
+    return VOGE_OK;
+}
+
+int voge_tune_batch(voge_ctx_t* ctx, const voge_item_t* items, int n_items, int flags, void* workspace,
+                    size_t workspace_bytes, void* stream, int trials, voge_tune_result_t* result) {
+    if (!ctx) return fail(VOGE_EINVAL, "ctx is null");
+    if (!items || n_items < 1 || n_items > voge::MAX_BATCH) return fail(VOGE_EINVAL, "n_items must be in [1, 4096]");
+    if (flags & ~(VOGE_FORWARD | VOGE_BACKWARD | VOGE_REUSE_PREP)) return fail(VOGE_EINVAL, "unknown flags");
+    if (!(flags & (VOGE_FORWARD | VOGE_BACKWARD))) return fail(VOGE_EINVAL, "VOGE_FORWARD or VOGE_BACKWARD is required");
+    if ((flags & VOGE_REUSE_PREP) && (flags & VOGE_FORWARD))
+        return fail(VOGE_EINVAL, "VOGE_REUSE_PREP goes with VOGE_BACKWARD alone");
+    if (trials < 1) return fail(VOGE_EINVAL, "trials must be >= 1");
+    if (int rc = check_workspace(workspace)) return rc;
+    for (int i = 0; i < n_items; ++i)
+        if (int rc = validate_item(items[i], flags, i)) return rc;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return fail(VOGE_EHIP, "cannot select the context's device");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<voge::ExecConfig> cands;
+    for (int graph = 0; graph < (s ? 2 : 1); ++graph)
+        for (int order = 0; order < 2; ++order) {
+            voge::ExecConfig c;
+            c.graph = graph;
+            c.order = order;
+            cands.push_back(c);
+        }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (int rc = hip_check(hipEventCreate(&e0), "hipEventCreate")) return rc;
+    if (int rc = hip_check(hipEventCreate(&e1), "hipEventCreate")) {
+        (void)hipEventDestroy(e0);
+        return rc;
+    }
+    int rc = VOGE_OK;
+    double best = 0.0, dflt = 0.0;
+    voge::ExecConfig best_cfg;
+    for (size_t ci = 0; ci < cands.size() && rc == VOGE_OK; ++ci) {
+        rc = run_batch(ctx, items, n_items, flags, workspace, workspace_bytes, s, &cands[ci]);   // warm-up / capture
+        if (rc == VOGE_OK) rc = hip_check(hipEventRecord(e0, s), "hipEventRecord");
+        for (int t = 0; t < trials && rc == VOGE_OK; ++t)
+            rc = run_batch(ctx, items, n_items, flags, workspace, workspace_bytes, s, &cands[ci]);
+        if (rc == VOGE_OK) rc = hip_check(hipEventRecord(e1, s), "hipEventRecord");
+        if (rc == VOGE_OK) rc = hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+        float ms = 0.f;
+        if (rc == VOGE_OK) rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        if (rc != VOGE_OK) break;
+        const double mean = ms / trials;
+        if (ci == 0) dflt = mean;
+        if (ci == 0 || mean < best) {
+            best = mean;
+            best_cfg = cands[ci];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != VOGE_OK) return rc;
+    {
+        std::lock_guard<std::mutex> g(ctx->tune_mu);
+        ctx->tuned[shape_key(ctx, items, n_items, flags)] = {best_cfg, best};
+    }
+    if (result) {
+        result->graph = best_cfg.graph;
+        result->order = best_cfg.order;
+        result->best_ms = best;
+        result->default_ms = dflt;
+    }
+    g_err.clear();
+    return VOGE_OK;
+}
+
+namespace {
+
+// The value after `"name":` in a JSON line written by voge_tune_save.
+bool json_field(const std::string& line, const char* name, std::string& out) {
+    const std::string tag = std::string("\"") + name + "\":";
+    const size_t p = line.find(tag);
+    if (p == std::string::npos) return false;
+    size_t i = p + tag.size();
+    if (i < line.size() && line[i] == '"') {
+        const size_t e = line.find('"', i + 1);
+        if (e == std::string::npos) return false;
+        out = line.substr(i + 1, e - i - 1);
+        return true;
+    }
+    size_t e = i;
+    while (e < line.size() && line[e] != ',' && line[e] != '}') ++e;
+    out = line.substr(i, e - i);
+    return !out.empty();
+}
+
+}  // namespace
+
+int voge_tune_save(voge_ctx_t* ctx, const char* path) {
+    if (!ctx || !path) return fail(VOGE_EINVAL, "ctx and path are required");
+    FILE* f = std::fopen(path, "w");
+    if (!f) return fail(VOGE_EINVAL, std::string("cannot write ") + path);
+    std::lock_guard<std::mutex> g(ctx->tune_mu);
+    for (const auto& kv : ctx->tuned) {
+        if (kv.first.find('"') != std::string::npos) continue;
+        std::fprintf(f, "{\"arch\":\"%s\",\"key\":\"%s\",\"graph\":%d,\"order\":%d,\"ms\":%.6g}\n", ctx->arch.c_str(),
+                     kv.first.c_str(), kv.second.first.graph, kv.second.first.order, kv.second.second);
+    }
+    const bool ok = std::fclose(f) == 0;
+    if (!ok) return fail(VOGE_EINVAL, std::string("cannot write ") + path);
+    g_err.clear();
+    return VOGE_OK;
+}
+
+int voge_tune_load(voge_ctx_t* ctx, const char* path) {
+    if (!ctx || !path) return fail(VOGE_EINVAL, "ctx and path are required");
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(VOGE_EINVAL, std::string("cannot read ") + path);
+    std::map<std::string, std::pair<voge::ExecConfig, double>> got;
+    char buf[65536];
+    int lineno = 0;
+    bool bad = false;
+    while (std::fgets(buf, sizeof(buf), f)) {
+        ++lineno;
+        std::string line(buf);
+        while (!line.empty() && (line.back() == '\n' || line.back() == '\r')) line.pop_back();
+        if (line.empty()) continue;
+        std::string arch, key, graph, order, ms;
+        if (!json_field(line, "arch", arch) || !json_field(line, "key", key) || !json_field(line, "graph", graph) ||
+            !json_field(line, "order", order) || !json_field(line, "ms", ms)) {
+            bad = true;
+            break;
+        }
+        char* end = nullptr;
+        const long gv = std::strtol(graph.c_str(), &end, 10);
+        if (*end || (gv != 0 && gv != 1)) { bad = true; break; }
+        const long ov = std::strtol(order.c_str(), &end, 10);
+        if (*end || (ov != 0 && ov != 1)) { bad = true; break; }
+        const double mv = std::strtod(ms.c_str(), &end);
+        if (*end) { bad = true; break; }
+        if (arch != ctx->arch) continue;
+        voge::ExecConfig c;
+        c.graph = (int)gv;
+        c.order = (int)ov;
+        got[key] = {c, mv};
+    }
+    std::fclose(f);
+    if (bad) return fail(VOGE_EINVAL, std::string("malformed line ") + std::to_string(lineno) + " in " + path);
+    {
+        std::lock_guard<std::mutex> g(ctx->tune_mu);
+        for (auto& kv : got) ctx->tuned[kv.first] = kv.second;
+    }
     g_err.clear();
     return VOGE_OK;
 }

@@ -146,10 +146,12 @@ __device__ __forceinline__ void kbuf_insert_upto(uint64_t (&key)[KB], uint64_t n
 }
 
 // Block -> tile.  Workgroups are dealt round-robin to the 8 XCDs (block b
-// runs on XCD b % 8), so each XCD renders a contiguous band of tiles and the
-// kernels those tiles share stay in that XCD's L2.
-__device__ __forceinline__ int tile_of_block() {
+// runs on XCD b % 8).  Order 0 (banded): each XCD renders a contiguous band
+// of tiles, so the kernels those tiles share stay in that XCD's L2.  Order 1
+// (plain): block b renders tile b, so every XCD takes every eighth tile.
+__device__ __forceinline__ int tile_of_block(int order) {
     const int b = blockIdx.x, nb = gridDim.x;
+    if (order == 1) return b;
     const int x = b & 7, local = b >> 3;
     const int per = nb >> 3, rem = nb & 7;
     return x * per + (x < rem ? x : rem) + local;
@@ -801,7 +803,7 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
 // before the kernel's first store, so the compiler keeps the fields in scalar
 // registers instead of re-reading the table after each store.
 __device__ __forceinline__ TraceArgs item_view(const GroupDev& g, int& tile) {
-    const int gt = g.tile0 + tile_of_block();
+    const int gt = g.tile0 + tile_of_block(g.order);
     const int item = g.single >= 0 ? g.single : g.tile_item[gt];
     const ItemDev* it = g.items + item;
     tile = gt - it->tile_start;

@@ -92,6 +92,13 @@ struct GroupDev {
     const int* tile_item;      // [total tiles] -> item
     int single;                // the group's item when it has only one, else -1
     int tile0, n_tiles;        // the group's global tiles
+    int order;                 // block -> tile order: 0 banded per XCD, 1 plain
+};
+
+// Execution choices of a call, picked by the autotuner per shape.
+struct ExecConfig {
+    int graph = 0;             // replay the launches from a cached HIP graph
+    int order = 0;             // block -> tile order of the trace kernels
 };
 
 // Host-side plan of a batch: sizes, table order and workspace offsets.

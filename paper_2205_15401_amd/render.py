@@ -255,15 +255,27 @@ class Batch:
     def set_grad_image(self, i: int, g: torch.Tensor) -> None:
         self.grad_images[i].copy_(g)
 
-    def run(self, forward: bool = True, backward: bool = False, reuse: bool = False, graph: bool = False,
-            stream: Optional[int] = None) -> None:
-        """One call of voge_render_batch on ``stream`` (default: torch's current stream)."""
-        flags = (nat.VOGE_FORWARD if forward else 0) | (nat.VOGE_BACKWARD if backward else 0)
-        flags |= (nat.VOGE_REUSE_PREP if reuse else 0) | (nat.VOGE_GRAPH if graph else 0)
+    def _flags(self, forward, backward, reuse):
         if backward and not self.backward:
             raise ValueError("this batch was built without a backward")
+        flags = (nat.VOGE_FORWARD if forward else 0) | (nat.VOGE_BACKWARD if backward else 0)
+        return flags | (nat.VOGE_REUSE_PREP if reuse else 0)
+
+    def run(self, forward: bool = True, backward: bool = False, reuse: bool = False, graph: bool = False,
+            tuned: bool = False, stream: Optional[int] = None) -> None:
+        """One call of voge_render_batch on ``stream`` (default: torch's current stream)."""
+        flags = self._flags(forward, backward, reuse)
+        flags |= (nat.VOGE_GRAPH if graph else 0) | (nat.VOGE_TUNED if tuned else 0)
         s = _stream(self.device) if stream is None else stream
         nat.voge_render_batch(context(self.device), self.arr, flags, _ptr(self.workspace), self.ws_bytes, s)
+
+    def tune(self, forward: bool = True, backward: bool = False, trials: int = 3,
+             stream: Optional[int] = None) -> nat.VogeTuneResult:
+        """Time the execution choices on this batch (voge_tune_batch); later
+        calls of ``run(tuned=True)`` with the same shapes use the fastest."""
+        s = _stream(self.device) if stream is None else stream
+        return nat.voge_tune_batch(context(self.device), self.arr, self._flags(forward, backward, False),
+                                   _ptr(self.workspace), self.ws_bytes, s, trials)
 
     def status(self):
         """Per-item device status words (synchronises)."""

@@ -280,3 +280,51 @@ def test_graph_replays_match_eager_calls():
     graph.run(forward=True, backward=True, graph=True, stream=side.cuda_stream)
     side.synchronize()
     compare(new_cams)
+
+
+def test_autotuned_choice_renders_the_same_and_the_cache_round_trips(tmp_path):
+    """The tuner times the execution choices on a batch; a tuned call renders
+    what the default call renders, and the choices survive a save and load."""
+    jobs = S.config_poses(seed=17, n_poses=10, size=64, n=2048)
+    scene = jobs[0].scene
+    dev = torch.device("cuda:0")
+    ds = dev_scene(scene)
+    its = [(0, R.camera_struct(j.camera), 20, 0.01) for j in jobs]
+    ref = R.Batch([ds], its, dev, backward=True, with_camera=True)
+    tuned = R.Batch([ds], its, dev, backward=True, with_camera=True)
+    for i, j in enumerate(jobs):
+        ref.set_grad_image(i, torch.from_numpy(j.grad_image))
+        tuned.set_grad_image(i, torch.from_numpy(j.grad_image))
+    side = torch.cuda.Stream()
+    ref.run(forward=True, backward=True)
+    torch.cuda.synchronize()
+    res = tuned.tune(forward=True, backward=True, trials=2, stream=side.cuda_stream)
+    assert res.graph in (0, 1) and res.order in (0, 1)
+    assert 0 < res.best_ms <= res.default_ms
+    for t in tuned.images:
+        t.fill_(float("nan"))
+    tuned.run(forward=True, backward=True, tuned=True, stream=side.cuda_stream)
+    side.synchronize()
+    for i, j in enumerate(jobs):
+        assert torch.equal(ref.images[i], tuned.images[i])
+        assert_grads_close(((ref.grad_means[i], tuned.grad_means[i]), (ref.grad_covs[i], tuned.grad_covs[i]),
+                            (ref.grad_attrs[i], tuned.grad_attrs[i]), (ref.grad_cameras[i], tuned.grad_cameras[i])),
+                           grad_floors(scene, j.camera, 20, 0.01, j.grad_image), f"tuned item {i}")
+    ctx = R.context(dev)
+    path = tmp_path / "tune.jsonl"
+    nat.voge_tune_save(ctx, str(path))
+    lines = path.read_text().splitlines()
+    mine = [l for l in lines if "64x64/K20/C3/N12*10" in l]
+    assert len(mine) == 1 and '"arch":"gfx' in mine[0]
+    assert f'"graph":{res.graph}' in mine[0] and f'"order":{res.order}' in mine[0]
+    other = tmp_path / "other.jsonl"
+    other.write_text('{"arch":"gfx000","key":"k","graph":1,"order":1,"ms":1}\n')
+    nat.voge_tune_load(ctx, str(other))                       # another architecture: skipped
+    nat.voge_tune_load(ctx, str(path))
+    bad = tmp_path / "bad.jsonl"
+    bad.write_text('{"arch":"gfx950","key":"k","graph":7,"order":0,"ms":1}\n')
+    with pytest.raises(nat.VogeError) as e:
+        nat.voge_tune_load(ctx, str(bad))
+    assert e.value.code == nat.VOGE_EINVAL
+    with pytest.raises(nat.VogeError):
+        nat.voge_tune_load(ctx, str(tmp_path / "missing.jsonl"))
