@@ -328,3 +328,18 @@ def test_autotuned_choice_renders_the_same_and_the_cache_round_trips(tmp_path):
     assert e.value.code == nat.VOGE_EINVAL
     with pytest.raises(nat.VogeError):
         nat.voge_tune_load(ctx, str(tmp_path / "missing.jsonl"))
+
+
+def test_uneven_batch_full_size_matches_the_oracle():
+    """The uneven batch at its full size in one call: 64 cloud scenes of
+    1,000-100,000 kernels, 64^2-512^2 images, K in {8, 16, 32} (three K-buffer
+    groups), forward + backward; every item against the oracle on 64 sampled
+    pixels and through an upstream gradient on those pixels."""
+    rng = np.random.default_rng(31)
+    jobs = S.config_uneven()
+    scenes = [j.scene for j in jobs]
+    items = [(i, j.camera, j.K, j.eta) for i, j in enumerate(jobs)]
+    batch, grads, pixs, frefs, _ = run_checked_batch(scenes, items, rng, n_pix=64)
+    assert batch.status() == [0] * len(items)
+    for i, (si, cam, K, eta) in enumerate(items):
+        check_item(batch, i, scenes[si], cam, K, eta, grads[i], pixs[i], frefs[i])
