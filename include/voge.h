@@ -116,12 +116,16 @@ typedef struct voge_item {
     float* grad_camera;       /* [15] out, optional                             */
 } voge_item_t;
 
-/* Create a library context bound to HIP device `device`.  Host memory only;
- * the calls below run on that device (the caller's current device is
- * restored on return).  Errors: VOGE_EINVAL (null ctx), VOGE_EHIP. */
+/* Create a library context bound to HIP device `device`.  Host memory only:
+ * the context holds a ring of four pinned host buffers (hipHostMalloc, 1.5 MB
+ * each) that stage item tables of large batches, the cached HIP graphs and
+ * the autotuner's choices; no device memory.  The calls below run on that
+ * device (the caller's current device is restored on return).
+ * Errors: VOGE_EINVAL (null ctx), VOGE_EHIP. */
 int voge_create(voge_ctx_t** ctx, int device);
 
-/* Release a context (no device memory is owned by it). */
+/* Release a context: waits for its staging copies, frees the pinned buffers
+ * and destroys its cached graphs. */
 int voge_destroy(voge_ctx_t* ctx);
 
 /* Bytes of workspace needed for N kernels, C channels and this camera's image

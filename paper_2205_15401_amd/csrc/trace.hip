@@ -1,27 +1,29 @@
 // trace.hip -- per-pixel ray tracing and K-nearest selection (k_select),
-// erf-sum transmittance and blending (k_blend), and the backward (k_bwd).
+// erf-sum transmittance and blending (k_blend), and the backward (k_bwd_pix,
+// k_bwd_red).
 //
-// Every kernel maps one workgroup of 256 lanes to one 16x16 screen tile;
-// each wave owns an 8x8 block and each lane one pixel.  Per-pixel kept lists
-// travel between the kernels through the workspace, slot-major:
-// list[s * S + q] with q = tile * 256 + lane-in-tile and S = n_tiles * 256,
-// so every list access of a wave is one contiguous segment.
+// Every kernel maps one workgroup of 256 lanes to one 16x16 screen tile of
+// some item of the batch; each wave owns an 8x8 block and each lane one
+// pixel.  Per-pixel kept lists travel between the kernels through the
+// workspace, slot-major per item: list[s * S + q] with q = tile * 256 +
+// lane-in-tile and S = n_tiles * 256, so every list access of a wave is one
+// contiguous segment.
 //
-//   k_select -- coarse stage + ray tracing + fine selection.  The tile
-//     streams the depth-ordered kernel list in chunks of 256: the lanes test
-//     the chunk's screen bounds against the tile, compact the survivors into
-//     LDS, and every pixel traces them in depth-bound order (VoGE Sec. 3.3,
-//     Eq. 6; App. A.1) along D' = (i - O_y, j - O_x, F):
+//   k_select -- coarse stage + ray tracing + fine selection.  Each wave
+//     scans its item's depth-ordered records 64 at a time, keeps those whose
+//     screen box meets its block, and every pixel traces them in order
+//     (VoGE Sec. 3.3, Eq. 6; App. A.1) along D' = (i - O_y, j - O_x, F):
 //         a = D'^T S D',  b = D'^T S M,  l = b / a,  -2q = M^T S M - b l   (FP64)
 //     and keeps e^q > eta, l > 0, the K smallest l (Sec. 3.3; App. A.3).
 //     A candidate is a 64-bit key: the bits of l (a positive double) with the
 //     low 24 bits replaced by the kernel's rank, so one unsigned compare
 //     orders by (l, rank) and the K-buffer is a register insertion network.
-//     A pixel is done once its K-th entry is nearer than the next kernel's
-//     depth bound; the tile stops when all its pixels are done.
+//     A pixel is done once its K-th entry is nearer than the next record's
+//     depth floor; the wave stops when all its pixels are done.
 //   k_blend -- E_k = sum_m e^{q_m} Phi((l_k - l_m) sqrt(a_m)) (Eq. 7 at
 //     t = l_k; App. A.2), T_k = exp(-E_k), W_k = T_k e^{q_k}, C = sum W_k c_k (Eq. 8).
-//   k_bwd -- gradients of C with the kept sets fixed (formulas above k_bwd).
+//   k_bwd_pix, k_bwd_red -- gradients of C with the kept sets fixed (formulas
+//     above bwd_pix_body).
 //
 // D' is F times the paper's D: l * D', q, the erf arguments and every weight
 // are unchanged by that scale; only l itself scales.

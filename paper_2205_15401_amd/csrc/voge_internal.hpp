@@ -1,13 +1,15 @@
 // voge_internal.hpp -- records, constants and device helpers shared by the
 // HIP sources of libvoge (gfx950 / CDNA4).  Not part of the public C ABI.
 //
-// Data layout in HBM (all per-camera, written by the prep kernels):
-//   CullRec  cull[N]  16 B  screen bbox + depth bound, in depth-bound order
+// Data layout in HBM (per item -- one kernel set seen by one camera --,
+// written by the prep kernels; the items' slices are concatenated):
+//   CullRec  cull[N]  16 B  screen bbox + depth-bucket floor, in depth order
 //   TraceRec rec[N]   96 B  per-kernel ray-tracing coefficients, same order
 //   GeoRec   geo[N]   72 B  camera-space centre and inverse covariance (backward)
-// The order is ascending in the lower bound of the ray parameter of the
-// kernel's eta-ellipsoid, so a tile can stop scanning once every pixel holds
-// K kernels that are all nearer than the next bound.
+// Within an item the order is ascending in the lower bound of the ray
+// parameter of the kernel's eta-ellipsoid (bucketed), so a block of pixels
+// can stop scanning once every pixel holds K kernels that are all nearer
+// than the next record's floor.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
