@@ -49,11 +49,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def source_digest() -> str:
+def code_text(text: str) -> str:
+    """Source text without comments and blank space: the digest of the kernel
+    code does not change when only comments do."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def source_digest(texts=None) -> str:
+    """Digest of the trace kernels' code (trace.hip and voge_internal.hpp)."""
     h = hashlib.sha256()
     for f in ("trace.hip", "voge_internal.hpp"):
-        with open(os.path.join(ROOT, "paper_2205_15401_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        if texts is None:
+            with open(os.path.join(ROOT, "paper_2205_15401_amd", "csrc", f)) as fh:
+                t = fh.read()
+        else:
+            t = texts[f]
+        h.update(code_text(t).encode())
     return h.hexdigest()[:16]
 
 
