@@ -521,19 +521,23 @@ __device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile) {
             dmd[k] = g[k] * T;
         }
     }
-    // pair loop: m streams from the list; its sums over k go to the scratch list
-    // slot m+1 is loaded while slot m is computed
+    // pair loop: m streams from the list (slot m+1 is loaded while slot m is
+    // computed); after the sums over k, slot m's scalars are complete except
+    // the k-side part of dL/dl, which goes to its own list at the end:
+    //   dq = (g_m T_m + sum_k dE_k Phi_km) m_m,  dl = -sum_k t_km (+ dl[m] later),
+    //   da = sum_k dx_km d_km / (2 s_m),  W = T_m m_m
     double ln = keff > 0 ? pl[0] : 0.0;
-    float mn = keff > 0 ? pm[0] : 0.f, sn = keff > 0 ? ps[0] : 1.f;
+    float mn = keff > 0 ? pm[0] : 0.f, sn = keff > 0 ? ps[0] : 1.f, tn = keff > 0 ? pT[0] : 0.f;
     for (int m = 0; m < kmax; ++m) {
         const bool in = m < keff;
         const size_t o = (size_t)m * S;
         const double lm = ln;
-        const float mm = mn, sm = sn;
+        const float mm = mn, sm = sn, tm = tn;
         const bool nin = m + 1 < keff;
         ln = nin ? pl[o + S] : 0.0;
         mn = nin ? pm[o + S] : 0.f;
         sn = nin ? ps[o + S] : 1.f;
+        tn = nin ? pT[o + S] : 0.f;
         const float hs = 0.5f / sm;
         float acc_dm = 0.f, acc_dl = 0.f, acc_da = 0.f;
 #pragma unroll
@@ -554,18 +558,16 @@ __device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile) {
                 }
             }
         }
-        if (in) pbw[o] = make_float4(acc_dm, acc_dl, acc_da, 0.f);
-    }
-    // per-pair scalars: dq = dL/dq, dl = dL/dl (D' units), da = dL/da, W
+        float dmd_m = 0.f;                       // dmd[m], m uniform in the wave
 #pragma unroll
-    for (int k = 0; k < KB; ++k) {
-        if (k < keff) {
-            const size_t o = (size_t)k * S;
-            const float4 acc = pbw[o];
-            const float mk = pm[o];
-            pbw[o] = make_float4((dmd[k] + acc.x) * mk, dl[k] + acc.y, acc.z, pT[o] * mk);
-        }
+        for (int k = 0; k < KB; ++k) dmd_m = k == m ? dmd[k] : dmd_m;
+        if (in) pbw[o] = make_float4((dmd_m + acc_dm) * mm, acc_dl, acc_da, tm * mm);
     }
+    // the k-side part of dL/dl of each slot
+    float* pbl = A.bwl + P.q;
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+        if (k < keff) pbl[(size_t)k * S] = dl[k];
 }
 
 // Backward, tile phase: group the tile's pairs by kernel and reduce them.
@@ -592,6 +594,7 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
     const size_t p = (size_t)P.pi * A.W + P.pj;
     const double* pl = A.kl_l + P.q;
     float4* pbw = A.bw + P.q;
+    const float* pbl = A.bwl + P.q;
     const float* Gp = A.grad_image + p * C;
     PairRec* tile_pairs = A.pairs + (size_t)tile * TILE_THREADS * A.K;
     __syncthreads();   // table initialised
@@ -661,7 +664,7 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
                 const float4 sc = pbw[o];
                 PairRec r;
                 r.dq = sc.x;
-                r.dl = sc.y;
+                r.dl = sc.y + pbl[o];
                 r.da = sc.z;
                 r.w = sc.w;
                 r.l = pl[o];
@@ -674,7 +677,7 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
                 const int rank = A.kl_r[P.q + o];
                 const float4 sc = pbw[o];
                 double out[9];
-                pair_chain(A.geo[rank], P.u, P.v, (double)A.F, pl[o], sc.x, sc.y, sc.z, out, gD);
+                pair_chain(A.geo[rank], P.u, P.v, (double)A.F, pl[o], sc.x, sc.y + pbl[o], sc.z, out, gD);
 #pragma unroll
                 for (int e = 0; e < 3; ++e) unsafeAtomicAdd(&A.gM[(size_t)rank * 3 + e], (float)out[e]);
 #pragma unroll
