@@ -196,6 +196,7 @@ BatchPlan plan_batch(const ItemShape* shapes, int n) {
         it.list_off = p.total_list;
         it.attr_off = p.total_attr;
         p.total_kern += it.s.N;
+        p.max_n = std::max(p.max_n, it.s.N);
         p.total_tiles += it.n_tiles;
         p.total_pblk += it.n_pblk;
         p.total_epi += it.n_epi;
@@ -435,8 +436,8 @@ int launch_compute(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, 
     if (fwd_part) {
         {
             ProfScope ps = scope("prep");
-            voge::launch_prep(b, p.total_pblk, p.total_kern, w.keys, w.vals, w.keys2, w.vals2, w.hist, w.cull, w.rec,
-                              w.geo, s);
+            voge::launch_prep(b, p.total_pblk, p.total_kern, p.max_n, w.keys, w.vals, w.keys2, w.vals2, w.hist,
+                              w.cull, w.rec, w.geo, s);
             if (int rc = hip_check(hipGetLastError(), "prep launch")) return rc;
         }
         {

@@ -297,6 +297,43 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(const uint32_t* _
     }
 }
 
+// Small items: one workgroup sorts an item's keys in LDS.  The values are
+// the item-local indices, so (key << 32 | index) are distinct and a bitonic
+// network over them yields exactly the stable order of the radix sort.
+constexpr int ISORT_MAX = 4096;
+constexpr int ISORT_THREADS = 1024;
+
+__global__ __launch_bounds__(ISORT_THREADS) void k_sort_items(BatchDev B, uint32_t* __restrict__ keys,
+                                                               uint32_t* __restrict__ vals) {
+    __shared__ uint64_t s[ISORT_MAX];
+    const ItemDev& it = B.items[blockIdx.x];
+    const int N = it.t.N, k0 = it.kern_start, tid = threadIdx.x;
+    if (N <= 1) return;
+    int n2 = 2;
+    while (n2 < N) n2 <<= 1;
+    for (int i = tid; i < n2; i += ISORT_THREADS)
+        s[i] = i < N ? ((uint64_t)keys[k0 + i] << 32) | vals[k0 + i] : ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= n2; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = tid; i < (n2 >> 1); i += ISORT_THREADS) {
+                const int lo = 2 * i - (i & (stride - 1)), hi = lo + stride;
+                const uint64_t a = s[lo], b = s[hi];
+                const bool ascending = (lo & size) == 0;
+                if ((a > b) == ascending) {
+                    s[lo] = b;
+                    s[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = tid; i < N; i += ISORT_THREADS) {
+        keys[k0 + i] = (uint32_t)(s[i] >> 32);
+        vals[k0 + i] = (uint32_t)s[i];
+    }
+}
+
 __global__ void k_fill_u32(uint32_t* __restrict__ p, size_t n, uint32_t v) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -339,12 +376,20 @@ void launch_init(const InitPack& pack, int first, int count, bool from_args, Ite
                        pblk_item, epi_item, hdr, clear_status ? 1 : 0, clear_header ? 1 : 0);
 }
 
-void launch_prep(const BatchDev& b, int total_pblk, int total_kern, uint32_t* keys, uint32_t* vals, uint32_t* keys2,
-                 uint32_t* vals2, uint32_t* hist, CullRec* cull, TraceRec* rec, GeoRec* geo, hipStream_t s) {
+void launch_prep(const BatchDev& b, int total_pblk, int total_kern, int max_n, uint32_t* keys, uint32_t* vals,
+                 uint32_t* keys2, uint32_t* vals2, uint32_t* hist, CullRec* cull, TraceRec* rec, GeoRec* geo,
+                 hipStream_t s) {
     if (total_kern <= 0) return;
     hipLaunchKernelGGL(k_prep_keys, dim3(total_pblk), dim3(PREP_THREADS), 0, s, b, keys, vals);
-    // four stable 8-bit passes: keys/vals -> keys2/vals2 -> keys/vals -> ...
     const int N = total_kern;
+    const int blocks = (N + PREP_THREADS - 1) / PREP_THREADS;
+    if (max_n <= ISORT_MAX) {
+        // every item sorts in one workgroup's LDS
+        hipLaunchKernelGGL(k_sort_items, dim3(b.n_items), dim3(ISORT_THREADS), 0, s, b, keys, vals);
+        hipLaunchKernelGGL(k_prep_records, dim3(blocks), dim3(PREP_THREADS), 0, s, b, N, keys, vals, cull, rec, geo);
+        return;
+    }
+    // four stable 8-bit passes: keys/vals -> keys2/vals2 -> keys/vals -> ...
     const int nblk = sort_blocks(N);
     uint32_t* kin = keys;
     uint32_t* vin = vals;
@@ -360,7 +405,6 @@ void launch_prep(const BatchDev& b, int total_pblk, int total_kern, uint32_t* ke
         uint32_t* t = kin; kin = kout; kout = t;
         t = vin; vin = vout; vout = t;
     }
-    const int blocks = (N + PREP_THREADS - 1) / PREP_THREADS;
     hipLaunchKernelGGL(k_prep_records, dim3(blocks), dim3(PREP_THREADS), 0, s, b, N, kin, vin, cull, rec, geo);
 }
 

@@ -127,7 +127,7 @@ struct GroupPlan {
 struct BatchPlan {
     std::vector<ItemPlan> items;     // table order (grouped by K-buffer depth)
     std::vector<GroupPlan> groups;
-    int total_kern = 0, total_tiles = 0, total_pblk = 0, total_epi = 0;
+    int total_kern = 0, total_tiles = 0, total_pblk = 0, total_epi = 0, max_n = 0;
     size_t total_list = 0, total_attr = 0;
     int item_bits = 0, sort_blocks = 0;
     size_t off_items, off_tile_item, off_pblk_item, off_epi_item;
@@ -157,8 +157,9 @@ void launch_init(const InitPack& pack, int first, int count, bool from_args, Ite
                  int* pblk_item, int* epi_item, WsHeader* hdr, bool clear_status, bool clear_header, hipStream_t s);
 
 void launch_fill_u32(void* p, size_t n, uint32_t v, hipStream_t s);
-void launch_prep(const BatchDev& b, int total_pblk, int total_kern, uint32_t* keys, uint32_t* vals, uint32_t* keys2,
-                 uint32_t* vals2, uint32_t* hist, CullRec* cull, TraceRec* rec, GeoRec* geo, hipStream_t s);
+void launch_prep(const BatchDev& b, int total_pblk, int total_kern, int max_n, uint32_t* keys, uint32_t* vals,
+                 uint32_t* keys2, uint32_t* vals2, uint32_t* hist, CullRec* cull, TraceRec* rec, GeoRec* geo,
+                 hipStream_t s);
 
 hipError_t launch_select(const GroupDev& g, int kb, hipStream_t s);
 hipError_t launch_blend(const GroupDev& g, int kb, hipStream_t s);
