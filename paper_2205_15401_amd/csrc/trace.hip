@@ -61,17 +61,59 @@ struct PixelCtx {
     size_t q;     // list index
 };
 
-__device__ __forceinline__ PixelCtx pixel_of(int tile, int ntx, int H, int W, float cx, float cy) {
-    const int tid = threadIdx.x, wave = tid / WAVE, lane = tid % WAVE;
+// Pixel `slot` (0..255) of a tile: slot s sits in the 8x8 block s / 64 at
+// row (s % 64) / 8, column s % 8 of that block; its lists live at
+// tile * 256 + s.
+__device__ __forceinline__ PixelCtx pixel_at(int tile, int slot, int ntx, int H, int W, float cx, float cy) {
+    const int blk = slot / WAVE, within = slot % WAVE;
     const int ti0 = (tile / ntx) * TILE, tj0 = (tile % ntx) * TILE;
     PixelCtx P;
-    P.pi = ti0 + (wave >> 1) * 8 + (lane >> 3);
-    P.pj = tj0 + (wave & 1) * 8 + (lane & 7);
+    P.pi = ti0 + (blk >> 1) * 8 + (within >> 3);
+    P.pj = tj0 + (blk & 1) * 8 + (within & 7);
     P.valid = P.pi < H && P.pj < W;
     P.u = (double)P.pi - (double)cy;
     P.v = (double)P.pj - (double)cx;
-    P.q = (size_t)tile * TILE_THREADS + tid;
+    P.q = (size_t)tile * TILE_THREADS + slot;
     return P;
+}
+
+// The lane's own pixel: slot = lane id in the workgroup.
+__device__ __forceinline__ PixelCtx pixel_of(int tile, int ntx, int H, int W, float cx, float cy) {
+    return pixel_at(tile, threadIdx.x, ntx, H, W, cx, cy);
+}
+
+// The tile's pixels regrouped by kept count (largest first), so that each
+// wave's pixels have similar counts: the per-pixel pair loops run to the
+// wave's largest count.  Returns the slot this lane works on.  Which lane
+// computes which pixel does not change any result.
+__device__ __forceinline__ int balanced_slot(const TraceArgs& A, int tile, int ntx) {
+    __shared__ int s_bin[MAX_K + 2];
+    __shared__ int s_perm[TILE_THREADS];
+    const int tid = threadIdx.x;
+    const PixelCtx P = pixel_of(tile, ntx, A.H, A.W, A.cx, A.cy);
+    const int ke = P.valid ? A.keff[P.q] : 0;
+    const int bin = MAX_K - ke;                  // descending counts
+    if (tid < MAX_K + 2) s_bin[tid] = 0;
+    __syncthreads();
+    const int pos = atomicAdd(&s_bin[bin], 1);
+    __syncthreads();
+    if (tid < WAVE) {
+        // exclusive scan of the MAX_K + 1 bins by the first wave (two per lane)
+        const int b0 = 2 * tid, b1 = 2 * tid + 1;
+        const int c0 = b0 <= MAX_K ? s_bin[b0] : 0, c1 = b1 <= MAX_K ? s_bin[b1] : 0;
+        int run = c0 + c1;
+        for (int off = 1; off < WAVE; off <<= 1) {
+            const int y = __shfl_up(run, off);
+            if (tid >= off) run += y;
+        }
+        const int ex = run - c0 - c1;
+        if (b0 <= MAX_K) s_bin[b0] = ex;
+        if (b1 <= MAX_K) s_bin[b1] = ex + c0;
+    }
+    __syncthreads();
+    s_perm[s_bin[bin] + pos] = tid;
+    __syncthreads();
+    return s_perm[tid];
 }
 
 // b / a for a > 0: hardware reciprocal estimate, two Newton steps and a
@@ -268,7 +310,7 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
 template <int KB>
 __device__ __forceinline__ void blend_body(const TraceArgs& A, int tile) {
     const int ntx = (A.W + TILE - 1) / TILE;
-    const PixelCtx P = pixel_of(tile, ntx, A.H, A.W, A.cx, A.cy);
+    const PixelCtx P = pixel_at(tile, balanced_slot(A, tile, ntx), ntx, A.H, A.W, A.cx, A.cy);
     const size_t S = A.S;
     const int keff = P.valid ? A.keff[P.q] : 0;
     const int kmax = wave_max_keff(keff);
@@ -452,9 +494,8 @@ __device__ __forceinline__ void flush_values(const TraceArgs& A, int rank, const
 // Backward, pixel phase: per-pair scalars (dq, dl, da, W) into the scratch list.
 template <int KB>
 __device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile) {
-    const int tid = threadIdx.x;
     const int ntx = (A.W + TILE - 1) / TILE;
-    const PixelCtx P = pixel_of(tile, ntx, A.H, A.W, A.cx, A.cy);
+    const PixelCtx P = pixel_at(tile, balanced_slot(A, tile, ntx), ntx, A.H, A.W, A.cx, A.cy);
     const size_t S = A.S;
     const int C = A.C;
 
