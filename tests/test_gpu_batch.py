@@ -343,3 +343,73 @@ def test_uneven_batch_full_size_matches_the_oracle():
     assert batch.status() == [0] * len(items)
     for i, (si, cam, K, eta) in enumerate(items):
         check_item(batch, i, scenes[si], cam, K, eta, grads[i], pixs[i], frefs[i])
+
+
+def test_repeated_calls_are_deterministic():
+    """Two identical calls: images, weight sums and kept lists bit for bit;
+    gradients (float atomics in any order) within the oracle's floors."""
+    rng = np.random.default_rng(41)
+    scenes, items = mixed_batch(rng)
+    dev = torch.device("cuda:0")
+    dscenes = [dev_scene(sc) for sc in scenes]
+    its = [(si, R.camera_struct(cam), K, eta) for si, cam, K, eta in items]
+    runs = []
+    Gs = [rng.standard_normal((cam.height, cam.width, scenes[si].attrs.shape[1])).astype(np.float32)
+          for si, cam, K, eta in items]
+    for _ in range(2):
+        b = R.Batch(dscenes, its, dev, backward=True, with_wsum=True, with_kept=True, with_camera=True)
+        for i, G in enumerate(Gs):
+            b.set_grad_image(i, torch.from_numpy(G))
+        b.run(forward=True, backward=True)
+        torch.cuda.synchronize()
+        runs.append(b)
+    a, b = runs
+    for i, (si, cam, K, eta) in enumerate(items):
+        assert torch.equal(a.images[i], b.images[i]) and torch.equal(a.wsums[i], b.wsums[i])
+        assert torch.equal(a.kepts[i], b.kepts[i])
+        assert_grads_close(((a.grad_means[i], b.grad_means[i]), (a.grad_covs[i], b.grad_covs[i]),
+                            (a.grad_attrs[i], b.grad_attrs[i]), (a.grad_cameras[i], b.grad_cameras[i])),
+                           grad_floors(scenes[si], cam, K, eta, Gs[i]), f"item {i}: repeat")
+
+
+def test_channel_counts_through_both_attribute_paths():
+    """C = 1 and 64 and 1024 (the maximum) and 4: attribute gathers take the
+    four-channel path when C is a multiple of 4, the scalar path otherwise,
+    and the backward reduction makes one pass per 8 channels."""
+    rng = np.random.default_rng(42)
+    scenes, items = [], []
+    for C, size in ((1, 40), (4, 32), (64, 24), (1024, 16)):
+        sc = S.isotropic_scene(rng, 200, C)
+        sc.attrs = rng.standard_normal((200, C)).astype(np.float32)
+        scenes.append(sc)
+        items.append((len(scenes) - 1, S.identity_camera(size), 12, 0.01))
+    batch, grads, pixs, frefs, _ = run_checked_batch(scenes, items, rng, n_pix=100_000)
+    for i, (si, cam, K, eta) in enumerate(items):
+        check_item(batch, i, scenes[si], cam, K, eta, grads[i], pixs[i], frefs[i])
+
+
+def test_device_calls_reject_bad_workspaces_and_pointers():
+    dev = torch.device("cuda:0")
+    ctx = R.context(dev)
+    sc = S.config_small().scene
+    m, c, a = dev_scene(sc)
+    cs = R.camera_struct(S.identity_camera(32))
+    it = nat.VogeItem()
+    it.means, it.covs, it.attrs = m.data_ptr(), c.data_ptr(), a.data_ptr()
+    it.N, it.C = sc.n, 3
+    it.camera = cs
+    it.params = R.params_struct(8, 0.01)
+    img = torch.empty((32, 32, 3), device=dev)
+    it.image = img.data_ptr()
+    need = nat.voge_batch_workspace_size([it], False)
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    s = torch.cuda.current_stream().cuda_stream
+    with pytest.raises(nat.VogeError) as e:
+        nat.voge_render_batch(ctx, [it], nat.VOGE_FORWARD, ws.data_ptr(), need - 256, s)
+    assert e.value.code == nat.VOGE_ENOSPACE
+    with pytest.raises(nat.VogeError) as e:
+        nat.voge_render_batch(ctx, [it], nat.VOGE_BACKWARD, ws.data_ptr(), need, s)   # no gradient pointers
+    assert e.value.code == nat.VOGE_EINVAL
+    nat.voge_render_batch(ctx, [it], nat.VOGE_FORWARD, ws.data_ptr(), need, s)
+    torch.cuda.synchronize()
+    assert torch.isfinite(img).all()
