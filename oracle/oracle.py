@@ -190,6 +190,41 @@ def backward(means, covs, attrs, cam_vec, H: int, W: int, K: int, grad, eta: flo
     return r
 
 
+class SampleResult:
+    """Per-kernel outputs of the oracle sampler (float64)."""
+
+    def __init__(self, N, C):
+        self.num = np.zeros((N, C))       # sum_p W_pk phi_p
+        self.den = np.zeros(N)            # sum_p W_pk
+        self.alpha = np.zeros((N, C))     # num / den, 0 where den == 0
+        self.fwd = None                   # the forward whose kept sets were used
+
+
+def sample(means, covs, cam_vec, H: int, W: int, K: int, features, eta: float = 0.01,
+           threads: int = 0) -> SampleResult:
+    """Inverse reconstruction of Sec. 3.4 (Eq. 10): every kernel takes the
+    W-weighted mean of the feature map over the pixels that keep it,
+    alpha_k = sum_p W_pk phi_p / sum_p W_pk, with W_pk = T(l_k) e^{q_k} the
+    kernel-to-pixel weight of Eq. 8 (the forward's kept records).  features is
+    (H, W, C) or (H*W, C).  A kernel that no pixel keeps has den = 0 and is
+    given alpha = 0 (the paper does not define the empty quotient)."""
+    m = _f64(means)
+    N = m.shape[0]
+    phi = np.asarray(features, np.float64).reshape(H * W, -1)
+    C = phi.shape[1]
+    fwd = forward(m, covs, np.zeros((N, 1)), cam_vec, H, W, K, eta, threads=threads)
+    r = SampleResult(N, C)
+    r.fwd = fwd
+    pix, slot = np.nonzero(fwd.kept_idx >= 0)
+    k = fwd.kept_idx[pix, slot]
+    w = fwd.kept_rec[pix, slot, 4]
+    np.add.at(r.num, k, w[:, None] * phi[pix])
+    np.add.at(r.den, k, w)
+    seen = r.den > 0
+    r.alpha[seen] = r.num[seen] / r.den[seen, None]
+    return r
+
+
 def quadrature(means, covs, cam_vec, H: int, W: int, K: int, eta: float = 0.01,
                pixels: Optional[Sequence[int]] = None, n_samples: int = 100_001, threads: int = 0):
     """Exact outer integral of Eq. 1 for each pixel's kept set.

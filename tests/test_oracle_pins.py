@@ -434,3 +434,75 @@ def test_p8_gradients_match_finite_differences():
     check("cv", cv, g.camera, 1e-6)
     # both gradient paths (through T(l_k) and through e^{q_k}) are exercised
     assert np.abs(g.means).max() > 0 and np.abs(g.covs).max() > 0 and np.abs(g.camera[12:]).max() > 0
+
+
+# ---------------------------------------------------------------------------
+# P9: the sampler (Sec. 3.4, Eq. 10)
+# ---------------------------------------------------------------------------
+
+def test_p9_sampler_against_one_hot_renders():
+    """Rendering one-hot attributes (attrs = I) gives image[p, j] = W_pj
+    through the blend of Eq. 8, a path the sampler does not use: the column
+    sums are the denominators and image^T phi the numerators of Eq. 10."""
+    means, covs, _ = tiny_scene(31, n=12)
+    N = means.shape[0]
+    R = rot([0.2, 1, 0.1], 0.3)
+    cv = cam_vec(R, (0.02, -0.03, 0.1), F=24.0, cx=11.0, cy=13.0)
+    H, W = 26, 22
+    rng = np.random.default_rng(8)
+    phi = rng.standard_normal((H, W, 3))
+    s = O.sample(means, covs, cv, H, W, 5, phi)
+    onehot = O.forward(means, covs, np.eye(N), cv, H, W, 5)
+    den = onehot.image.sum(axis=0)
+    num = onehot.image.T @ phi.reshape(H * W, 3)
+    assert (den > 0).sum() >= N - 2
+    np.testing.assert_allclose(s.den, den, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(s.num, num, rtol=1e-12, atol=1e-13)
+    seen = den > 0
+    np.testing.assert_allclose(s.alpha[seen], num[seen] / den[seen, None], rtol=1e-11)
+
+
+def test_p9_sampler_constant_features_and_empty_kernels():
+    """A constant feature map samples to that constant on every kernel some
+    pixel keeps; a kernel behind the camera is kept nowhere and gets den 0,
+    alpha 0."""
+    means, covs, _ = tiny_scene(32, n=7)
+    means = np.vstack([means, [[0.0, 0.0, -3.0]]])
+    covs = np.vstack([covs, covs[:1]])
+    cv = cam_vec(F=24.0, cx=12.0, cy=12.0)
+    phi = np.broadcast_to(np.array([0.7, -2.0]), (24, 24, 2))
+    s = O.sample(means, covs, cv, 24, 24, 4, phi)
+    seen = s.den > 0
+    assert seen[:7].sum() >= 5 and not seen[7]
+    np.testing.assert_allclose(s.alpha[seen], np.broadcast_to([0.7, -2.0], (seen.sum(), 2)), rtol=1e-13)
+    assert np.all(s.alpha[7] == 0.0) and s.den[7] == 0.0
+
+
+def test_p9_sampler_recovers_the_centre_of_a_symmetric_footprint():
+    """A lone axis-aligned kernel on the optical axis has a footprint that is
+    mirror-symmetric in rows and columns about the principal point; on a grid
+    symmetric about it, sampling the pixel coordinates (row, column) returns
+    the principal point (cy, cx).  cy != cx, so swapped axes fail."""
+    H, W, cy, cx = 65, 49, 32.0, 24.0
+    cv = cam_vec(F=40.0, cx=cx, cy=cy)
+    means = np.array([[0.0, 0.0, 3.0]])
+    covs = packed(np.diag([0.3, 0.15, 0.2]) ** 2)[None]
+    ii, jj = np.meshgrid(np.arange(H, dtype=float), np.arange(W, dtype=float), indexing="ij")
+    phi = np.stack([ii, jj, (ii - cy) * (jj - cx)], axis=-1)
+    s = O.sample(means, covs, cv, H, W, 2, phi)
+    assert s.den[0] > 1.0
+    np.testing.assert_allclose(s.alpha[0], [cy, cx, 0.0], atol=1e-10)
+
+
+def test_p9_sampler_numerator_is_the_attribute_gradient():
+    """d/dc_k of sum_p <G_p, C_p> is sum_p W_pk G_p (Eq. 8 is linear in the
+    attributes): the numerator of Eq. 10 with phi = G, from the backward."""
+    job = S.config_small()
+    sc = job.scene
+    cv = job.camera.as_vector()
+    H, W = job.camera.height, job.camera.width
+    rng = np.random.default_rng(9)
+    G = rng.standard_normal((H, W, sc.attrs.shape[1]))
+    s = O.sample(sc.means, sc.covs, cv, H, W, 16, G)
+    b = O.backward(sc.means, sc.covs, sc.attrs, cv, H, W, 16, G)
+    np.testing.assert_allclose(s.num, b.attrs, rtol=1e-10, atol=1e-12 * np.abs(b.attrs).max())
