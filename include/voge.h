@@ -63,9 +63,10 @@ extern "C" {
 #define VOGE_STATUS_NOTSPD 1     /* some covariance was not SPD (skipped)      */
 #define VOGE_STATUS_NONFINITE 2  /* some centre or covariance was not finite   */
 
-/* Call flags.  voge_render_backward takes VOGE_REUSE_PREP alone;
- * voge_render_batch takes VOGE_FORWARD and/or VOGE_BACKWARD, optionally with
- * VOGE_REUSE_PREP (backward only), VOGE_GRAPH and VOGE_TUNED. */
+/* Call flags.  voge_render_backward and voge_sample take VOGE_REUSE_PREP
+ * alone; voge_render_batch takes VOGE_FORWARD with VOGE_BACKWARD or
+ * VOGE_SAMPLE or neither, or VOGE_BACKWARD or VOGE_SAMPLE alone, optionally
+ * with VOGE_REUSE_PREP (without VOGE_FORWARD), VOGE_GRAPH and VOGE_TUNED. */
 #define VOGE_REUSE_PREP 1     /* the workspace holds the preparation and kept
                                  lists of a forward of the same items          */
 #define VOGE_FORWARD 2        /* batch: render the images                      */
@@ -74,6 +75,8 @@ extern "C" {
                                  graph cached per shape (captured on first use) */
 #define VOGE_TUNED 16         /* batch: use the execution choices voge_tune_batch
                                  found for these shapes (defaults if none)     */
+#define VOGE_SAMPLE 32        /* batch: sample the feature maps onto the kernels
+                                 (Sec. 3.4, Eq. 10; see voge_sample)           */
 
 #define VOGE_MAX_BATCH 4096   /* items per voge_render_batch call              */
 
@@ -95,9 +98,11 @@ typedef struct voge_params {
 typedef struct voge_ctx voge_ctx_t;
 
 /* One render of a batch: a kernel set seen by a camera.  Pointers as in
- * voge_render_forward / voge_render_backward (device memory); outputs that a
- * call does not produce may be NULL.  Items may share kernel arrays (many
- * cameras of one scene) but not output buffers. */
+ * voge_render_forward / voge_render_backward / voge_sample (device memory);
+ * buffers that a call does not use may be NULL (attrs too, in a call with
+ * VOGE_SAMPLE alone).  C is the channel count of every per-channel array the
+ * call uses.  Items may share kernel arrays (many cameras of one scene) but
+ * not output buffers. */
 typedef struct voge_item {
     const float* means;       /* [N*3]                                          */
     const float* covs;        /* [N*6] packed xx, xy, xz, yy, yz, zz            */
@@ -114,6 +119,9 @@ typedef struct voge_item {
     float* grad_covs;         /* [N*6] out, required with VOGE_BACKWARD         */
     float* grad_attrs;        /* [N*C] out, required with VOGE_BACKWARD         */
     float* grad_camera;       /* [15] out, optional                             */
+    const float* features;    /* [H*W*C] in, required with VOGE_SAMPLE          */
+    float* sampled;           /* [N*C] out, required with VOGE_SAMPLE           */
+    float* sample_weight;     /* [N] out, optional                              */
 } voge_item_t;
 
 /* Create a library context bound to HIP device `device`.  Host memory only:
@@ -129,8 +137,9 @@ int voge_create(voge_ctx_t** ctx, int device);
 int voge_destroy(voge_ctx_t* ctx);
 
 /* Bytes of workspace needed for N kernels, C channels and this camera's image
- * size; with_backward = 1 sizes it for voge_render_backward as well (the
- * forward uses a prefix of the same layout, so one workspace serves both).
+ * size; with_backward = 1 sizes it for voge_render_backward and voge_sample as
+ * well (the forward uses a prefix of the same layout, so one workspace serves
+ * all three).
  * The workspace must be device memory aligned to 256 bytes. */
 int voge_workspace_size(int N, int C, const voge_camera_t* cam, const voge_params_t* params, int with_backward,
                         size_t* bytes);
@@ -161,9 +170,29 @@ int voge_render_backward(voge_ctx_t* ctx, const float* means, const float* covs,
                          float* grad_means, float* grad_covs, float* grad_attrs, float* grad_camera, int flags,
                          void* workspace, size_t workspace_bytes, void* stream);
 
+/* Sampler: the inverse reconstruction of Sec. 3.4 (Eq. 10).  Every kernel
+ * takes the W-weighted mean of a feature map phi over the pixels that keep it,
+ *   alpha_k = sum_p W_pk phi_p / sum_p W_pk,   W_pk = T(l_k) e^{q_k} (Eq. 8),
+ * with the kept sets and weights of voge_render_forward for the same kernels,
+ * camera and params.
+ *   features       [H*W*C] in: phi, HWC like the images
+ *   sampled        [N*C] out: alpha; 0 for a kernel that no pixel keeps (the
+ *                  paper leaves that quotient undefined)
+ *   sample_weight  [N] out, optional (NULL): sum_p W_pk, 0 where none
+ *   flags          VOGE_REUSE_PREP when `workspace` still holds the forward of
+ *                  voge_render_forward for the same kernels, camera and params
+ *                  (its kept sets and weights are reused), else 0
+ *   workspace      >= voge_workspace_size(..., 1)
+ * Per kernel, the sums are accumulated in float32 with atomic adds of
+ * per-tile partials (their order may vary from call to call).
+ * Errors: VOGE_EINVAL, VOGE_ENOSPACE, VOGE_EHIP. */
+int voge_sample(voge_ctx_t* ctx, const float* means, const float* covs, int N, int C, const voge_camera_t* cam,
+                const voge_params_t* params, const float* features, float* sampled, float* sample_weight, int flags,
+                void* workspace, size_t workspace_bytes, void* stream);
+
 /* Bytes of workspace for a batch of n_items (1 <= n_items <= VOGE_MAX_BATCH);
- * with_backward = 1 sizes it for VOGE_BACKWARD too.  Only the shapes (N, C,
- * camera size, K) of the items matter. */
+ * with_backward = 1 sizes it for VOGE_BACKWARD and VOGE_SAMPLE too.  Only
+ * the shapes (N, C, camera size, K) of the items matter. */
 int voge_batch_workspace_size(const voge_item_t* items, int n_items, int with_backward, size_t* bytes);
 
 /* Render a batch of items in one sequence of launches: every item's kernels
@@ -173,14 +202,17 @@ int voge_batch_workspace_size(const voge_item_t* items, int n_items, int with_ba
  * voge_render_backward on that item alone, up to the order of floating-point
  * accumulation and the order of kernels at exactly equal depth.
  *   items      host array [n_items], read before return
- *   flags      VOGE_FORWARD, VOGE_BACKWARD or both; VOGE_REUSE_PREP with
- *              VOGE_BACKWARD alone when `workspace` holds a forward of the
- *              same items (shapes, kernels, cameras, params) -- then the kept
- *              sets of that forward are used; VOGE_GRAPH replays the launches
+ *   flags      VOGE_FORWARD, VOGE_BACKWARD, VOGE_SAMPLE, or VOGE_FORWARD with
+ *              one of the other two (VOGE_BACKWARD and VOGE_SAMPLE share
+ *              scratch and do not combine); VOGE_REUSE_PREP with
+ *              VOGE_BACKWARD or VOGE_SAMPLE alone when `workspace` holds a
+ *              forward of the same items (shapes, kernels, cameras, params) --
+ *              then the kept sets of that forward are used; VOGE_GRAPH replays the launches
  *              from a HIP graph that the context caches per (workspace,
  *              flags, item shapes); it needs a stream other than the null
  *              stream, and the graph is captured on that stream at first use.
- *   workspace  >= voge_batch_workspace_size(items, n_items, VOGE_BACKWARD set)
+ *   workspace  >= voge_batch_workspace_size(items, n_items, VOGE_BACKWARD or
+ *              VOGE_SAMPLE set)
  * The item table is staged through the context: two calls on one context may
  * run from different threads, but calls in flight on one workspace race.
  * Errors: VOGE_EINVAL (an item's shapes or pointers, flags), VOGE_ENOSPACE,

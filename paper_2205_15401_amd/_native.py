@@ -25,13 +25,14 @@ VOGE_FORWARD = 2
 VOGE_BACKWARD = 4
 VOGE_GRAPH = 8
 VOGE_TUNED = 16
+VOGE_SAMPLE = 32
 VOGE_MAX_BATCH = 4096
 
 EXPORTS = [
     "voge_create", "voge_destroy", "voge_workspace_size", "voge_render_forward",
     "voge_render_backward", "voge_status", "voge_last_error", "voge_version", "voge_debug_phi",
     "voge_profile_enable", "voge_profile_read", "voge_batch_workspace_size", "voge_render_batch",
-    "voge_batch_status", "voge_tune_batch", "voge_tune_save", "voge_tune_load",
+    "voge_batch_status", "voge_tune_batch", "voge_tune_save", "voge_tune_load", "voge_sample",
 ]
 
 
@@ -50,7 +51,8 @@ class VogeItem(ctypes.Structure):
                 ("N", ctypes.c_int32), ("C", ctypes.c_int32), ("camera", VogeCamera), ("params", VogeParams),
                 ("image", ctypes.c_void_p), ("wsum", ctypes.c_void_p), ("kept", ctypes.c_void_p),
                 ("grad_image", ctypes.c_void_p), ("grad_means", ctypes.c_void_p), ("grad_covs", ctypes.c_void_p),
-                ("grad_attrs", ctypes.c_void_p), ("grad_camera", ctypes.c_void_p)]
+                ("grad_attrs", ctypes.c_void_p), ("grad_camera", ctypes.c_void_p),
+                ("features", ctypes.c_void_p), ("sampled", ctypes.c_void_p), ("sample_weight", ctypes.c_void_p)]
 
 
 class VogeTuneResult(ctypes.Structure):
@@ -88,6 +90,7 @@ def load(path: str = LIB_PATH):
         lib.voge_workspace_size.argtypes = [I, I, CamP, ParP, I, ctypes.POINTER(SZ)]
         lib.voge_render_forward.argtypes = [P, P, P, P, I, I, CamP, ParP, P, P, P, P, SZ, P]
         lib.voge_render_backward.argtypes = [P, P, P, P, I, I, CamP, ParP, P, P, P, P, P, I, P, SZ, P]
+        lib.voge_sample.argtypes = [P, P, P, I, I, CamP, ParP, P, P, P, I, P, SZ, P]
         lib.voge_status.argtypes = [P, ctypes.POINTER(ctypes.c_int32), P]
         lib.voge_last_error.argtypes = []
         lib.voge_last_error.restype = ctypes.c_char_p
@@ -153,6 +156,13 @@ def voge_render_backward(ctx, means, covs, attrs, N, C, cam, params, grad_image,
                                               ctypes.byref(params), grad_image, grad_means, grad_covs,
                                               grad_attrs, grad_camera, int(flags), workspace,
                                               int(workspace_bytes), stream))
+
+
+def voge_sample(ctx, means, covs, N, C, cam, params, features, sampled, sample_weight, flags, workspace,
+                workspace_bytes, stream) -> int:
+    return _check(load().voge_sample(ctx, means, covs, int(N), int(C), ctypes.byref(cam), ctypes.byref(params),
+                                     features, sampled, sample_weight, int(flags), workspace,
+                                     int(workspace_bytes), stream))
 
 
 def voge_status(workspace, stream) -> int:

@@ -102,12 +102,14 @@ int check_camera(const voge_camera_t* cam) {
     return VOGE_OK;
 }
 
+// attrs == nullptr with need_attrs false: a call that does not read them (the sampler).
 int check_common(const voge_ctx_t* ctx, const float* means, const float* covs, const float* attrs, int N, int C,
-                 const voge_camera_t* cam, const voge_params_t* params) {
+                 const voge_camera_t* cam, const voge_params_t* params, bool need_attrs = true) {
     if (!ctx) return fail(VOGE_EINVAL, "ctx is null");
     if (N < 0 || N >= voge::MAX_KERNELS) return fail(VOGE_EINVAL, "N must be in [0, 2^24)");
     if (C < 1 || C > 1024) return fail(VOGE_EINVAL, "C must be in [1, 1024]");
-    if (N > 0 && (!means || !covs || !attrs)) return fail(VOGE_EINVAL, "means, covs and attrs are required");
+    if (N > 0 && (!means || !covs)) return fail(VOGE_EINVAL, "means and covs are required");
+    if (N > 0 && need_attrs && !attrs) return fail(VOGE_EINVAL, "attrs is required");
     if (int rc = check_camera(cam)) return rc;
     if (!params) return fail(VOGE_EINVAL, "params is null");
     if (!(params->eta > 0.f && params->eta < 1.f)) return fail(VOGE_EINVAL, "eta must be in (0, 1)");
@@ -260,7 +262,9 @@ int validate_item(const voge_item_t& it, int flags, int i) {
     auto bad = [&](const char* what) { return fail(VOGE_EINVAL, "item " + std::to_string(i) + ": " + what); };
     if (it.N < 0 || it.N >= voge::MAX_KERNELS) return bad("N must be in [0, 2^24)");
     if (it.C < 1 || it.C > 1024) return bad("C must be in [1, 1024]");
-    if (it.N > 0 && (!it.means || !it.covs || !it.attrs)) return bad("means, covs and attrs are required");
+    if (it.N > 0 && (!it.means || !it.covs)) return bad("means and covs are required");
+    if (it.N > 0 && (flags & (VOGE_FORWARD | VOGE_BACKWARD)) && !it.attrs)
+        return bad("attrs is required with VOGE_FORWARD or VOGE_BACKWARD");
     if (int rc = check_camera(&it.camera)) return bad(g_err.c_str()), rc;
     if (!(it.params.eta > 0.f && it.params.eta < 1.f)) return bad("eta must be in (0, 1)");
     if (it.params.K < 1 || it.params.K > voge::MAX_K) return bad("K must be in [1, 64]");
@@ -270,8 +274,27 @@ int validate_item(const voge_item_t& it, int flags, int i) {
         if (it.N > 0 && (!it.grad_means || !it.grad_covs || !it.grad_attrs))
             return bad("grad_means, grad_covs and grad_attrs are required with VOGE_BACKWARD");
     }
+    if (flags & VOGE_SAMPLE) {
+        if (!it.features) return bad("features is required with VOGE_SAMPLE");
+        if (it.N > 0 && !it.sampled) return bad("sampled is required with VOGE_SAMPLE");
+    }
     return VOGE_OK;
 }
+
+// The work flags of a batch call: at least one of forward, backward and
+// sampling; backward and sampling share the gradient scratch; a reused
+// preparation excludes a new forward.
+int check_work_flags(int flags) {
+    if (!(flags & (VOGE_FORWARD | VOGE_BACKWARD | VOGE_SAMPLE)))
+        return fail(VOGE_EINVAL, "VOGE_FORWARD, VOGE_BACKWARD or VOGE_SAMPLE is required");
+    if ((flags & VOGE_BACKWARD) && (flags & VOGE_SAMPLE))
+        return fail(VOGE_EINVAL, "VOGE_BACKWARD and VOGE_SAMPLE do not combine in one call");
+    if ((flags & VOGE_REUSE_PREP) && (flags & VOGE_FORWARD))
+        return fail(VOGE_EINVAL, "VOGE_REUSE_PREP goes with VOGE_BACKWARD or VOGE_SAMPLE alone");
+    return VOGE_OK;
+}
+
+constexpr int WORK_FLAGS = VOGE_FORWARD | VOGE_BACKWARD | VOGE_SAMPLE | VOGE_REUSE_PREP;
 
 voge::ItemShape shape_of(const voge_item_t& it) {
     return {it.N, it.C, it.camera.height, it.camera.width, it.params.K};
@@ -335,8 +358,7 @@ BatchWs carve_batch(void* ws, const voge::BatchPlan& p) {
 }
 
 // The device record of table entry j.
-voge::ItemDev item_record(const voge::BatchPlan& p, int j, const voge_item_t& src, const BatchWs& w, int flags,
-                          bool with_backward) {
+voge::ItemDev item_record(const voge::BatchPlan& p, int j, const voge_item_t& src, const BatchWs& w, int flags) {
     const voge::ItemPlan& ip = p.items[j];
     voge::ItemDev d{};
     voge::TraceArgs& t = d.t;
@@ -368,7 +390,18 @@ voge::ItemDev item_record(const voge::BatchPlan& p, int j, const voge_item_t& sr
         t.wsum = src.wsum;
         t.kept = src.kept;
     }
-    if (with_backward) {
+    if (flags & VOGE_SAMPLE) {
+        const size_t nk = p.total_kern > 0 ? (size_t)p.total_kern : 1;
+        float* gM = w.grads;
+        float* gA = gM + 9 * nk;
+        t.grad_image = src.features;
+        t.gW = gM + 3 * k0;
+        t.gA = gA + ip.attr_off;
+        t.pairs = w.pairs + lo;
+        d.sampled = src.sampled;
+        d.sample_weight = src.sample_weight;
+    }
+    if (flags & VOGE_BACKWARD) {
         const size_t nk = p.total_kern > 0 ? (size_t)p.total_kern : 1;
         float* gM = w.grads;
         float* gS = gM + 3 * nk;
@@ -473,6 +506,24 @@ int launch_compute(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, 
             if (int rc = hip_check(voge::launch_epilogue(b, p.total_epi, s), "epilogue launch")) return rc;
         }
     }
+    if (flags & VOGE_SAMPLE) {
+        {
+            ProfScope ps = scope("zero");
+            const size_t nk = p.total_kern > 0 ? (size_t)p.total_kern : 1;
+            voge::launch_fill_u32(w.grads, 9 * nk + p.total_attr, 0u, s);
+        }
+        {
+            ProfScope ps = scope("sample_reduce");
+            for (const auto& g : p.groups)
+                if (int rc = hip_check(voge::launch_sample_reduce(group_dev(g, w, cfg), g.kb, s), "sample reduce launch"))
+                    return rc;
+        }
+        {
+            ProfScope ps = scope("sample_epilogue");
+            if (int rc = hip_check(voge::launch_sample_epilogue(b, p.total_epi, s), "sample epilogue launch"))
+                return rc;
+        }
+    }
     return VOGE_OK;
 }
 
@@ -480,7 +531,7 @@ std::vector<int64_t> graph_key(const voge::BatchPlan& p, const void* ws, int fla
     std::vector<int64_t> k;
     k.reserve(4 + 5 * p.items.size());
     k.push_back((int64_t)reinterpret_cast<uintptr_t>(ws));
-    k.push_back(flags & (VOGE_FORWARD | VOGE_BACKWARD | VOGE_REUSE_PREP));
+    k.push_back(flags & WORK_FLAGS);
     k.push_back(cfg.order);
     k.push_back((int64_t)p.items.size());
     for (const auto& it : p.items) {
@@ -500,7 +551,7 @@ int run_graph(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, int f
 // the items' shapes in call order (height x width, K, C and the bit length of
 // N), run-length coded.
 std::string shape_key(const voge_ctx_t* ctx, const voge_item_t* items, int n, int flags) {
-    std::string k = ctx->arch + ";f" + std::to_string(flags & (VOGE_FORWARD | VOGE_BACKWARD | VOGE_REUSE_PREP)) + ";";
+    std::string k = ctx->arch + ";f" + std::to_string(flags & WORK_FLAGS) + ";";
     std::string prev;
     int run = 0;
     auto flush = [&]() {
@@ -527,17 +578,17 @@ std::string shape_key(const voge_ctx_t* ctx, const voge_item_t* items, int n, in
 // execution choices (the autotuner's trials).
 int run_batch(voge_ctx_t* ctx, const voge_item_t* items, int n, int flags, void* workspace, size_t workspace_bytes,
               hipStream_t s, const voge::ExecConfig* force = nullptr) {
-    const bool backward = (flags & VOGE_BACKWARD) != 0;
+    const bool scratch = (flags & (VOGE_BACKWARD | VOGE_SAMPLE)) != 0;   // the gradient scratch is in use
     std::vector<voge::ItemShape> shapes(n);
     for (int i = 0; i < n; ++i) shapes[i] = shape_of(items[i]);
     const voge::BatchPlan p = voge::plan_batch(shapes.data(), n);
     if (p.total_kern >= (1 << 30)) return fail(VOGE_EINVAL, "too many kernels in one batch");
-    if (workspace_bytes < (backward ? p.bwd_bytes : p.fwd_bytes)) return fail(VOGE_ENOSPACE, "workspace too small");
+    if (workspace_bytes < (scratch ? p.bwd_bytes : p.fwd_bytes)) return fail(VOGE_ENOSPACE, "workspace too small");
     DeviceGuard guard(ctx->device);
     if (!guard.ok) return fail(VOGE_EHIP, "cannot select the context's device");
     const BatchWs w = carve_batch(workspace, p);
     std::vector<voge::ItemDev> recs(n);
-    for (int j = 0; j < n; ++j) recs[j] = item_record(p, j, items[p.items[j].caller], w, flags, backward);
+    for (int j = 0; j < n; ++j) recs[j] = item_record(p, j, items[p.items[j].caller], w, flags);
     voge::ExecConfig cfg;
     if (force) {
         cfg = *force;
@@ -658,7 +709,7 @@ int check_workspace(void* workspace) {
 
 extern "C" {
 
-int voge_version(void) { return 10100; }
+int voge_version(void) { return 10200; }
 
 const char* voge_last_error(void) { return g_err.c_str(); }
 
@@ -777,6 +828,25 @@ int voge_render_backward(voge_ctx_t* ctx, const float* means, const float* covs,
     return VOGE_OK;
 }
 
+int voge_sample(voge_ctx_t* ctx, const float* means, const float* covs, int N, int C, const voge_camera_t* cam,
+                const voge_params_t* params, const float* features, float* sampled, float* sample_weight, int flags,
+                void* workspace, size_t workspace_bytes, void* stream) {
+    if (int rc = check_common(ctx, means, covs, nullptr, N, C, cam, params, false)) return rc;
+    if (!features) return fail(VOGE_EINVAL, "features is required");
+    if (N > 0 && !sampled) return fail(VOGE_EINVAL, "sampled is required");
+    if (flags & ~VOGE_REUSE_PREP) return fail(VOGE_EINVAL, "unknown flags");
+    if (int rc = check_workspace(workspace)) return rc;
+    voge_item_t it = single_item(means, covs, nullptr, N, C, cam, params);
+    it.features = features;
+    it.sampled = sampled;
+    it.sample_weight = sample_weight;
+    if (int rc = run_batch(ctx, &it, 1, VOGE_SAMPLE | (flags & VOGE_REUSE_PREP), workspace, workspace_bytes,
+                           static_cast<hipStream_t>(stream)))
+        return rc;
+    g_err.clear();
+    return VOGE_OK;
+}
+
 int voge_batch_workspace_size(const voge_item_t* items, int n_items, int with_backward, size_t* bytes) {
     if (!bytes) return fail(VOGE_EINVAL, "bytes is null");
     if (!items || n_items < 1 || n_items > voge::MAX_BATCH) return fail(VOGE_EINVAL, "n_items must be in [1, 4096]");
@@ -795,11 +865,8 @@ int voge_render_batch(voge_ctx_t* ctx, const voge_item_t* items, int n_items, in
                       size_t workspace_bytes, void* stream) {
     if (!ctx) return fail(VOGE_EINVAL, "ctx is null");
     if (!items || n_items < 1 || n_items > voge::MAX_BATCH) return fail(VOGE_EINVAL, "n_items must be in [1, 4096]");
-    if (flags & ~(VOGE_FORWARD | VOGE_BACKWARD | VOGE_REUSE_PREP | VOGE_GRAPH | VOGE_TUNED))
-        return fail(VOGE_EINVAL, "unknown flags");
-    if (!(flags & (VOGE_FORWARD | VOGE_BACKWARD))) return fail(VOGE_EINVAL, "VOGE_FORWARD or VOGE_BACKWARD is required");
-    if ((flags & VOGE_REUSE_PREP) && (flags & VOGE_FORWARD))
-        return fail(VOGE_EINVAL, "VOGE_REUSE_PREP goes with VOGE_BACKWARD alone");
+    if (flags & ~(WORK_FLAGS | VOGE_GRAPH | VOGE_TUNED)) return fail(VOGE_EINVAL, "unknown flags");
+    if (int rc = check_work_flags(flags)) return rc;
     if ((flags & VOGE_GRAPH) && stream == nullptr) return fail(VOGE_EINVAL, "VOGE_GRAPH needs a non-null stream");
     if (int rc = check_workspace(workspace)) return rc;
     for (int i = 0; i < n_items; ++i)
@@ -814,10 +881,8 @@ int voge_tune_batch(voge_ctx_t* ctx, const voge_item_t* items, int n_items, int 
                     size_t workspace_bytes, void* stream, int trials, voge_tune_result_t* result) {
     if (!ctx) return fail(VOGE_EINVAL, "ctx is null");
     if (!items || n_items < 1 || n_items > voge::MAX_BATCH) return fail(VOGE_EINVAL, "n_items must be in [1, 4096]");
-    if (flags & ~(VOGE_FORWARD | VOGE_BACKWARD | VOGE_REUSE_PREP)) return fail(VOGE_EINVAL, "unknown flags");
-    if (!(flags & (VOGE_FORWARD | VOGE_BACKWARD))) return fail(VOGE_EINVAL, "VOGE_FORWARD or VOGE_BACKWARD is required");
-    if ((flags & VOGE_REUSE_PREP) && (flags & VOGE_FORWARD))
-        return fail(VOGE_EINVAL, "VOGE_REUSE_PREP goes with VOGE_BACKWARD alone");
+    if (flags & ~WORK_FLAGS) return fail(VOGE_EINVAL, "unknown flags");
+    if (int rc = check_work_flags(flags)) return rc;
     if (trials < 1) return fail(VOGE_EINVAL, "trials must be >= 1");
     if (int rc = check_workspace(workspace)) return rc;
     for (int i = 0; i < n_items; ++i)

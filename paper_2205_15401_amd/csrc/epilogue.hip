@@ -1,5 +1,6 @@
-// epilogue.hip -- backward epilogue (FP64): camera-space gradients of each
-// kernel back to world space, and the camera gradient.
+// epilogue.hip -- per-kernel epilogues.  Backward (FP64): camera-space
+// gradients of each kernel back to world space, and the camera gradient.
+// Sampler: the quotient of Eq. 10.
 //
 // With M = R M0 + T and S = R S0 R^T, S0 = Sigma^-1 (VoGE Sec. 3.3, Eq. 3-4),
 // and G = the symmetric gradient w.r.t. S:
@@ -140,6 +141,33 @@ __global__ __launch_bounds__(FIN_THREADS) void k_cam_finalize(BatchDev B) {
     }
     s = wave_sum_d(s);
     if (lane == 0) it.grad_camera[e] = (float)(e == 13 || e == 14 ? -s : s);
+}
+
+// Sampler epilogue (Sec. 3.4, Eq. 10): one thread per kernel rank divides
+// the reduced sum_p W phi by sum_p W and writes alpha in original kernel
+// order; a kernel that no pixel keeps gets alpha = 0 and weight 0.
+__global__ __launch_bounds__(EPI_THREADS) void k_sample_epilogue(BatchDev B) {
+    const int item = B.n_items == 1 ? 0 : B.epi_item[blockIdx.x];
+    const ItemDev it = B.items[item];     // a copy, read before any store
+    const TraceArgs& A = it.t;
+    const int r = (blockIdx.x - it.epi_start) * EPI_THREADS + threadIdx.x;
+    if (r >= A.N) return;
+    const size_t n = A.rec[r].idx;
+    const int C = A.C;
+    const float den = A.gW[r];
+    const float* num = A.gA + (size_t)r * C;
+    float* out = it.sampled + n * C;
+    if (den > 0.f) {
+        for (int c = 0; c < C; ++c) out[c] = num[c] / den;
+    } else {
+        for (int c = 0; c < C; ++c) out[c] = 0.f;
+    }
+    if (it.sample_weight) it.sample_weight[n] = den;
+}
+
+hipError_t launch_sample_epilogue(const BatchDev& b, int total_epi, hipStream_t s) {
+    if (total_epi > 0) hipLaunchKernelGGL(k_sample_epilogue, dim3(total_epi), dim3(EPI_THREADS), 0, s, b);
+    return hipGetLastError();
 }
 
 hipError_t launch_epilogue(const BatchDev& b, int total_epi, hipStream_t s) {

@@ -479,14 +479,20 @@ constexpr int RED_CH = 8;              // attribute channels per reduction pass
 constexpr int RED_NV = 9 + RED_CH;     // values per partial sum
 
 // Add one kernel's partial sums to global memory: the 9 geometric values
-// (pass 0 only) and attribute channels c0 .. c0+nc-1.
+// (pass 0 only; the sampler has one, the weight sum, in their place) and
+// attribute channels c0 .. c0+nc-1.
+template <bool SAMPLE>
 __device__ __forceinline__ void flush_values(const TraceArgs& A, int rank, const float* v, bool geom, int c0,
                                              int nc) {
     if (geom) {
+        if (SAMPLE) {
+            unsafeAtomicAdd(&A.gW[rank], v[0]);
+        } else {
 #pragma unroll
-        for (int q = 0; q < 3; ++q) unsafeAtomicAdd(&A.gM[(size_t)rank * 3 + q], v[q]);
+            for (int q = 0; q < 3; ++q) unsafeAtomicAdd(&A.gM[(size_t)rank * 3 + q], v[q]);
 #pragma unroll
-        for (int q = 0; q < 6; ++q) unsafeAtomicAdd(&A.gS[(size_t)rank * 6 + q], v[3 + q]);
+            for (int q = 0; q < 6; ++q) unsafeAtomicAdd(&A.gS[(size_t)rank * 6 + q], v[3 + q]);
+        }
     }
     for (int q = 0; q < nc; ++q) unsafeAtomicAdd(&A.gA[(size_t)rank * A.C + c0 + q], v[9 + q]);
 }
@@ -612,7 +618,10 @@ __device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile) {
 }
 
 // Backward, tile phase: group the tile's pairs by kernel and reduce them.
-template <int KB>
+// SAMPLE: the sampler of Sec. 3.4 (Eq. 10) on the same pairs -- the pixel map
+// is phi, a pair's weight is W = T e^q of the forward, and pass 0 sums W
+// instead of running the geometric chain.
+template <int KB, bool SAMPLE>
 __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int tile, unsigned char* smem) {
     __shared__ double s_red[TILE_THREADS / WAVE][3];
     __shared__ int s_scan[TILE_THREADS];
@@ -702,20 +711,35 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
         if (k < keff) {
             if (sp[k] >= 0) {
                 const size_t o = (size_t)k * S;
-                const float4 sc = pbw[o];
                 PairRec r;
-                r.dq = sc.x;
-                r.dl = sc.y + pbl[o];
-                r.da = sc.z;
-                r.w = sc.w;
-                r.l = pl[o];
+                if (SAMPLE) {
+                    r.dq = 0.f;
+                    r.dl = 0.f;
+                    r.da = 0.f;
+                    r.w = A.kl_T[P.q + o] * A.kl_m[P.q + o];   // the blend's W, same rounding
+                    r.l = 0.0;
+                } else {
+                    const float4 sc = pbw[o];
+                    r.dq = sc.x;
+                    r.dl = sc.y + pbl[o];
+                    r.da = sc.z;
+                    r.w = sc.w;
+                    r.l = pl[o];
+                }
                 r.pt = tid;
-                r.rank = A.kl_r[P.q + o];
+                r.rank = rk[k];
                 tile_pairs[s_off[sp[k] >> 16] + (sp[k] & 0xFFFF)] = r;
+            } else if (SAMPLE) {
+                // table full: this pair goes straight to global memory
+                const size_t o = (size_t)k * S;
+                const int rank = rk[k];
+                const float w = A.kl_T[P.q + o] * A.kl_m[P.q + o];
+                unsafeAtomicAdd(&A.gW[rank], w);
+                for (int c = 0; c < C; ++c) unsafeAtomicAdd(&A.gA[(size_t)rank * C + c], w * Gp[c]);
             } else {
                 // table full: this pair goes straight to global memory
                 const size_t o = (size_t)k * S;
-                const int rank = A.kl_r[P.q + o];
+                const int rank = rk[k];
                 const float4 sc = pbw[o];
                 double out[9];
                 pair_chain(A.geo[rank], P.u, P.v, (double)A.F, pl[o], sc.x, sc.y + pbl[o], sc.z, out, gD);
@@ -771,7 +795,7 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
                         s_tk[tid] = cur;
                         for (int q = v0; q < RED_NV; ++q) s_tail[tid * RED_NV + q] = acc[q];
                     } else {                                           // complete run
-                        flush_values(A, cur, acc, geom, c0, nc);
+                        flush_values<SAMPLE>(A, cur, acc, geom, c0, nc);
                     }
                     ++nseg;
                 }
@@ -779,11 +803,13 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
 #pragma unroll
                 for (int q = 0; q < RED_NV; ++q) acc[q] = 0.f;
                 cur = r.rank;
-                if (geom) G = A.geo[cur];
+                if (geom && !SAMPLE) G = A.geo[cur];
             }
             const int w = r.pt / WAVE, ln = r.pt % WAVE;
             const int row = ti0 + (w >> 1) * 8 + (ln >> 3), col = tj0 + (w & 1) * 8 + (ln & 7);
-            if (geom) {
+            if (geom && SAMPLE) {
+                acc[0] += r.w;
+            } else if (geom) {
                 double out[9];
                 pair_chain(G, (double)row - (double)A.cy, (double)col - (double)A.cx, (double)A.F, r.l, r.dq, r.dl,
                            r.da, out, gD);
@@ -822,11 +848,12 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
                 for (int q = v0; q < RED_NV; ++q) sum[q] += s_head[t2 * RED_NV + q];
                 if (s_tk[t2] >= 0) break;                             // the run ends inside chunk t2
             }
-            flush_values(A, k, sum, geom, c0, nc);
+            flush_values<SAMPLE>(A, k, sum, geom, c0, nc);
         }
         __syncthreads();
     }
 
+    if (SAMPLE) return;
     // per-tile sum of dL/dD' (for the intrinsics), fixed order
     const int wave = tid / WAVE, lane = tid % WAVE;
     const double gx = wave_sum(gD[0]), gy = wave_sum(gD[1]), gz = wave_sum(gD[2]);
@@ -887,7 +914,15 @@ __global__ __launch_bounds__(TILE_THREADS) void k_bwd_red(GroupDev g, int hcap) 
     extern __shared__ __align__(16) unsigned char smem[];
     int tile;
     const TraceArgs A = item_view(g, tile);
-    bwd_red_body<KB>(A, hcap, tile, smem);
+    bwd_red_body<KB, false>(A, hcap, tile, smem);
+}
+
+template <int KB>
+__global__ __launch_bounds__(TILE_THREADS) void k_sample_red(GroupDev g, int hcap) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    int tile;
+    const TraceArgs A = item_view(g, tile);
+    bwd_red_body<KB, true>(A, hcap, tile, smem);
 }
 
 // Diagnostics: the device Phi on an array.
@@ -920,9 +955,12 @@ static hipError_t run_kb(int which, const GroupDev& g, hipStream_t s) {
         hipLaunchKernelGGL(k_blend<KB>, dim3(nt), dim3(TILE_THREADS), 0, s, g);
     } else if (which == 2) {
         hipLaunchKernelGGL(k_bwd_pix<KB>, dim3(nt), dim3(TILE_THREADS), 0, s, g);
-    } else {
+    } else if (which == 3) {
         const int hcap = table_capacity(0);
         hipLaunchKernelGGL(k_bwd_red<KB>, dim3(nt), dim3(TILE_THREADS), bwd_lds_bytes(hcap, KB), s, g, hcap);
+    } else {
+        const int hcap = table_capacity(0);
+        hipLaunchKernelGGL(k_sample_red<KB>, dim3(nt), dim3(TILE_THREADS), bwd_lds_bytes(hcap, KB), s, g, hcap);
     }
     return hipGetLastError();
 }
@@ -941,6 +979,7 @@ hipError_t launch_select(const GroupDev& g, int kb, hipStream_t s) { return disp
 hipError_t launch_blend(const GroupDev& g, int kb, hipStream_t s) { return dispatch(1, g, kb, s); }
 hipError_t launch_bwd(const GroupDev& g, int kb, hipStream_t s) { return dispatch(2, g, kb, s); }
 hipError_t launch_bwd_reduce(const GroupDev& g, int kb, hipStream_t s) { return dispatch(3, g, kb, s); }
+hipError_t launch_sample_reduce(const GroupDev& g, int kb, hipStream_t s) { return dispatch(4, g, kb, s); }
 
 hipError_t launch_phi(const float* x, float* y, int n, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(k_phi, dim3((n + 255) / 256), dim3(256), 0, s, x, y, n);

@@ -48,9 +48,11 @@ struct TraceArgs {
     float* image;
     float* wsum;
     int32_t* kept;
-    // backward
-    const float* grad_image;
-    float* gA;                 // [N][C] attribute gradients in rank order
+    // backward, and the sampler of Sec. 3.4 (Eq. 10), which reduces the same
+    // pairs with phi in place of dL/dC and no geometric chain
+    const float* grad_image;   // per-pixel map reduced onto the kernels: dL/dC, or phi when sampling
+    float* gA;                 // [N][C] attribute gradients (sampling: sum_p W phi) in rank order
+    float* gW;                 // [N] sampling: sum_p W, rank order (shares gM's storage)
     float* gM;                 // [N][3] camera-space centre gradients, rank order
     float* gS;                 // [N][6] camera-space inverse-covariance gradients
     double* tileD;             // [n_tiles][3] per-tile sums of dL/dD'
@@ -68,6 +70,8 @@ struct ItemDev {
     float* grad_covs;
     float* grad_attrs;
     float* grad_camera;        // 15 floats or null
+    float* sampled;            // sampling outputs: [N*C] alpha, [N] sum_p W (optional)
+    float* sample_weight;
     double* camP;              // [n_epi][12] per-block camera partials
     int* status;               // this item's device status word
     CamDev cam;
@@ -165,7 +169,9 @@ hipError_t launch_select(const GroupDev& g, int kb, hipStream_t s);
 hipError_t launch_blend(const GroupDev& g, int kb, hipStream_t s);
 hipError_t launch_bwd(const GroupDev& g, int kb, hipStream_t s);          // pixel phase
 hipError_t launch_bwd_reduce(const GroupDev& g, int kb, hipStream_t s);   // tile reduction
+hipError_t launch_sample_reduce(const GroupDev& g, int kb, hipStream_t s); // sampler: tile reduction
 hipError_t launch_phi(const float* x, float* y, int n, hipStream_t s);
 hipError_t launch_epilogue(const BatchDev& b, int total_epi, hipStream_t s);
+hipError_t launch_sample_epilogue(const BatchDev& b, int total_epi, hipStream_t s);
 
 }  // namespace voge

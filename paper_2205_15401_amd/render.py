@@ -135,6 +135,38 @@ def render_backward(means: torch.Tensor, covs: torch.Tensor, attrs: torch.Tensor
     return gm, gc, ga, gk
 
 
+def sample(means: torch.Tensor, covs: torch.Tensor, features: torch.Tensor, cam: nat.VogeCamera,
+           K: int = 20, eta: float = 0.01, workspace: Optional[torch.Tensor] = None, reuse: bool = False,
+           with_weight: bool = False):
+    """Sampler of Sec. 3.4 (Eq. 10): features [H,W,C] onto the kernels.
+    Returns (alpha [N,C], sum_p W [N] or None, workspace).  ``reuse`` takes
+    the kept sets of the last forward on ``workspace`` (same kernels and
+    camera)."""
+    if not (means.is_cuda and covs.is_cuda and features.is_cuda):
+        raise ValueError("means, covs and features must be device tensors")
+    for name, t, cols in (("means", means, 3), ("covs", covs, 6)):
+        if t.dtype != torch.float32 or t.dim() != 2 or t.shape[1] != cols or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float32 tensor of shape (N, {cols})")
+    if covs.shape[0] != means.shape[0]:
+        raise ValueError("means and covs disagree on N")
+    f = features.contiguous()
+    if f.dtype != torch.float32 or f.dim() != 3 or tuple(f.shape[:2]) != (cam.height, cam.width):
+        raise ValueError("features must be float32 of shape (H, W, C)")
+    dev = means.device
+    N, C = means.shape[0], f.shape[2]
+    par = params_struct(K, eta)
+    need = workspace_bytes(N, C, cam, par, True)
+    if workspace is None or workspace.numel() < need:
+        if reuse:
+            raise ValueError("reuse needs the forward's workspace sized for sampling")
+        workspace = new_workspace(need, dev)
+    alpha = torch.empty((N, C), dtype=torch.float32, device=dev)
+    wk = torch.empty(N, dtype=torch.float32, device=dev) if with_weight else None
+    nat.voge_sample(context(dev), _ptr(means), _ptr(covs), N, C, cam, par, _ptr(f), _ptr(alpha), _ptr(wk),
+                    nat.VOGE_REUSE_PREP if reuse else 0, _ptr(workspace), workspace.numel(), _stream(dev))
+    return alpha, wk, workspace
+
+
 def status(workspace: torch.Tensor) -> int:
     """Device status bits of the last forward on this workspace (synchronises)."""
     return nat.voge_status(_ptr(workspace), _stream(workspace.device))
@@ -203,10 +235,13 @@ class Batch:
     live in ``images``, ``wsums``, ``kepts`` and, with a backward, in
     ``grad_means``, ``grad_covs``, ``grad_attrs`` and ``grad_cameras``
     (per item; gradients are per item, not summed over items of one scene).
+    With ``sample``, each item also carries a feature map ``features[i]``
+    [H,W,C] that ``run(sample=True)`` samples onto the kernels (Sec. 3.4,
+    Eq. 10) into ``sampled[i]`` [N,C] and ``sample_weights[i]`` [N].
     """
 
     def __init__(self, scenes, items, device: torch.device, backward: bool = False, with_wsum: bool = False,
-                 with_kept: bool = False, with_camera: bool = False):
+                 with_kept: bool = False, with_camera: bool = False, sample: bool = False):
         for m, c, a in scenes:
             _check_inputs(m, c, a)
         self.device = device
@@ -215,7 +250,9 @@ class Batch:
         if not 1 <= self.n <= nat.VOGE_MAX_BATCH:
             raise ValueError(f"a batch holds 1 to {nat.VOGE_MAX_BATCH} items")
         self.backward = backward
+        self.sample = sample
         self.arr = (nat.VogeItem * self.n)()
+        self.features, self.sampled, self.sample_weights = [], [], []
         self.images, self.wsums, self.kepts = [], [], []
         self.grad_images, self.grad_means, self.grad_covs, self.grad_attrs, self.grad_cameras = [], [], [], [], []
         self.scene_of = []
@@ -248,33 +285,42 @@ class Batch:
                 if with_camera:
                     self.grad_cameras.append(torch.empty(15, **f32))
                     it.grad_camera = _ptr(self.grad_cameras[-1])
+            if sample:
+                self.features.append(torch.zeros((H, W, C), **f32))
+                self.sampled.append(torch.empty((N, C), **f32))
+                self.sample_weights.append(torch.empty(N, **f32))
+                it.features, it.sampled, it.sample_weight = (_ptr(self.features[-1]), _ptr(self.sampled[-1]),
+                                                             _ptr(self.sample_weights[-1]))
             self.scene_of.append(si)
-        self.ws_bytes = nat.voge_batch_workspace_size(self.arr, backward)
+        self.ws_bytes = nat.voge_batch_workspace_size(self.arr, backward or sample)
         self.workspace = new_workspace(self.ws_bytes, device)
 
     def set_grad_image(self, i: int, g: torch.Tensor) -> None:
         self.grad_images[i].copy_(g)
 
-    def _flags(self, forward, backward, reuse):
+    def _flags(self, forward, backward, reuse, sample=False):
         if backward and not self.backward:
             raise ValueError("this batch was built without a backward")
+        if sample and not self.sample:
+            raise ValueError("this batch was built without sampling")
         flags = (nat.VOGE_FORWARD if forward else 0) | (nat.VOGE_BACKWARD if backward else 0)
+        flags |= nat.VOGE_SAMPLE if sample else 0
         return flags | (nat.VOGE_REUSE_PREP if reuse else 0)
 
     def run(self, forward: bool = True, backward: bool = False, reuse: bool = False, graph: bool = False,
-            tuned: bool = False, stream: Optional[int] = None) -> None:
+            tuned: bool = False, stream: Optional[int] = None, sample: bool = False) -> None:
         """One call of voge_render_batch on ``stream`` (default: torch's current stream)."""
-        flags = self._flags(forward, backward, reuse)
+        flags = self._flags(forward, backward, reuse, sample)
         flags |= (nat.VOGE_GRAPH if graph else 0) | (nat.VOGE_TUNED if tuned else 0)
         s = _stream(self.device) if stream is None else stream
         nat.voge_render_batch(context(self.device), self.arr, flags, _ptr(self.workspace), self.ws_bytes, s)
 
     def tune(self, forward: bool = True, backward: bool = False, trials: int = 3,
-             stream: Optional[int] = None) -> nat.VogeTuneResult:
+             stream: Optional[int] = None, sample: bool = False) -> nat.VogeTuneResult:
         """Time the execution choices on this batch (voge_tune_batch); later
         calls of ``run(tuned=True)`` with the same shapes use the fastest."""
         s = _stream(self.device) if stream is None else stream
-        return nat.voge_tune_batch(context(self.device), self.arr, self._flags(forward, backward, False),
+        return nat.voge_tune_batch(context(self.device), self.arr, self._flags(forward, backward, False, sample),
                                    _ptr(self.workspace), self.ws_bytes, s, trials)
 
     def status(self):

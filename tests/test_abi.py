@@ -44,7 +44,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_version(lib):
-    assert nat.voge_version() == 10100
+    assert nat.voge_version() == 10200
 
 
 def cam(h=64, w=64, f=64.0):
@@ -98,6 +98,28 @@ def test_calls_without_context_are_rejected_on_the_host(lib):
         nat.voge_create(-1)
 
 
+def test_sampler_rejects_bad_arguments_on_the_host(lib):
+    fake_ctx = ctypes.c_void_p(1).value
+
+    def rejected(**kw):
+        a = dict(ctx=fake_ctx, means=256, covs=256, N=10, C=3, cam=cam(), params=par(), features=256, sampled=256,
+                 sample_weight=None, flags=0, workspace=256, workspace_bytes=1 << 30, stream=None)
+        a.update(kw)
+        with pytest.raises(nat.VogeError) as e:
+            nat.voge_sample(*a.values())
+        assert e.value.code == nat.VOGE_EINVAL
+        return nat.voge_last_error()
+
+    assert "ctx" in rejected(ctx=None)
+    assert "features" in rejected(features=None)
+    assert "sampled" in rejected(sampled=None)
+    assert "flags" in rejected(flags=nat.VOGE_FORWARD)
+    assert "means" in rejected(means=None)
+    assert "C" in rejected(C=0)
+    assert "workspace" in rejected(workspace=None)
+    assert "aligned" in rejected(workspace=300)
+
+
 def test_bad_eta_is_rejected_before_any_device_work(lib):
     # a non-null fake context: argument checks run before the context is used
     fake_ctx = ctypes.c_void_p(1).value
@@ -108,7 +130,7 @@ def test_bad_eta_is_rejected_before_any_device_work(lib):
         assert e.value.code == nat.VOGE_EINVAL
 
 
-def item(N=100, C=3, h=64, w=64, K=20, eta=0.01, image=1, grads=False):
+def item(N=100, C=3, h=64, w=64, K=20, eta=0.01, image=1, grads=False, sample=False):
     it = nat.VogeItem()
     it.means = it.covs = it.attrs = 256 if N > 0 else None
     it.N, it.C = N, C
@@ -117,6 +139,8 @@ def item(N=100, C=3, h=64, w=64, K=20, eta=0.01, image=1, grads=False):
     it.image = image
     if grads:
         it.grad_image = it.grad_means = it.grad_covs = it.grad_attrs = 256
+    if sample:
+        it.features = it.sampled = 256
     return it
 
 
@@ -124,14 +148,16 @@ def test_item_struct_matches_the_header(tmp_path):
     """The ctypes mirror of voge_item_t has the C compiler's size and offsets."""
     src = tmp_path / "layout.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "voge.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(voge_item_t),'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(voge_item_t),'
                    ' offsetof(voge_item_t, camera), offsetof(voge_item_t, params),'
-                   ' offsetof(voge_item_t, image), offsetof(voge_item_t, grad_camera)); return 0;}\n')
+                   ' offsetof(voge_item_t, image), offsetof(voge_item_t, grad_camera),'
+                   ' offsetof(voge_item_t, features), offsetof(voge_item_t, sample_weight)); return 0;}\n')
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     I = nat.VogeItem
-    assert got == [ctypes.sizeof(I), I.camera.offset, I.params.offset, I.image.offset, I.grad_camera.offset]
+    assert got == [ctypes.sizeof(I), I.camera.offset, I.params.offset, I.image.offset, I.grad_camera.offset,
+                   I.features.offset, I.sample_weight.offset]
 
 
 def test_batch_workspace_is_no_larger_than_separate_workspaces(lib):
@@ -166,6 +192,18 @@ def test_batch_rejects_bad_arguments_on_the_host(lib):
     assert "item 0" in rejected([item(grads=False)], nat.VOGE_BACKWARD)
     assert "item 1" in rejected([item(), item(K=65)], nat.VOGE_FORWARD)
     assert "item 0" in rejected([item(eta=1.5)], nat.VOGE_FORWARD)
+    # sampling: features and sampled are required, attrs is not; it does not
+    # combine with the backward or with a reused preparation plus a forward
+    S = nat.VOGE_SAMPLE
+    assert "features" in rejected([item()], S)
+    assert "combine" in rejected([item(sample=True, grads=True)], S | nat.VOGE_BACKWARD)
+    rejected([item(sample=True)], S | nat.VOGE_FORWARD | nat.VOGE_REUSE_PREP)
+    no_attrs = item(sample=True)
+    no_attrs.attrs = None
+    assert "attrs" in rejected([no_attrs], S | nat.VOGE_FORWARD)
+    no_out = item(sample=True)
+    no_out.sampled = None
+    assert "sampled" in rejected([no_out], S)
     with pytest.raises(nat.VogeError):
         nat.voge_batch_workspace_size([], False)
     with pytest.raises(nat.VogeError):

@@ -1,0 +1,244 @@
+"""The sampler (Sec. 3.4, Eq. 10) on the GPU vs the FP64 oracle, through the
+C ABI: the single call (voge_sample), reuse of a forward's kept sets, and
+batches (voge_render_batch with VOGE_SAMPLE, alone or with the forward).
+
+Tolerance, from the 1e-5 relative bar of the forward and backward: the
+weight sum d_k = sum_p W_pk is a sum of positive terms, so
+|d_gpu - d_ref| <= 1e-5 d_ref; the numerator n_k = sum_p W_pk phi_p is held
+to 1e-5 of its absolute sum a_k = sum_p W_pk |phi_p| (the bar of the
+attribute gradient, which it equals), and through alpha = n / d that gives
+|alpha_gpu - alpha_ref| <= 1e-5 (a_k / d_k + |alpha_ref|).  Kernels that a
+near-tie pixel keeps on either side (the oracle's flags) have more than one
+correct kept set and are left out; the tests check that they are few.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2205_15401_amd import _native as nat
+from paper_2205_15401_amd import render as R
+from paper_2205_15401_amd import scenes as S
+
+from parity import RTOL, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    nat.load()
+    return torch.device("cuda:0")
+
+
+def dev_geometry(scene):
+    return to_dev(scene.means), to_dev(scene.covs)
+
+
+def features_for(rng, cam, C):
+    return rng.standard_normal((cam.height, cam.width, C)).astype(np.float32)
+
+
+def ambiguous_kernels(ref_fwd, kept_gpu, K):
+    """Kernels kept, by the oracle or by the GPU, at a pixel the oracle flags."""
+    flagged = ref_fwd.flags != 0
+    ids = set(ref_fwd.kept_idx[flagged].ravel().tolist())
+    if kept_gpu is not None:
+        ids |= set(np.asarray(kept_gpu).reshape(-1, K)[flagged].ravel().tolist())
+    ids.discard(-1)
+    return np.array(sorted(ids), np.int64)
+
+
+def check_sample(alpha_gpu, weight_gpu, scene, cam, K, eta, phi, kept_gpu=None, what=""):
+    """alpha (N, C) and weight sums (N,) of the GPU against the oracle."""
+    N = scene.means.shape[0]
+    H, W = cam.height, cam.width
+    ref = O.sample(scene.means, scene.covs, cam.as_vector(), H, W, K, phi, eta)
+    absref = O.sample(scene.means, scene.covs, cam.as_vector(), H, W, K, np.abs(phi), eta)
+    amb = ambiguous_kernels(ref.fwd, kept_gpu, K)
+    assert amb.size <= max(3, N // 50), f"{what}: {amb.size} kernels at near ties"
+    keep = np.ones(N, bool)
+    keep[amb] = False
+    a = np.asarray(alpha_gpu, np.float64)
+    seen = ref.den > 0
+    unseen = keep & ~seen
+    # kernels no pixel keeps: exactly zero
+    assert np.all(a[unseen] == 0.0), f"{what}: alpha of unseen kernels"
+    m = keep & seen
+    bound = RTOL * (absref.num[m] / ref.den[m, None] + np.abs(ref.alpha[m])) + 1e-30
+    ratio = np.abs(a[m] - ref.alpha[m]) / bound
+    assert ratio.size == 0 or ratio.max() <= 1.0, f"{what}: alpha, worst {ratio.max():.3g} of the bound"
+    if weight_gpu is not None:
+        w = np.asarray(weight_gpu, np.float64)
+        assert np.all(w[unseen] == 0.0), f"{what}: weight of unseen kernels"
+        wr = np.abs(w[m] - ref.den[m]) / (RTOL * ref.den[m])
+        assert wr.size == 0 or wr.max() <= 1.0, f"{what}: weight sums, worst {wr.max():.3g} of the bound"
+    return ref, int(m.sum())
+
+
+@pytest.mark.parametrize("C", [1, 3, 5, 16])
+def test_single_call_matches_the_oracle(C):
+    """A torus of 3,000 kernels at 72 x 88 (ragged tiles of 16), C channels
+    (one and several reduction passes, with and without four-channel rows)."""
+    rng = np.random.default_rng(100 + C)
+    scene = S.torus_scene(rng, 3000, C, centre=(0.0, 0.0, 3.0))
+    cam = S.identity_camera(88, focal=70.0, height=72)
+    phi = features_for(rng, cam, C)
+    m, c = dev_geometry(scene)
+    alpha, wk, _ = R.sample(m, c, torch.from_numpy(phi).cuda(), R.camera_struct(cam), 20, 0.01,
+                            with_weight=True)
+    torch.cuda.synchronize()
+    _, n_cmp = check_sample(alpha.cpu().numpy(), wk.cpu().numpy(), scene, cam, 20, 0.01, phi, what=f"C={C}")
+    assert n_cmp > 1000
+
+
+def test_reuse_of_a_forward_and_the_joint_call():
+    """Sampling from the kept sets of an earlier forward (VOGE_REUSE_PREP)
+    and the forward with the sampler in one batch call give the oracle's
+    result; the joint call's image is the forward's, bit for bit."""
+    rng = np.random.default_rng(101)
+    scene = S.cloud_scene(rng, 2500, 4)
+    cam = S.look_at_camera(np.array([0.4, -0.3, -0.2]), 96, focal=90.0, target=(0.0, 0.0, 3.0))
+    phi = features_for(rng, cam, 4)
+    m, c = dev_geometry(scene)
+    a = to_dev(scene.attrs)
+    cs = R.camera_struct(cam)
+    img, _, kept, ws = R.render_forward(m, c, a, cs, 20, 0.01, with_kept=True, for_backward=True)
+    alpha, wk, _ = R.sample(m, c, torch.from_numpy(phi).cuda(), cs, 20, 0.01, workspace=ws, reuse=True,
+                            with_weight=True)
+    torch.cuda.synchronize()
+    check_sample(alpha.cpu().numpy(), wk.cpu().numpy(), scene, cam, 20, 0.01, phi, kept.cpu().numpy(), "reuse")
+
+    dev = torch.device("cuda:0")
+    batch = R.Batch([(m, c, a)], [(0, cs, 20, 0.01)], dev, with_kept=True, sample=True)
+    batch.features[0].copy_(torch.from_numpy(phi))
+    batch.run(forward=True, sample=True)
+    torch.cuda.synchronize()
+    assert torch.equal(batch.images[0], img)
+    assert torch.equal(batch.kepts[0], kept)
+    check_sample(batch.sampled[0].cpu().numpy(), batch.sample_weights[0].cpu().numpy(), scene, cam, 20, 0.01,
+                 phi, kept.cpu().numpy(), "joint")
+
+
+def test_mixed_batch_matches_the_oracle_per_item():
+    """Scenes of several sizes and channel counts, K from 4 to 32 (four
+    compiled K-buffer depths in one call), a shared scene, ragged and tiny
+    images, an item without kernels; sampling alone, without attributes."""
+    rng = np.random.default_rng(102)
+    spheres = S.config_small().scene
+    torus = S.torus_scene(rng, 2000, 5)
+    cloud = S.cloud_scene(rng, 1500, 5)
+    empty = S.Scene(np.zeros((0, 3), np.float32), np.zeros((0, 6), np.float32), np.zeros((0, 5), np.float32))
+    scenes = [spheres, torus, cloud, empty]
+    rot = S.look_at_camera(np.array([0.4, -0.3, -0.2]), 72, focal=80.0, target=(0.0, 0.0, 3.0))
+    rot.height, rot.cy = 100, 47.5
+    items = [(0, S.identity_camera(64), 16, 0.01), (1, rot, 20, 0.01),
+             (2, S.identity_camera(80, focal=60.0, height=48), 8, 0.01), (3, S.identity_camera(16), 4, 0.01),
+             (2, S.identity_camera(40), 32, 0.05), (1, S.identity_camera(1), 20, 0.01)]
+    dev = torch.device("cuda:0")
+    arr = (nat.VogeItem * len(items))()
+    keep_alive, outs, phis = [], [], []
+    for i, (si, cam, K, eta) in enumerate(items):
+        sc = scenes[si]
+        N, C = sc.means.shape[0], sc.attrs.shape[1]
+        m, c = dev_geometry(sc)
+        phi = features_for(rng, cam, C)
+        f = torch.from_numpy(phi).to(dev)
+        al = torch.full((N, C), float("nan"), device=dev)
+        wk = torch.full((N,), float("nan"), device=dev)
+        it = arr[i]
+        it.means, it.covs, it.attrs = m.data_ptr(), c.data_ptr(), None
+        it.N, it.C = N, C
+        it.camera, it.params = R.camera_struct(cam), R.params_struct(K, eta)
+        it.features, it.sampled, it.sample_weight = f.data_ptr(), al.data_ptr(), wk.data_ptr()
+        keep_alive += [m, c, f]
+        outs.append((al, wk))
+        phis.append(phi)
+    nbytes = nat.voge_batch_workspace_size(arr, True)
+    ws = R.new_workspace(nbytes, dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    nat.voge_render_batch(R.context(dev), arr, nat.VOGE_SAMPLE, ws.data_ptr(), nbytes, stream)
+    torch.cuda.synchronize()
+    assert nat.voge_batch_status(ws.data_ptr(), len(items), stream) == [0] * len(items)
+    for i, (si, cam, K, eta) in enumerate(items):
+        al, wk = outs[i]
+        check_sample(al.cpu().numpy(), wk.cpu().numpy(), scenes[si], cam, K, eta, phis[i], what=f"item {i}")
+
+
+def test_constant_features_and_kernels_nobody_keeps():
+    """A constant map samples to that constant (to FP32 rounding); kernels
+    behind the camera or off screen get alpha 0 and weight 0."""
+    rng = np.random.default_rng(103)
+    scene = S.isotropic_scene(rng, 400, 2)
+    scene.means[:20, 2] = -3.0                     # behind the camera
+    scene.means[20:40, 0] = 50.0                   # far outside the view
+    cam = S.identity_camera(48)
+    phi = np.broadcast_to(np.array([0.25, -3.0], np.float32), (48, 48, 2)).copy()
+    m, c = dev_geometry(scene)
+    alpha, wk, _ = R.sample(m, c, torch.from_numpy(phi).cuda(), R.camera_struct(cam), 16, 0.01, with_weight=True)
+    torch.cuda.synchronize()
+    a, w = alpha.cpu().numpy(), wk.cpu().numpy()
+    assert np.all(a[:40] == 0.0) and np.all(w[:40] == 0.0)
+    seen = w > 0
+    assert seen.sum() > 200
+    np.testing.assert_allclose(a[seen], np.broadcast_to([0.25, -3.0], (seen.sum(), 2)), rtol=2e-6)
+    check_sample(a, w, scene, cam, 16, 0.01, phi, what="constant")
+
+
+def test_graph_replays_sample_like_eager_calls():
+    """VOGE_GRAPH with VOGE_SAMPLE: several replays, with other work and new
+    feature maps between them, each equal to the oracle."""
+    rng = np.random.default_rng(104)
+    scene = S.torus_scene(rng, 1500, 3, centre=(0.0, 0.0, 0.0), attr_dist="uniform")
+    cams = [S.random_pose(rng, 64) for _ in range(3)]
+    dev = torch.device("cuda:0")
+    m, c = dev_geometry(scene)
+    a = to_dev(scene.attrs)
+    batch = R.Batch([(m, c, a)], [(0, R.camera_struct(cm), 20, 0.01) for cm in cams], dev, sample=True)
+    stream = torch.cuda.Stream(dev)
+    for rep in range(3):
+        phis = [features_for(rng, cm, 3) for cm in cams]
+        for i, phi in enumerate(phis):
+            batch.features[i].copy_(torch.from_numpy(phi))
+        torch.cuda.synchronize()
+        batch.run(forward=False, sample=True, graph=True, stream=stream.cuda_stream)
+        torch.cuda.synchronize()
+        _ = (torch.ones(1 << 20, device=dev) * 2).sum().item()       # other work between replays
+        for i, cm in enumerate(cams):
+            check_sample(batch.sampled[i].cpu().numpy(), batch.sample_weights[i].cpu().numpy(), scene, cm, 20,
+                         0.01, phis[i], what=f"replay {rep} item {i}")
+
+
+def test_pose_batch_at_full_size():
+    """The many-pose workload's shapes (256 poses of the 4,096-kernel torus at
+    128 x 128, K = 20, 3 channels), sampled in one call: every kernel's alpha
+    is a convex combination of the feature values (inside their range), and
+    three poses match the oracle kernel by kernel."""
+    rng = np.random.default_rng(105)
+    jobs = S.config_poses()
+    scene = jobs[0].scene
+    dev = torch.device("cuda:0")
+    m, c = dev_geometry(scene)
+    a = to_dev(scene.attrs)
+    batch = R.Batch([(m, c, a)], [(0, R.camera_struct(j.camera), j.K, j.eta) for j in jobs], dev, sample=True)
+    phis = []
+    for i, j in enumerate(jobs):
+        phi = features_for(rng, j.camera, 3)
+        phis.append(phi)
+        batch.features[i].copy_(torch.from_numpy(phi))
+    batch.run(forward=False, sample=True)
+    torch.cuda.synchronize()
+    assert batch.status() == [0] * len(jobs)
+    for i, phi in enumerate(phis):
+        al, w = batch.sampled[i].cpu().numpy(), batch.sample_weights[i].cpu().numpy()
+        lo, hi = phi.reshape(-1, 3).min(axis=0), phi.reshape(-1, 3).max(axis=0)
+        tol = 1e-5 * np.maximum(np.abs(lo), np.abs(hi))
+        assert np.all(w >= 0.0) and np.all(np.isfinite(al))
+        assert np.all((al >= lo - tol) & (al <= hi + tol)), f"pose {i}: alpha outside the feature range"
+        assert np.all(al[w == 0] == 0.0)
+    for i in (0, 101, 255):
+        check_sample(batch.sampled[i].cpu().numpy(), batch.sample_weights[i].cpu().numpy(), scene,
+                     jobs[i].camera, jobs[i].K, jobs[i].eta, phis[i], what=f"pose {i}")
