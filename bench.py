@@ -266,6 +266,60 @@ def bench_poses(args, torch, dev):
     }
 
 
+def bench_sampler(args, torch, dev, jobs):
+    """The sampler of Sec. 3.4 (Eq. 10) on the many-pose workload: N(0,1)
+    feature maps of every pose sampled onto the torus's kernels, one
+    voge_render_batch(VOGE_SAMPLE) call per step (selection, weights and the
+    per-kernel reduction; no image)."""
+    import numpy as np
+    from paper_2205_15401_amd import _native as nat
+    from paper_2205_15401_amd import render as R
+
+    sc = jobs[0].scene
+    m, c, a = (torch.from_numpy(x).to(dev) for x in (sc.means, sc.covs, sc.attrs))
+    K, eta = jobs[0].K, jobs[0].eta
+    batch = R.Batch([(m, c, a)], [(0, R.camera_struct(j.camera), K, eta) for j in jobs], dev, sample=True)
+    rng = np.random.default_rng(17)
+    for i, j in enumerate(jobs):
+        phi = rng.standard_normal((j.camera.height, j.camera.width, sc.channels)).astype(np.float32)
+        batch.features[i].copy_(torch.from_numpy(phi))
+    side = torch.cuda.Stream()
+    s = side.cuda_stream
+    timer = Timer(torch, side)
+    rays = sum(j.camera.height * j.camera.width for j in jobs)
+    steps = max(1, args.sample_steps)
+    total_e, per_e = timer.run(lambda: batch.run(forward=False, sample=True, stream=s), steps, args.warmup)
+    total_g, per_g = timer.run(lambda: batch.run(forward=False, sample=True, graph=True, stream=s), steps,
+                               args.warmup)
+    ctx = R.context(dev)
+    nat.voge_profile_enable(ctx, True)
+    nat.voge_profile_read(ctx, reset=True)
+    for _ in range(args.profile_steps):
+        batch.run(forward=False, sample=True, stream=s)
+    torch.cuda.synchronize()
+    phases = nat.voge_profile_read(ctx, reset=True)
+    nat.voge_profile_enable(ctx, False)
+    ms_e, ms_g = total_e / steps, total_g / steps
+    log(f"[bench] sampler: eager {ms_e:.3f} ms/step ({rays / ms_e / 1e3:.1f} Mrays/s), graph {ms_g:.3f} ms/step")
+    for name, (tot, cnt) in sorted(phases.items()):
+        log(f"[bench]   sampler phase {name:16s} {tot / max(cnt, 1) * 1e3:10.2f} us avg over {cnt}")
+    return {"value": rays / ms_e / 1e3, "ms": ms_e, "per": per_e, "graph_value": rays / ms_g / 1e3, "graph_ms": ms_g,
+            "phases": phases, "steps": steps}
+
+
+def sampler_roofline(phases, opc, K, workload):
+    """The sampler step's dominant kernel against the FP32 vector peak."""
+    flops = {"select": opc["flop_select"], "blend_sample": opc["flop_blend_weights"] + opc["flop_sample_reduce"]}
+    kb = kb_of(K)
+    kname = {"select": f"k_select<{kb}>", "blend_sample": f"k_blend_sample<{kb}>"}
+    avg = {k: phases[k][0] / phases[k][1] for k in flops if k in phases and phases[k][1] > 0}
+    dom = max(avg, key=avg.get)
+    achieved = flops[dom] / (avg[dom] / 1e3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 6), "kernel": kname[dom], "avg_us": round(avg[dom] * 1e3, 2),
+            "algorithmic_flop_per_launch": flops[dom]}
+
+
 def bench_torus(args, torch, dev):
     from paper_2205_15401_amd import _native as nat
     from paper_2205_15401_amd import render as R
@@ -387,6 +441,7 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--torus-steps", type=int, default=50, help="timed steps of the single 512x512 image")
     ap.add_argument("--cpu-sample", type=int, default=1048576, help="rays for the oracle baseline (0 = skip)")
+    ap.add_argument("--sample-steps", type=int, default=20, help="timed steps of the sampler (0 = skip)")
     ap.add_argument("--serving-requests", type=int, default=600, help="timed requests per load (0 = skip serving)")
     ap.add_argument("--serving-warmup", type=int, default=100)
     ap.add_argument("--serving-capacity-requests", type=int, default=200)
@@ -428,6 +483,7 @@ def main():
         print(json.dumps({"metric": None, "value": None, "single_image": single, "serving": serving}), flush=True)
         return
     r = bench_poses(args, torch, dev)
+    sampler = bench_sampler(args, torch, dev, r["jobs"]) if args.sample_steps > 0 else None
     single = bench_torus(args, torch, dev) if args.torus_steps > 0 else None
     serving = bench_serving(args, torch, dev) if args.serving_requests > 0 else None
     calibration_copy()
@@ -435,7 +491,10 @@ def main():
     opc_path = os.path.join(ROOT, "oracle", f"opcount_{POSES_NAME}.json")
     roofline = None
     if os.path.exists(opc_path):
-        roofline = roofline_of(r["phases"], json.load(open(opc_path)), r["K"], POSES_NAME)
+        opc = json.load(open(opc_path))
+        roofline = roofline_of(r["phases"], opc, r["K"], POSES_NAME)
+        if sampler is not None:
+            sampler["roofline"] = sampler_roofline(sampler["phases"], opc, r["K"], POSES_NAME)
     else:
         log(f"[bench] {opc_path} missing: roofline omitted")
 
@@ -472,6 +531,13 @@ def main():
             "steps": args.per_call_steps,
             "render_latency_ms": {"p50": pct(r["per_render"], 50), "p99": pct(r["per_render"], 99)}},
         "batched_vs_per_call": None if r["per_call_ms"] is None else round(r["eager_value"] / r["per_call_value"], 3),
+        "sampler": None if sampler is None else {
+            "what": "Sec. 3.4 Eq. 10: 256 N(0,1) feature maps sampled onto the kernels, one batch call per step",
+            "value": round(sampler["value"], 3), "unit": "Mrays/s", "ms_per_step": round(sampler["ms"], 5),
+            "steps": sampler["steps"], "latency_ms": {"p50": pct(sampler["per"], 50), "p99": pct(sampler["per"], 99)},
+            "graph": {"value": round(sampler["graph_value"], 3), "ms_per_step": round(sampler["graph_ms"], 5)},
+            "phases_us": {k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in sampler["phases"].items()},
+            "roofline": sampler.get("roofline")},
         "single_image": single,
         "serving": serving,
         "phases_us": {k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in r["phases"].items()},

@@ -61,6 +61,9 @@ def count(jobs, name: str) -> dict:
     out["flop_bwd"] = O.backward_flops(ke, C)
     out["flop_bwd_pixel"] = O.FLOP_BPAIR * out["sum_k_eff_sq"] + O.flop_bkept_pixel(C) * out["sum_k_eff"]
     out["flop_bwd_chain"] = O.flop_bkept_chain(C) * out["sum_k_eff"]
+    # the sampler: the forward's blend without the colour sum, then the pair reduction
+    out["flop_blend_weights"] = out["flop_blend"] - 2 * C * out["sum_k_eff"]
+    out["flop_sample_reduce"] = O.flop_sample(C) * out["sum_k_eff"]
     out["flop_forward"] = O.FLOP_TRACE * n_pass + out["flop_blend"]
     out["flop_per_ray_fwd_bwd"] = (out["flop_forward"] + out["flop_bwd"]) / out["rays"]
     out["oracle_seconds"] = round(time.time() - t0, 2)

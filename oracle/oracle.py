@@ -30,6 +30,9 @@ the arithmetic of the formulas as evaluated here, per unit of work:
       symmetric dL/dS (40), dL/dD (20), accumulate M and S gradients (9 minus 3
       counted above).  Of these, 2C + 4 (G.c_k, dm, dE, dq) belong with the
       per-pixel pair work and 106 + 2C with the per-kernel chain.
+  Sampler (Sec. 3.4, Eq. 10; the kept sets and T given by the forward):
+  FLOP_SAMPLE = 2 + 2C per kept kernel: W = T e^q (1), accumulate W phi (2C)
+      and W (1); the C divisions per kernel are per-kernel work, not counted.
 """
 
 from __future__ import annotations
@@ -58,6 +61,10 @@ FLOP_BPAIR = 20
 
 def flop_kept(C: int) -> int:
     return 6 + 2 * C + 2
+
+
+def flop_sample(C: int) -> int:
+    return 2 + 2 * C
 
 
 def flop_bkept(C: int) -> int:

@@ -205,8 +205,9 @@ BatchPlan plan_batch(const ItemShape* shapes, int n) {
         p.total_list += (size_t)it.s.K * it.S;
         p.total_attr += (size_t)it.s.N * it.s.C;
         if (p.groups.empty() || p.groups.back().kb != it.kb)
-            p.groups.push_back({it.kb, j, 0, it.tile_start, 0});
+            p.groups.push_back({it.kb, j, 0, it.tile_start, 0, 1});
         p.groups.back().n_items += 1;
+        p.groups.back().max_c = std::max(p.groups.back().max_c, it.s.C);
         p.groups.back().n_tiles += it.n_tiles;
     }
     int ib = 0;
@@ -478,11 +479,30 @@ int launch_compute(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, 
             for (const auto& g : p.groups)
                 if (int rc = hip_check(voge::launch_select(group_dev(g, w, cfg), g.kb, s), "select launch")) return rc;
         }
+    }
+    if (flags & VOGE_SAMPLE) {
         {
-            ProfScope ps = scope("blend");
-            for (const auto& g : p.groups)
-                if (int rc = hip_check(voge::launch_blend(group_dev(g, w, cfg), g.kb, s), "blend launch")) return rc;
+            ProfScope ps = scope("zero");
+            const size_t nk = p.total_kern > 0 ? (size_t)p.total_kern : 1;
+            voge::launch_fill_u32(w.grads, 9 * nk + p.total_attr, 0u, s);
         }
+        {
+            // the blend, with the sampler's per-tile reduction fused in
+            ProfScope ps = scope("blend_sample");
+            for (const auto& g : p.groups)
+                if (int rc = hip_check(voge::launch_blend_sample(group_dev(g, w, cfg), g.kb, g.max_c, s),
+                                       "blend+sample launch"))
+                    return rc;
+        }
+        {
+            ProfScope ps = scope("sample_epilogue");
+            if (int rc = hip_check(voge::launch_sample_epilogue(b, p.total_epi, s), "sample epilogue launch"))
+                return rc;
+        }
+    } else if (fwd_part) {
+        ProfScope ps = scope("blend");
+        for (const auto& g : p.groups)
+            if (int rc = hip_check(voge::launch_blend(group_dev(g, w, cfg), g.kb, s), "blend launch")) return rc;
     }
     if (flags & VOGE_BACKWARD) {
         {
@@ -504,24 +524,6 @@ int launch_compute(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, 
         {
             ProfScope ps = scope("epilogue");
             if (int rc = hip_check(voge::launch_epilogue(b, p.total_epi, s), "epilogue launch")) return rc;
-        }
-    }
-    if (flags & VOGE_SAMPLE) {
-        {
-            ProfScope ps = scope("zero");
-            const size_t nk = p.total_kern > 0 ? (size_t)p.total_kern : 1;
-            voge::launch_fill_u32(w.grads, 9 * nk + p.total_attr, 0u, s);
-        }
-        {
-            ProfScope ps = scope("sample_reduce");
-            for (const auto& g : p.groups)
-                if (int rc = hip_check(voge::launch_sample_reduce(group_dev(g, w, cfg), g.kb, s), "sample reduce launch"))
-                    return rc;
-        }
-        {
-            ProfScope ps = scope("sample_epilogue");
-            if (int rc = hip_check(voge::launch_sample_epilogue(b, p.total_epi, s), "sample epilogue launch"))
-                return rc;
         }
     }
     return VOGE_OK;

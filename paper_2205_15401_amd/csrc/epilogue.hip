@@ -143,19 +143,19 @@ __global__ __launch_bounds__(FIN_THREADS) void k_cam_finalize(BatchDev B) {
     if (lane == 0) it.grad_camera[e] = (float)(e == 13 || e == 14 ? -s : s);
 }
 
-// Sampler epilogue (Sec. 3.4, Eq. 10): one thread per kernel rank divides
-// the reduced sum_p W phi by sum_p W and writes alpha in original kernel
-// order; a kernel that no pixel keeps gets alpha = 0 and weight 0.
+// Sampler epilogue (Sec. 3.4, Eq. 10): one thread per kernel divides the
+// reduced sum_p W phi by sum_p W (both in original kernel order); a kernel
+// that no pixel keeps gets alpha = 0 and weight 0.
 __global__ __launch_bounds__(EPI_THREADS) void k_sample_epilogue(BatchDev B) {
     const int item = B.n_items == 1 ? 0 : B.epi_item[blockIdx.x];
     const ItemDev it = B.items[item];     // a copy, read before any store
     const TraceArgs& A = it.t;
     const int r = (blockIdx.x - it.epi_start) * EPI_THREADS + threadIdx.x;
     if (r >= A.N) return;
-    const size_t n = A.rec[r].idx;
+    const size_t n = r;
     const int C = A.C;
-    const float den = A.gW[r];
-    const float* num = A.gA + (size_t)r * C;
+    const float den = A.gW[n];
+    const float* num = A.gA + n * C;
     float* out = it.sampled + n * C;
     if (den > 0.f) {
         for (int c = 0; c < C; ++c) out[c] = num[c] / den;

@@ -306,9 +306,102 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
     A.keff[P.q] = keff;
 }
 
+// ----------------------------------------------------------------- sampler
+//
+// The sampler of Sec. 3.4 (Eq. 10) rides on the blend: once the blend has
+// written a pixel's transmittances, the lane adds W_k = T_k e^{q_k} and
+// W_k phi_p to its kernels' entries in a per-tile table in LDS (a hash on the
+// original kernel index, float atomic adds); after a barrier each used entry
+// makes one global atomic add per value.  Feature maps of more than SAMPLE_CH channels take
+// one pass per SAMPLE_CH channels over the same table; pairs whose kernel
+// finds the table full go to global memory directly.
+constexpr int SAMPLE_HCAP = 1024;     // distinct kernels per tile held in LDS
+constexpr int SAMPLE_CH = 8;          // feature channels per pass
+
+size_t sample_lds_bytes(int max_c) {
+    const int nv = (max_c < SAMPLE_CH ? max_c : SAMPLE_CH) + 1;
+    return (size_t)SAMPLE_HCAP * (1 + nv) * sizeof(float);
+}
+
+__device__ __forceinline__ int hash_insert(int* s_key, int hmask, int key) {
+    int h = (int)(((uint32_t)key * 2654435761u) >> 7) & hmask;
+    for (int probe = 0; probe <= hmask; ++probe) {
+        const int cur = atomicCAS(&s_key[h], -1, key);
+        if (cur == -1 || cur == key) return h;
+        h = (h + 1) & hmask;
+    }
+    return -1;
+}
+
+// `q`: the pixel's list index; its weights are read back from the lists the
+// blend has just written (W = T e^q, the product the blend forms).
+__device__ __forceinline__ void sample_tile(const TraceArgs& A, bool valid, size_t q, size_t p, int keff,
+                                            unsigned char* smem) {
+    const int tid = threadIdx.x;
+    const int C = A.C;
+    const size_t S = A.S;
+    const int nv = min(C, SAMPLE_CH) + 1;        // per entry: the weight sum, then one pass's channels
+    int* s_key = reinterpret_cast<int*>(smem);
+    float* s_val = reinterpret_cast<float*>(s_key + SAMPLE_HCAP);
+    for (int i = tid; i < SAMPLE_HCAP; i += TILE_THREADS) s_key[i] = -1;
+    for (int i = tid; i < SAMPLE_HCAP * nv; i += TILE_THREADS) s_val[i] = 0.f;
+    __syncthreads();
+    const float* phi = A.grad_image + p * C;
+    const float* pT = A.kl_T + q;
+    const float* pm = A.kl_m + q;
+    const int* pi = A.kl_i + q;
+    for (int c0 = 0; c0 == 0 || c0 < C; c0 += SAMPLE_CH) {
+        const int nc = min(SAMPLE_CH, C - c0);
+        if (c0 > 0) {
+            for (int i = tid; i < SAMPLE_HCAP * nv; i += TILE_THREADS) s_val[i] = 0.f;
+            __syncthreads();
+        }
+        float f[SAMPLE_CH];
+#pragma unroll
+        for (int c = 0; c < SAMPLE_CH; ++c) f[c] = (valid && keff > 0 && c < nc) ? phi[c0 + c] : 0.f;
+        // slot k+1 is loaded while slot k is added
+        float Tn = keff > 0 ? pT[0] : 0.f, mn = keff > 0 ? pm[0] : 0.f;
+        int in = keff > 0 ? pi[0] : 0;
+        for (int k = 0; k < keff; ++k) {
+            const float w = Tn * mn;
+            const int key = in;
+            if (k + 1 < keff) {
+                const size_t o = (size_t)(k + 1) * S;
+                Tn = pT[o];
+                mn = pm[o];
+                in = pi[o];
+            }
+            // the kernel's entry (inserted by the first pass, found by later ones)
+            const int h = hash_insert(s_key, SAMPLE_HCAP - 1, key);
+            if (h >= 0) {
+                float* v = s_val + h * nv;
+                if (c0 == 0) atomicAdd(v, w);
+#pragma unroll
+                for (int c = 0; c < SAMPLE_CH; ++c)
+                    if (c < nc) atomicAdd(v + 1 + c, w * f[c]);
+            } else {
+                if (c0 == 0) unsafeAtomicAdd(&A.gW[key], w);
+#pragma unroll
+                for (int c = 0; c < SAMPLE_CH; ++c)
+                    if (c < nc) unsafeAtomicAdd(&A.gA[(size_t)key * C + c0 + c], w * f[c]);
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < SAMPLE_HCAP; i += TILE_THREADS) {
+            const int key = s_key[i];
+            if (key < 0) continue;
+            const float* v = s_val + i * nv;
+            if (c0 == 0) unsafeAtomicAdd(&A.gW[key], v[0]);
+            for (int c = 0; c < nc; ++c) unsafeAtomicAdd(&A.gA[(size_t)key * C + c0 + c], v[1 + c]);
+        }
+        if (c0 + SAMPLE_CH < C) __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------------- blend
-template <int KB>
-__device__ __forceinline__ void blend_body(const TraceArgs& A, int tile) {
+// SAMPLE: also run the sampler on the tile (smem: sample_lds_bytes).
+template <int KB, bool SAMPLE>
+__device__ __forceinline__ void blend_body(const TraceArgs& A, int tile, unsigned char* smem) {
     const int ntx = (A.W + TILE - 1) / TILE;
     const PixelCtx P = pixel_at(tile, balanced_slot(A, tile, ntx), ntx, A.H, A.W, A.cx, A.cy);
     const size_t S = A.S;
@@ -349,7 +442,7 @@ __device__ __forceinline__ void blend_body(const TraceArgs& A, int tile) {
             }
         }
     }
-    if (!P.valid) return;
+    if (!SAMPLE && !P.valid) return;
     const size_t p = (size_t)P.pi * A.W + P.pj;
     float Wt[KB];
     int ik[KB];
@@ -367,6 +460,8 @@ __device__ __forceinline__ void blend_body(const TraceArgs& A, int tile) {
             ws += Wt[k];
         }
     }
+    if (SAMPLE) sample_tile(A, P.valid, P.q, p, keff, smem);
+    if (!P.valid) return;
     if (A.image) {
         if ((A.C & 3) == 0) {
             // four channels per load and store
@@ -479,20 +574,14 @@ constexpr int RED_CH = 8;              // attribute channels per reduction pass
 constexpr int RED_NV = 9 + RED_CH;     // values per partial sum
 
 // Add one kernel's partial sums to global memory: the 9 geometric values
-// (pass 0 only; the sampler has one, the weight sum, in their place) and
-// attribute channels c0 .. c0+nc-1.
-template <bool SAMPLE>
+// (pass 0 only) and attribute channels c0 .. c0+nc-1.
 __device__ __forceinline__ void flush_values(const TraceArgs& A, int rank, const float* v, bool geom, int c0,
                                              int nc) {
     if (geom) {
-        if (SAMPLE) {
-            unsafeAtomicAdd(&A.gW[rank], v[0]);
-        } else {
 #pragma unroll
-            for (int q = 0; q < 3; ++q) unsafeAtomicAdd(&A.gM[(size_t)rank * 3 + q], v[q]);
+        for (int q = 0; q < 3; ++q) unsafeAtomicAdd(&A.gM[(size_t)rank * 3 + q], v[q]);
 #pragma unroll
-            for (int q = 0; q < 6; ++q) unsafeAtomicAdd(&A.gS[(size_t)rank * 6 + q], v[3 + q]);
-        }
+        for (int q = 0; q < 6; ++q) unsafeAtomicAdd(&A.gS[(size_t)rank * 6 + q], v[3 + q]);
     }
     for (int q = 0; q < nc; ++q) unsafeAtomicAdd(&A.gA[(size_t)rank * A.C + c0 + q], v[9 + q]);
 }
@@ -618,10 +707,7 @@ __device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile) {
 }
 
 // Backward, tile phase: group the tile's pairs by kernel and reduce them.
-// SAMPLE: the sampler of Sec. 3.4 (Eq. 10) on the same pairs -- the pixel map
-// is phi, a pair's weight is W = T e^q of the forward, and pass 0 sums W
-// instead of running the geometric chain.
-template <int KB, bool SAMPLE>
+template <int KB>
 __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int tile, unsigned char* smem) {
     __shared__ double s_red[TILE_THREADS / WAVE][3];
     __shared__ int s_scan[TILE_THREADS];
@@ -711,31 +797,16 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
         if (k < keff) {
             if (sp[k] >= 0) {
                 const size_t o = (size_t)k * S;
+                const float4 sc = pbw[o];
                 PairRec r;
-                if (SAMPLE) {
-                    r.dq = 0.f;
-                    r.dl = 0.f;
-                    r.da = 0.f;
-                    r.w = A.kl_T[P.q + o] * A.kl_m[P.q + o];   // the blend's W, same rounding
-                    r.l = 0.0;
-                } else {
-                    const float4 sc = pbw[o];
-                    r.dq = sc.x;
-                    r.dl = sc.y + pbl[o];
-                    r.da = sc.z;
-                    r.w = sc.w;
-                    r.l = pl[o];
-                }
+                r.dq = sc.x;
+                r.dl = sc.y + pbl[o];
+                r.da = sc.z;
+                r.w = sc.w;
+                r.l = pl[o];
                 r.pt = tid;
                 r.rank = rk[k];
                 tile_pairs[s_off[sp[k] >> 16] + (sp[k] & 0xFFFF)] = r;
-            } else if (SAMPLE) {
-                // table full: this pair goes straight to global memory
-                const size_t o = (size_t)k * S;
-                const int rank = rk[k];
-                const float w = A.kl_T[P.q + o] * A.kl_m[P.q + o];
-                unsafeAtomicAdd(&A.gW[rank], w);
-                for (int c = 0; c < C; ++c) unsafeAtomicAdd(&A.gA[(size_t)rank * C + c], w * Gp[c]);
             } else {
                 // table full: this pair goes straight to global memory
                 const size_t o = (size_t)k * S;
@@ -795,7 +866,7 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
                         s_tk[tid] = cur;
                         for (int q = v0; q < RED_NV; ++q) s_tail[tid * RED_NV + q] = acc[q];
                     } else {                                           // complete run
-                        flush_values<SAMPLE>(A, cur, acc, geom, c0, nc);
+                        flush_values(A, cur, acc, geom, c0, nc);
                     }
                     ++nseg;
                 }
@@ -803,13 +874,11 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
 #pragma unroll
                 for (int q = 0; q < RED_NV; ++q) acc[q] = 0.f;
                 cur = r.rank;
-                if (geom && !SAMPLE) G = A.geo[cur];
+                if (geom) G = A.geo[cur];
             }
             const int w = r.pt / WAVE, ln = r.pt % WAVE;
             const int row = ti0 + (w >> 1) * 8 + (ln >> 3), col = tj0 + (w & 1) * 8 + (ln & 7);
-            if (geom && SAMPLE) {
-                acc[0] += r.w;
-            } else if (geom) {
+            if (geom) {
                 double out[9];
                 pair_chain(G, (double)row - (double)A.cy, (double)col - (double)A.cx, (double)A.F, r.l, r.dq, r.dl,
                            r.da, out, gD);
@@ -848,12 +917,11 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
                 for (int q = v0; q < RED_NV; ++q) sum[q] += s_head[t2 * RED_NV + q];
                 if (s_tk[t2] >= 0) break;                             // the run ends inside chunk t2
             }
-            flush_values<SAMPLE>(A, k, sum, geom, c0, nc);
+            flush_values(A, k, sum, geom, c0, nc);
         }
         __syncthreads();
     }
 
-    if (SAMPLE) return;
     // per-tile sum of dL/dD' (for the intrinsics), fixed order
     const int wave = tid / WAVE, lane = tid % WAVE;
     const double gx = wave_sum(gD[0]), gy = wave_sum(gD[1]), gz = wave_sum(gD[2]);
@@ -899,7 +967,15 @@ template <int KB>
 __global__ __launch_bounds__(TILE_THREADS) void k_blend(GroupDev g) {
     int tile;
     const TraceArgs A = item_view(g, tile);
-    blend_body<KB>(A, tile);
+    blend_body<KB, false>(A, tile, nullptr);
+}
+
+template <int KB>
+__global__ __launch_bounds__(TILE_THREADS) void k_blend_sample(GroupDev g) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    int tile;
+    const TraceArgs A = item_view(g, tile);
+    blend_body<KB, true>(A, tile, smem);
 }
 
 template <int KB>
@@ -914,15 +990,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_bwd_red(GroupDev g, int hcap) 
     extern __shared__ __align__(16) unsigned char smem[];
     int tile;
     const TraceArgs A = item_view(g, tile);
-    bwd_red_body<KB, false>(A, hcap, tile, smem);
-}
-
-template <int KB>
-__global__ __launch_bounds__(TILE_THREADS) void k_sample_red(GroupDev g, int hcap) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    int tile;
-    const TraceArgs A = item_view(g, tile);
-    bwd_red_body<KB, true>(A, hcap, tile, smem);
+    bwd_red_body<KB>(A, hcap, tile, smem);
 }
 
 // Diagnostics: the device Phi on an array.
@@ -946,7 +1014,7 @@ int table_capacity(int C) {
 }
 
 template <int KB>
-static hipError_t run_kb(int which, const GroupDev& g, hipStream_t s) {
+static hipError_t run_kb(int which, const GroupDev& g, hipStream_t s, int max_c = 1) {
     const int nt = g.n_tiles;
     if (nt <= 0) return hipSuccess;
     if (which == 0) {
@@ -959,19 +1027,18 @@ static hipError_t run_kb(int which, const GroupDev& g, hipStream_t s) {
         const int hcap = table_capacity(0);
         hipLaunchKernelGGL(k_bwd_red<KB>, dim3(nt), dim3(TILE_THREADS), bwd_lds_bytes(hcap, KB), s, g, hcap);
     } else {
-        const int hcap = table_capacity(0);
-        hipLaunchKernelGGL(k_sample_red<KB>, dim3(nt), dim3(TILE_THREADS), bwd_lds_bytes(hcap, KB), s, g, hcap);
+        hipLaunchKernelGGL(k_blend_sample<KB>, dim3(nt), dim3(TILE_THREADS), sample_lds_bytes(max_c), s, g);
     }
     return hipGetLastError();
 }
 
-static hipError_t dispatch(int which, const GroupDev& g, int kb, hipStream_t s) {
+static hipError_t dispatch(int which, const GroupDev& g, int kb, hipStream_t s, int max_c = 1) {
     switch (kb) {
-        case 8: return run_kb<8>(which, g, s);
-        case 16: return run_kb<16>(which, g, s);
-        case 20: return run_kb<20>(which, g, s);
-        case 32: return run_kb<32>(which, g, s);
-        default: return run_kb<64>(which, g, s);
+        case 8: return run_kb<8>(which, g, s, max_c);
+        case 16: return run_kb<16>(which, g, s, max_c);
+        case 20: return run_kb<20>(which, g, s, max_c);
+        case 32: return run_kb<32>(which, g, s, max_c);
+        default: return run_kb<64>(which, g, s, max_c);
     }
 }
 
@@ -979,7 +1046,9 @@ hipError_t launch_select(const GroupDev& g, int kb, hipStream_t s) { return disp
 hipError_t launch_blend(const GroupDev& g, int kb, hipStream_t s) { return dispatch(1, g, kb, s); }
 hipError_t launch_bwd(const GroupDev& g, int kb, hipStream_t s) { return dispatch(2, g, kb, s); }
 hipError_t launch_bwd_reduce(const GroupDev& g, int kb, hipStream_t s) { return dispatch(3, g, kb, s); }
-hipError_t launch_sample_reduce(const GroupDev& g, int kb, hipStream_t s) { return dispatch(4, g, kb, s); }
+hipError_t launch_blend_sample(const GroupDev& g, int kb, int max_c, hipStream_t s) {
+    return dispatch(4, g, kb, s, max_c);
+}
 
 hipError_t launch_phi(const float* x, float* y, int n, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(k_phi, dim3((n + 255) / 256), dim3(256), 0, s, x, y, n);

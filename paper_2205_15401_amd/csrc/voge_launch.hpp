@@ -48,11 +48,10 @@ struct TraceArgs {
     float* image;
     float* wsum;
     int32_t* kept;
-    // backward, and the sampler of Sec. 3.4 (Eq. 10), which reduces the same
-    // pairs with phi in place of dL/dC and no geometric chain
+    // backward, and the sampler of Sec. 3.4 (Eq. 10)
     const float* grad_image;   // per-pixel map reduced onto the kernels: dL/dC, or phi when sampling
-    float* gA;                 // [N][C] attribute gradients (sampling: sum_p W phi) in rank order
-    float* gW;                 // [N] sampling: sum_p W, rank order (shares gM's storage)
+    float* gA;                 // [N][C] attribute gradients in rank order (sampling: sum_p W phi, original order)
+    float* gW;                 // [N] sampling: sum_p W, original order (shares gM's storage)
     float* gM;                 // [N][3] camera-space centre gradients, rank order
     float* gS;                 // [N][6] camera-space inverse-covariance gradients
     double* tileD;             // [n_tiles][3] per-tile sums of dL/dD'
@@ -126,6 +125,7 @@ struct GroupPlan {
     int kb;
     int first_item, n_items;
     int tile0, n_tiles;
+    int max_c;                 // largest channel count of the group's items
 };
 
 struct BatchPlan {
@@ -169,7 +169,8 @@ hipError_t launch_select(const GroupDev& g, int kb, hipStream_t s);
 hipError_t launch_blend(const GroupDev& g, int kb, hipStream_t s);
 hipError_t launch_bwd(const GroupDev& g, int kb, hipStream_t s);          // pixel phase
 hipError_t launch_bwd_reduce(const GroupDev& g, int kb, hipStream_t s);   // tile reduction
-hipError_t launch_sample_reduce(const GroupDev& g, int kb, hipStream_t s); // sampler: tile reduction
+// blend plus the sampler; max_c: the largest channel count of the group's items
+hipError_t launch_blend_sample(const GroupDev& g, int kb, int max_c, hipStream_t s);
 hipError_t launch_phi(const float* x, float* y, int n, hipStream_t s);
 hipError_t launch_epilogue(const BatchDev& b, int total_epi, hipStream_t s);
 hipError_t launch_sample_epilogue(const BatchDev& b, int total_epi, hipStream_t s);

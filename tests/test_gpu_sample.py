@@ -79,7 +79,7 @@ def check_sample(alpha_gpu, weight_gpu, scene, cam, K, eta, phi, kept_gpu=None, 
     return ref, int(m.sum())
 
 
-@pytest.mark.parametrize("C", [1, 3, 5, 16])
+@pytest.mark.parametrize("C", [1, 3, 5, 16, 40])
 def test_single_call_matches_the_oracle(C):
     """A torus of 3,000 kernels at 72 x 88 (ragged tiles of 16), C channels
     (one and several reduction passes, with and without four-channel rows)."""
