@@ -307,6 +307,42 @@ def bench_sampler(args, torch, dev, jobs):
             "phases": phases, "steps": steps}
 
 
+def bench_fit(args, torch, dev):
+    """The multi-view fitting loop at the paper's setting: a 2,562-kernel
+    sphere fitted to 20 views (128 x 128) of a 10,242-kernel target, 5 random
+    views per iteration, Adam on centres and colours, MSE on RGB and
+    silhouette.  The targets are rendered once by this renderer."""
+    from paper_2205_15401_amd import fit as FIT
+    from paper_2205_15401_amd import scenes as S
+
+    target, start = S.bumpy_target(5), S.sphere_start(4)
+    cams = S.multiview_cameras(20, 128)
+    views = FIT.Views(cams, K=20)
+    to = lambda x: torch.from_numpy(x).to(dev)  # noqa: E731
+    with torch.no_grad():
+        img = views.render(to(target.means), to(target.covs), FIT.silhouette_attrs(to(target.attrs)))
+    t_rgb, t_sil = img[..., :3].contiguous(), img[..., 3].contiguous()
+    m0, c0, col0 = to(start.means), to(start.covs), to(start.attrs)
+    FIT.fit_views(views, m0, c0, col0, t_rgb, t_sil, iters=10, seed=0)           # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    _, _, hist = FIT.fit_views(views, m0, c0, col0, t_rgb, t_sil, iters=args.fit_iters, seed=1)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / args.fit_iters
+    rays = 5 * 128 * 128
+    log(f"[bench] fit: {args.fit_iters} iterations, {ms:.3f} ms/iteration ({rays / ms / 1e3:.1f} Mrays/s fwd+bwd), "
+        f"loss {float(hist[:10].mean()):.5f} -> {float(hist[-50:].mean()):.5f}")
+    return {"what": "shape fitting: 2562-kernel sphere to 20 views of a 10242-kernel target, 5 views/iteration, "
+                    "Adam on centres and colours, MSE on RGB + silhouette",
+            "iterations": args.fit_iters, "ms_per_iteration": round(ms, 5), "iterations_per_s": round(1e3 / ms, 2),
+            "rays_per_iteration": rays, "value": round(rays / ms / 1e3, 3), "unit": "Mrays/s", "wall_s": round(wall, 3),
+            "loss_first10": round(float(hist[:10].mean()), 6), "loss_last50": round(float(hist[-50:].mean()), 6)}
+
+
 def sampler_roofline(phases, opc, K, workload):
     """The sampler step's dominant kernel against the FP32 vector peak."""
     flops = {"select": opc["flop_select"], "blend_sample": opc["flop_blend_weights"] + opc["flop_sample_reduce"]}
@@ -442,6 +478,7 @@ def main():
     ap.add_argument("--torus-steps", type=int, default=50, help="timed steps of the single 512x512 image")
     ap.add_argument("--cpu-sample", type=int, default=1048576, help="rays for the oracle baseline (0 = skip)")
     ap.add_argument("--sample-steps", type=int, default=20, help="timed steps of the sampler (0 = skip)")
+    ap.add_argument("--fit-iters", type=int, default=2000, help="iterations of the fitting loop (0 = skip)")
     ap.add_argument("--serving-requests", type=int, default=600, help="timed requests per load (0 = skip serving)")
     ap.add_argument("--serving-warmup", type=int, default=100)
     ap.add_argument("--serving-capacity-requests", type=int, default=200)
@@ -484,6 +521,7 @@ def main():
         return
     r = bench_poses(args, torch, dev)
     sampler = bench_sampler(args, torch, dev, r["jobs"]) if args.sample_steps > 0 else None
+    fit = bench_fit(args, torch, dev) if args.fit_iters > 0 else None
     single = bench_torus(args, torch, dev) if args.torus_steps > 0 else None
     serving = bench_serving(args, torch, dev) if args.serving_requests > 0 else None
     calibration_copy()
@@ -538,6 +576,7 @@ def main():
             "graph": {"value": round(sampler["graph_value"], 3), "ms_per_step": round(sampler["graph_ms"], 5)},
             "phases_us": {k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in sampler["phases"].items()},
             "roofline": sampler.get("roofline")},
+        "fit": fit,
         "single_image": single,
         "serving": serving,
         "phases_us": {k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in r["phases"].items()},

@@ -257,6 +257,44 @@ def random_pose(rng: np.random.Generator, size: int, dist_range=(2.5, 4.0),
     return look_at_camera(pos, size)
 
 
+def multiview_cameras(n: int = 20, size: int = 128, dist: float = 3.5, focal_scale: float = 1.2,
+                      elev_deg: float = 15.0) -> List[Camera]:
+    """n look-at views around the origin: azimuths evenly spaced, elevation
+    alternating +-elev_deg, all at distance dist (the multi-view setting of
+    the shape-fitting experiment)."""
+    cams = []
+    for k in range(n):
+        az = 2.0 * math.pi * k / n
+        el = math.radians(elev_deg if k % 2 == 0 else -elev_deg)
+        pos = dist * np.array([math.cos(el) * math.sin(az), math.sin(el), math.cos(el) * math.cos(az)])
+        cams.append(look_at_camera(pos, size, focal=focal_scale * size))
+    return cams
+
+
+def bumpy_target(subdivisions: int = 5, amplitude: float = 0.4, flatten: float = 0.3) -> Scene:
+    """A synthetic fitting target: an icosphere pushed out radially by
+    1 + amplitude sin(3x) cos(2y) sin(2z + 1), converted to flattened
+    Gaussians (zeta = 0.5), coloured by its unit normal, 0.5 + 0.5 n."""
+    from .convert import icosphere, mesh_to_gaussians, vertex_normals
+
+    v, f = icosphere(subdivisions)
+    r = 1.0 + amplitude * np.sin(3 * v[:, 0]) * np.cos(2 * v[:, 1]) * np.sin(2 * v[:, 2] + 1.0)
+    v = v * r[:, None]
+    means, covs = mesh_to_gaussians(v, f, 0.5, flatten=flatten)
+    colors = (0.5 + 0.5 * vertex_normals(v, f)).astype(np.float32)
+    return Scene(means=means, covs=covs, attrs=colors)
+
+
+def sphere_start(subdivisions: int = 4, radius: float = 1.0, gray: float = 0.5) -> Scene:
+    """The fitting start: an icosphere (2,562 vertices at 4 subdivisions)
+    converted to isotropic Gaussians (zeta = 0.5), uniform grey."""
+    from .convert import icosphere, mesh_to_gaussians
+
+    v, f = icosphere(subdivisions, radius)
+    means, covs = mesh_to_gaussians(v, f, 0.5)
+    return Scene(means=means, covs=covs, attrs=np.full((v.shape[0], 3), gray, np.float32))
+
+
 def upstream_gradient(rng: np.random.Generator, h: int, w: int, c: int) -> np.ndarray:
     return rng.standard_normal((h, w, c)).astype(np.float32)
 
