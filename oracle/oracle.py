@@ -102,7 +102,7 @@ def _lib():
             Dbl = ctypes.c_double
             lib.oracle_forward.argtypes = [P, P, P, I, I, P, I, I, Dbl, I, P, L, I, P, P, P, P, P, P, P]
             lib.oracle_forward.restype = I
-            lib.oracle_backward.argtypes = [P, P, P, I, I, P, I, I, Dbl, I, P, L, P, I, P, P, P, P, P, P, P, P]
+            lib.oracle_backward.argtypes = [P, P, P, I, I, P, I, I, Dbl, I, P, L, P, I, P, P, P, P, P, P, P, P, I]
             lib.oracle_backward.restype = I
             lib.oracle_quadrature.argtypes = [P, P, I, P, I, I, Dbl, I, P, L, I, I, P, P, P]
             lib.oracle_quadrature.restype = I
@@ -178,10 +178,16 @@ class BackwardResult:
         self.n_invalid = 0
 
 
+BLOCK_T = 1      # ablation: no gradient through the transmittance T(l_k)
+BLOCK_RHO = 2    # ablation: no gradient through the factor e^{q_k} of Eq. 8
+
+
 def backward(means, covs, attrs, cam_vec, H: int, W: int, K: int, grad, eta: float = 0.01,
-             pixels: Optional[Sequence[int]] = None, threads: int = 0) -> BackwardResult:
+             pixels: Optional[Sequence[int]] = None, threads: int = 0, mode: int = 0) -> BackwardResult:
     """Gradients of sum_p <grad_p, C_p> over the given pixels (grad is
-    (n_pix, C), or (H, W, C) when pixels is None)."""
+    (n_pix, C), or (H, W, C) when pixels is None).  mode: 0, or BLOCK_T and/or
+    BLOCK_RHO, the gradient ablations of the paper's pose-estimation ablation
+    table ("w/o grad T(r)" and "w/o grad rho(r)")."""
     m, c, a, cv = _f64(means), _f64(covs), _f64(attrs), _f64(cam_vec)
     N, C = m.shape[0], a.shape[1]
     pix, n = _pix(pixels, H, W)
@@ -190,7 +196,8 @@ def backward(means, covs, attrs, cam_vec, H: int, W: int, K: int, grad, eta: flo
     rc = _lib().oracle_backward(_ptr(m), _ptr(c), _ptr(a), N, C, _ptr(cv), H, W, float(eta), K,
                                 _ptr(pix), n, _ptr(g), threads,
                                 _ptr(r.means), _ptr(r.covs), _ptr(r.attrs), _ptr(r.camera),
-                                _ptr(r.abs_means), _ptr(r.abs_covs), _ptr(r.abs_attrs), _ptr(r.abs_camera))
+                                _ptr(r.abs_means), _ptr(r.abs_covs), _ptr(r.abs_attrs), _ptr(r.abs_camera),
+                                int(mode))
     if rc < 0:
         raise ValueError("oracle_backward: bad arguments")
     r.n_invalid = rc

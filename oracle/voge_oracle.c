@@ -52,6 +52,10 @@
 #define OR_FLAG_TIE 1      /* |l_K - l_{K+1}| <= 1e-6 l_K: the K-th place is a near tie   */
 #define OR_FLAG_ETA 2      /* some kernel with l > 0 sits within 1e-5 of the threshold q  */
 
+/* gradient ablations of oracle_backward (grad_mode bits) */
+#define ORACLE_BLOCK_T 1     /* no gradient through the transmittance T(l_k)               */
+#define ORACLE_BLOCK_RHO 2   /* no gradient through the factor e^{q_k} of Eq. 8            */
+
 typedef struct {
     double R[9], T[3];
     double F, Ox, Oy;
@@ -371,12 +375,14 @@ void oracle_transmittance(const double* rec, int n, const double* t, int nt, dou
  * linear steps (each pair term of the transmittance derivative, each term of
  * the chain to world space), i.e. the sum of the absolute values of all
  * per-pair contributions to that element.
+ * grad_mode: 0, or ORACLE_BLOCK_T and/or ORACLE_BLOCK_RHO (the gradient
+ * ablations of the paper's pose-estimation ablation table).
  * Returns the number of skipped kernels or -1. */
 int oracle_backward(const double* means, const double* covs, const double* attrs, int N, int C,
                     const double* cam15, int H, int W, double eta, int K,
                     const int64_t* pix, int64_t n_pix, const double* grad_pix, int nthreads,
                     double* g_means, double* g_covs, double* g_attrs, double* g_cam,
-                    double* a_means, double* a_covs, double* a_attrs, double* a_cam) {
+                    double* a_means, double* a_covs, double* a_attrs, double* a_cam, int grad_mode) {
     if (check_args(N, C, H, W, eta, K)) return -1;
     cam_t cam;
     load_camera(cam15, H, W, &cam);
@@ -437,11 +443,15 @@ int oracle_backward(const double* means, const double* covs, const double* attrs
                     gA[(size_t)kept[k].idx * C + c] += Wt[k] * G[c];
                     aA[(size_t)kept[k].idx * C + c] += fabs(Wt[k] * G[c]);
                 }
-                /* W_k = exp(-E_k) e^{q_k}: direct path through e^{q_k}, and dL/dE_k */
-                dm[k] = g * exp(-E[k]);
-                adm[k] = ag * exp(-E[k]);
-                dE[k] = -g * Wt[k];
-                adE[k] = ag * Wt[k];
+                /* W_k = exp(-E_k) e^{q_k}: direct path through e^{q_k}, and dL/dE_k.
+                 * The ablations of the paper's pose-estimation table stop one
+                 * of the two: ORACLE_BLOCK_T the path through the
+                 * transmittance T = exp(-E), ORACLE_BLOCK_RHO the direct
+                 * factor e^{q_k} of Eq. 8 (e^{q_m} inside E stays). */
+                dm[k] = (grad_mode & ORACLE_BLOCK_RHO) ? 0.0 : g * exp(-E[k]);
+                adm[k] = (grad_mode & ORACLE_BLOCK_RHO) ? 0.0 : ag * exp(-E[k]);
+                dE[k] = (grad_mode & ORACLE_BLOCK_T) ? 0.0 : -g * Wt[k];
+                adE[k] = (grad_mode & ORACLE_BLOCK_T) ? 0.0 : ag * Wt[k];
                 dl[k] = da[k] = adl[k] = ada[k] = 0.0;
             }
             /* E_k = sum_m m_m Phi(x_km),  x_km = (l_k - l_m) sqrt(a_m),

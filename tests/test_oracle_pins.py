@@ -506,3 +506,59 @@ def test_p9_sampler_numerator_is_the_attribute_gradient():
     s = O.sample(sc.means, sc.covs, cv, H, W, 16, G)
     b = O.backward(sc.means, sc.covs, sc.attrs, cv, H, W, 16, G)
     np.testing.assert_allclose(s.num, b.attrs, rtol=1e-10, atol=1e-12 * np.abs(b.attrs).max())
+
+
+# ---------------------------------------------------------------------------
+# P10: gradient ablations (the pose-estimation ablation table: "w/o grad T",
+#      "w/o grad rho")
+# ---------------------------------------------------------------------------
+
+def test_p10_lone_kernel_ablation_factors():
+    """A lone kernel: C = m e^{-m/2} c with m = e^q, so dC/dm is
+    (1 - m/2) e^{-m/2} c in full, e^{-m/2} c without the gradient through T
+    and -(m/2) e^{-m/2} c without the gradient through e^q; the chain from m
+    to the geometry is shared, so every geometric gradient scales by those
+    factors."""
+    cv = cam_vec()
+    means = np.array([[0.2, -0.1, 3.0]])
+    covs = packed(SIGMAS[2])[None]
+    attrs = np.array([[0.7, -1.3]])
+    pix = [37 * 64 + 30]
+    fwd = O.forward(means, covs, attrs, cv, 64, 64, 4, pixels=pix)
+    assert fwd.kept_idx[0, 0] == 0
+    m = math.exp(fwd.kept_rec[0, 0, 1])
+    G = np.array([[0.4, 0.9]])
+    full = O.backward(means, covs, attrs, cv, 64, 64, 4, G, pixels=pix)
+    bt = O.backward(means, covs, attrs, cv, 64, 64, 4, G, pixels=pix, mode=O.BLOCK_T)
+    br = O.backward(means, covs, attrs, cv, 64, 64, 4, G, pixels=pix, mode=O.BLOCK_RHO)
+    f_full, f_t, f_r = 1 - m / 2, 1.0, -m / 2
+    for name in ("means", "covs", "camera"):
+        g = getattr(full, name)
+        assert np.abs(g).max() > 0
+        np.testing.assert_allclose(getattr(bt, name) * f_full, g * f_t, rtol=1e-9, atol=1e-14)
+        np.testing.assert_allclose(getattr(br, name) * f_full, g * f_r, rtol=1e-9, atol=1e-14)
+    for r in (bt, br):
+        np.testing.assert_allclose(r.attrs, full.attrs, rtol=1e-13, atol=0)
+
+
+def test_p10_ablations_split_the_gradient():
+    """The geometric gradient is the sum of the path through T and the
+    direct path through e^q, so full = (w/o grad rho) + (w/o grad T), and
+    with both blocked only the attribute gradient is left."""
+    job = S.config_small()
+    sc = job.scene
+    cv = job.camera.as_vector()
+    rng = np.random.default_rng(10)
+    G = rng.standard_normal((64, 64, 3))
+    full = O.backward(sc.means, sc.covs, sc.attrs, cv, 64, 64, 16, G)
+    bt = O.backward(sc.means, sc.covs, sc.attrs, cv, 64, 64, 16, G, mode=O.BLOCK_T)
+    br = O.backward(sc.means, sc.covs, sc.attrs, cv, 64, 64, 16, G, mode=O.BLOCK_RHO)
+    both = O.backward(sc.means, sc.covs, sc.attrs, cv, 64, 64, 16, G, mode=O.BLOCK_T | O.BLOCK_RHO)
+    for name in ("means", "covs", "camera"):
+        g = getattr(full, name)
+        scale = np.abs(getattr(full, "abs_" + name)).max()
+        np.testing.assert_allclose(getattr(bt, name) + getattr(br, name), g, rtol=0, atol=1e-12 * scale)
+        assert np.abs(getattr(bt, name) - g).max() > 1e-6 * scale       # each ablation changes it
+        assert np.abs(getattr(br, name) - g).max() > 1e-6 * scale
+        assert np.all(getattr(both, name) == 0.0)
+    np.testing.assert_allclose(both.attrs, full.attrs, rtol=1e-12, atol=1e-15)
