@@ -63,10 +63,12 @@ extern "C" {
 #define VOGE_STATUS_NOTSPD 1     /* some covariance was not SPD (skipped)      */
 #define VOGE_STATUS_NONFINITE 2  /* some centre or covariance was not finite   */
 
-/* Call flags.  voge_render_backward and voge_sample take VOGE_REUSE_PREP
- * alone; voge_render_batch takes VOGE_FORWARD with VOGE_BACKWARD or
- * VOGE_SAMPLE or neither, or VOGE_BACKWARD or VOGE_SAMPLE alone, optionally
- * with VOGE_REUSE_PREP (without VOGE_FORWARD), VOGE_GRAPH and VOGE_TUNED. */
+/* Call flags.  voge_render_backward takes VOGE_REUSE_PREP, VOGE_BLOCK_T and
+ * VOGE_BLOCK_RHO; voge_sample takes VOGE_REUSE_PREP alone; voge_render_batch
+ * takes VOGE_FORWARD with VOGE_BACKWARD or VOGE_SAMPLE or neither, or
+ * VOGE_BACKWARD or VOGE_SAMPLE alone, optionally with VOGE_REUSE_PREP
+ * (without VOGE_FORWARD), VOGE_GRAPH, VOGE_TUNED and (with VOGE_BACKWARD)
+ * the two ablation bits. */
 #define VOGE_REUSE_PREP 1     /* the workspace holds the preparation and kept
                                  lists of a forward of the same items          */
 #define VOGE_FORWARD 2        /* batch: render the images                      */
@@ -77,6 +79,11 @@ extern "C" {
                                  found for these shapes (defaults if none)     */
 #define VOGE_SAMPLE 32        /* batch: sample the feature maps onto the kernels
                                  (Sec. 3.4, Eq. 10; see voge_sample)           */
+/* Gradient ablations of the backward (the paper's pose-estimation ablation
+ * table), for voge_render_backward and batches with VOGE_BACKWARD: */
+#define VOGE_BLOCK_T 64       /* no gradient through the transmittance T(l_k)  */
+#define VOGE_BLOCK_RHO 128    /* no gradient through the factor e^{q_k} of Eq. 8
+                                 (e^{q_m} inside T keeps its gradient)         */
 
 #define VOGE_MAX_BATCH 4096   /* items per voge_render_batch call              */
 
@@ -163,7 +170,9 @@ int voge_render_forward(voge_ctx_t* ctx, const float* means, const float* covs, 
  *   grad_camera [15] optional (NULL): dL/dR (9, row-major, entries treated as
  *   independent), dL/dT (3), dL/dF, dL/dO_x, dL/dO_y.
  *   flags: VOGE_REUSE_PREP when `workspace` still holds the preparation done
- *   by voge_render_forward for the same kernels, camera and params (skips it).
+ *   by voge_render_forward for the same kernels, camera and params (skips it);
+ *   VOGE_BLOCK_T / VOGE_BLOCK_RHO for the ablated gradients (attribute
+ *   gradients are unchanged by either).
  *   workspace: >= voge_workspace_size(..., 1). */
 int voge_render_backward(voge_ctx_t* ctx, const float* means, const float* covs, const float* attrs, int N, int C,
                          const voge_camera_t* cam, const voge_params_t* params, const float* grad_image,
@@ -189,6 +198,29 @@ int voge_render_backward(voge_ctx_t* ctx, const float* means, const float* covs,
 int voge_sample(voge_ctx_t* ctx, const float* means, const float* covs, int N, int C, const voge_camera_t* cam,
                 const voge_params_t* params, const float* features, float* sampled, float* sample_weight, int flags,
                 void* workspace, size_t workspace_bytes, void* stream);
+
+/* Exact-integral mode, a diagnostic of the closed form (App. A.2): for every
+ * pixel's kept set (the same selection as voge_render_forward) the outer
+ * integral of Eq. 1 by quadrature and the closed form of Eq. 7-8, in FP64.
+ * Along the ray kernel m has density e^{q_m} g_m(t), g_m(t) =
+ * sqrt(a_m/pi) exp(-a_m (t - l_m)^2), whose running integral is the erf sum
+ * of Eq. 7; then
+ *   W_m = int exp(-E(t)) e^{q_m} g_m(t) dt
+ * by the trapezoid rule on n_samples points over
+ * [min_m l_m - 9/sqrt(a_m), max_m l_m + 9/sqrt(a_m)].
+ *   n_samples  3 .. 2^24 quadrature points per pixel
+ *   w_exact    [H*W*K] double out: the quadrature W, kept-list order, 0 padded
+ *   w_approx   [H*W*K] double out: the closed form T(l_k) e^{q_k}
+ *   total      [H*W*2] double out: sum_k w_exact, and 1 - exp(-sum_m e^{q_m})
+ *              (the total mass the closed form reaches in the limit)
+ *   kept       [H*W*K] int32 out, optional: the kept kernels, -1 padded
+ *   flags      VOGE_REUSE_PREP to take the kept sets of a forward on
+ *              `workspace`, else 0
+ *   workspace  >= voge_workspace_size(..., 0)
+ * Errors: VOGE_EINVAL, VOGE_ENOSPACE, VOGE_EHIP. */
+int voge_quadrature(voge_ctx_t* ctx, const float* means, const float* covs, int N, const voge_camera_t* cam,
+                    const voge_params_t* params, int n_samples, double* w_exact, double* w_approx, double* total,
+                    int32_t* kept, int flags, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Bytes of workspace for a batch of n_items (1 <= n_items <= VOGE_MAX_BATCH);
  * with_backward = 1 sizes it for VOGE_BACKWARD and VOGE_SAMPLE too.  Only

@@ -26,6 +26,8 @@ VOGE_BACKWARD = 4
 VOGE_GRAPH = 8
 VOGE_TUNED = 16
 VOGE_SAMPLE = 32
+VOGE_BLOCK_T = 64
+VOGE_BLOCK_RHO = 128
 VOGE_MAX_BATCH = 4096
 
 EXPORTS = [
@@ -33,6 +35,7 @@ EXPORTS = [
     "voge_render_backward", "voge_status", "voge_last_error", "voge_version", "voge_debug_phi",
     "voge_profile_enable", "voge_profile_read", "voge_batch_workspace_size", "voge_render_batch",
     "voge_batch_status", "voge_tune_batch", "voge_tune_save", "voge_tune_load", "voge_sample",
+    "voge_quadrature",
 ]
 
 
@@ -91,6 +94,7 @@ def load(path: str = LIB_PATH):
         lib.voge_render_forward.argtypes = [P, P, P, P, I, I, CamP, ParP, P, P, P, P, SZ, P]
         lib.voge_render_backward.argtypes = [P, P, P, P, I, I, CamP, ParP, P, P, P, P, P, I, P, SZ, P]
         lib.voge_sample.argtypes = [P, P, P, I, I, CamP, ParP, P, P, P, I, P, SZ, P]
+        lib.voge_quadrature.argtypes = [P, P, P, I, CamP, ParP, I, P, P, P, P, I, P, SZ, P]
         lib.voge_status.argtypes = [P, ctypes.POINTER(ctypes.c_int32), P]
         lib.voge_last_error.argtypes = []
         lib.voge_last_error.restype = ctypes.c_char_p
@@ -163,6 +167,13 @@ def voge_sample(ctx, means, covs, N, C, cam, params, features, sampled, sample_w
     return _check(load().voge_sample(ctx, means, covs, int(N), int(C), ctypes.byref(cam), ctypes.byref(params),
                                      features, sampled, sample_weight, int(flags), workspace,
                                      int(workspace_bytes), stream))
+
+
+def voge_quadrature(ctx, means, covs, N, cam, params, n_samples, w_exact, w_approx, total, kept, flags, workspace,
+                    workspace_bytes, stream) -> int:
+    return _check(load().voge_quadrature(ctx, means, covs, int(N), ctypes.byref(cam), ctypes.byref(params),
+                                         int(n_samples), w_exact, w_approx, total, kept, int(flags), workspace,
+                                         int(workspace_bytes), stream))
 
 
 def voge_status(workspace, stream) -> int:

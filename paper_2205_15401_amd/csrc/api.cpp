@@ -292,10 +292,13 @@ int check_work_flags(int flags) {
         return fail(VOGE_EINVAL, "VOGE_BACKWARD and VOGE_SAMPLE do not combine in one call");
     if ((flags & VOGE_REUSE_PREP) && (flags & VOGE_FORWARD))
         return fail(VOGE_EINVAL, "VOGE_REUSE_PREP goes with VOGE_BACKWARD or VOGE_SAMPLE alone");
+    if ((flags & (VOGE_BLOCK_T | VOGE_BLOCK_RHO)) && !(flags & VOGE_BACKWARD))
+        return fail(VOGE_EINVAL, "VOGE_BLOCK_T and VOGE_BLOCK_RHO go with VOGE_BACKWARD");
     return VOGE_OK;
 }
 
-constexpr int WORK_FLAGS = VOGE_FORWARD | VOGE_BACKWARD | VOGE_SAMPLE | VOGE_REUSE_PREP;
+constexpr int WORK_FLAGS =
+    VOGE_FORWARD | VOGE_BACKWARD | VOGE_SAMPLE | VOGE_REUSE_PREP | VOGE_BLOCK_T | VOGE_BLOCK_RHO;
 
 voge::ItemShape shape_of(const voge_item_t& it) {
     return {it.N, it.C, it.camera.height, it.camera.width, it.params.K};
@@ -373,6 +376,7 @@ voge::ItemDev item_record(const voge::BatchPlan& p, int j, const voge_item_t& sr
     t.K = ip.s.K;
     t.C = ip.s.C;
     t.n_tiles = ip.n_tiles;
+    t.grad_mode = ((flags & VOGE_BLOCK_T) ? 1 : 0) | ((flags & VOGE_BLOCK_RHO) ? 2 : 0);
     t.S = ip.S;
     t.F = src.camera.focal;
     t.cx = src.camera.cx;
@@ -463,7 +467,7 @@ int upload_items(voge_ctx_t* ctx, const std::vector<voge::ItemDev>& recs, const 
 
 // All launches of a call after the table upload.
 int launch_compute(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, int flags,
-                   const voge::ExecConfig& cfg, bool profile, hipStream_t s) {
+                   const voge::ExecConfig& cfg, bool profile, hipStream_t s, const voge::QuadOut* quad = nullptr) {
     const voge::BatchDev b = batch_dev(p, w);
     auto scope = [&](const char* name) { return ProfScope(profile ? ctx : nullptr, name, s); };
     const bool fwd_part = (flags & VOGE_FORWARD) || !(flags & VOGE_REUSE_PREP);
@@ -479,6 +483,12 @@ int launch_compute(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, 
             for (const auto& g : p.groups)
                 if (int rc = hip_check(voge::launch_select(group_dev(g, w, cfg), g.kb, s), "select launch")) return rc;
         }
+    }
+    if (quad) {
+        // exact-integral mode (one item): the quadrature replaces the blend
+        ProfScope ps = scope("quadrature");
+        const voge::GroupPlan& g = p.groups[0];
+        return hip_check(voge::launch_quadrature(group_dev(g, w, cfg), g.kb, *quad, s), "quadrature launch");
     }
     if (flags & VOGE_SAMPLE) {
         {
@@ -579,7 +589,7 @@ std::string shape_key(const voge_ctx_t* ctx, const voge_item_t* items, int n, in
 // The whole call: checks, plan, table, launches.  `force` overrides the
 // execution choices (the autotuner's trials).
 int run_batch(voge_ctx_t* ctx, const voge_item_t* items, int n, int flags, void* workspace, size_t workspace_bytes,
-              hipStream_t s, const voge::ExecConfig* force = nullptr) {
+              hipStream_t s, const voge::ExecConfig* force = nullptr, const voge::QuadOut* quad = nullptr) {
     const bool scratch = (flags & (VOGE_BACKWARD | VOGE_SAMPLE)) != 0;   // the gradient scratch is in use
     std::vector<voge::ItemShape> shapes(n);
     for (int i = 0; i < n; ++i) shapes[i] = shape_of(items[i]);
@@ -603,14 +613,14 @@ int run_batch(voge_ctx_t* ctx, const voge_item_t* items, int n, int flags, void*
         }
         if (flags & VOGE_GRAPH) cfg.graph = 1;
     }
-    if (s == nullptr) cfg.graph = 0;       // graphs are captured on a non-null stream only
+    if (s == nullptr || quad) cfg.graph = 0;       // graphs: non-null streams, render calls only
     const bool fwd_part = (flags & VOGE_FORWARD) || !(flags & VOGE_REUSE_PREP);
     {
         ProfScope ps(ctx, "upload", s);
         if (int rc = upload_items(ctx, recs, w, fwd_part, s)) return rc;
     }
     if (cfg.graph) return run_graph(ctx, p, w, flags, cfg, s);
-    return launch_compute(ctx, p, w, flags, cfg, true, s);
+    return launch_compute(ctx, p, w, flags, cfg, true, s, quad);
 }
 
 }  // namespace
@@ -711,7 +721,7 @@ int check_workspace(void* workspace) {
 
 extern "C" {
 
-int voge_version(void) { return 10200; }
+int voge_version(void) { return 10300; }
 
 const char* voge_last_error(void) { return g_err.c_str(); }
 
@@ -815,7 +825,7 @@ int voge_render_backward(voge_ctx_t* ctx, const float* means, const float* covs,
     if (!grad_image) return fail(VOGE_EINVAL, "grad_image is required");
     if (N > 0 && (!grad_means || !grad_covs || !grad_attrs))
         return fail(VOGE_EINVAL, "grad_means, grad_covs and grad_attrs are required");
-    if (flags & ~VOGE_REUSE_PREP) return fail(VOGE_EINVAL, "unknown flags");
+    if (flags & ~(VOGE_REUSE_PREP | VOGE_BLOCK_T | VOGE_BLOCK_RHO)) return fail(VOGE_EINVAL, "unknown flags");
     if (int rc = check_workspace(workspace)) return rc;
     voge_item_t it = single_item(means, covs, attrs, N, C, cam, params);
     it.grad_image = grad_image;
@@ -823,7 +833,7 @@ int voge_render_backward(voge_ctx_t* ctx, const float* means, const float* covs,
     it.grad_covs = grad_covs;
     it.grad_attrs = grad_attrs;
     it.grad_camera = grad_camera;
-    if (int rc = run_batch(ctx, &it, 1, VOGE_BACKWARD | (flags & VOGE_REUSE_PREP), workspace, workspace_bytes,
+    if (int rc = run_batch(ctx, &it, 1, VOGE_BACKWARD | flags, workspace, workspace_bytes,
                            static_cast<hipStream_t>(stream)))
         return rc;
     g_err.clear();
@@ -844,6 +854,26 @@ int voge_sample(voge_ctx_t* ctx, const float* means, const float* covs, int N, i
     it.sample_weight = sample_weight;
     if (int rc = run_batch(ctx, &it, 1, VOGE_SAMPLE | (flags & VOGE_REUSE_PREP), workspace, workspace_bytes,
                            static_cast<hipStream_t>(stream)))
+        return rc;
+    g_err.clear();
+    return VOGE_OK;
+}
+
+int voge_quadrature(voge_ctx_t* ctx, const float* means, const float* covs, int N, const voge_camera_t* cam,
+                    const voge_params_t* params, int n_samples, double* w_exact, double* w_approx, double* total,
+                    int32_t* kept, int flags, void* workspace, size_t workspace_bytes, void* stream) {
+    if (int rc = check_common(ctx, means, covs, nullptr, N, 1, cam, params, false)) return rc;
+    if (!w_exact || !w_approx || !total) return fail(VOGE_EINVAL, "w_exact, w_approx and total are required");
+    if (n_samples < 3 || n_samples > (1 << 24)) return fail(VOGE_EINVAL, "n_samples must be in [3, 2^24]");
+    if (flags & ~VOGE_REUSE_PREP) return fail(VOGE_EINVAL, "unknown flags");
+    if (int rc = check_workspace(workspace)) return rc;
+    voge_item_t it = single_item(means, covs, nullptr, N, 1, cam, params);
+    const voge::QuadOut q{w_exact, w_approx, total, kept, n_samples};
+    // the preparation and selection of a forward (unless reused), then the
+    // quadrature in place of the blend; the item has no image
+    const int work = (flags & VOGE_REUSE_PREP) ? VOGE_REUSE_PREP : VOGE_FORWARD;
+    if (int rc = run_batch(ctx, &it, 1, work, workspace, workspace_bytes, static_cast<hipStream_t>(stream), nullptr,
+                           &q))
         return rc;
     g_err.clear();
     return VOGE_OK;

@@ -648,13 +648,15 @@ __device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile) {
             }
         }
     }
+    // the ablations stop the path through T (dE) or the direct factor e^q (dmd)
+    const bool keep_T = !(A.grad_mode & 1), keep_rho = !(A.grad_mode & 2);
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
         if (k < keff) {
             const float T = pT[(size_t)k * S];
             const float W = T * pm[(size_t)k * S];
-            dE[k] = -g[k] * W;
-            dmd[k] = g[k] * T;
+            dE[k] = keep_T ? -g[k] * W : 0.f;
+            dmd[k] = keep_rho ? g[k] * T : 0.f;
         }
     }
     // pair loop: m streams from the list (slot m+1 is loaded while slot m is
@@ -938,6 +940,102 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
     }
 }
 
+// ------------------------------------------------------- exact-integral mode
+//
+// The outer integral of Eq. 1 by quadrature for each pixel's kept set, next
+// to the closed form of Eq. 8, both in FP64 (a diagnostic of the
+// approximation, App. A.2).  Along the ray kernel m has density
+// e^{q_m} g_m(t), g_m(t) = sqrt(a_m/pi) exp(-a_m (t - l_m)^2), whose running
+// integral is the erf sum of Eq. 7; the transmittance is exp(-E(t)) and
+//   W_m = int T(t) e^{q_m} g_m(t) dt
+// is taken by the trapezoid rule on n_samples points over
+// [min_m l_m - 9/sqrt(a_m), max_m l_m + 9/sqrt(a_m)] (D' units; the rule is
+// invariant under the scaling of t).  One wave per pixel: each kept kernel
+// is re-traced in FP64 from its record, lane j takes samples j, j + 64, ...,
+// and the per-kernel sums are reduced across the wave.
+constexpr int QUAD_BLOCKS_PER_TILE = TILE_THREADS / (TILE_THREADS / WAVE);   // a block: one pixel per wave
+
+template <int KB>
+__global__ __launch_bounds__(TILE_THREADS) void k_quadrature(GroupDev g, QuadOut out) {
+    __shared__ double s_l[TILE_THREADS / WAVE][KB], s_a[TILE_THREADS / WAVE][KB], s_m[TILE_THREADS / WAVE][KB];
+    const TraceArgs A = g.items[g.single].t;
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int tile = blockIdx.x / QUAD_BLOCKS_PER_TILE;
+    const int slot = (blockIdx.x % QUAD_BLOCKS_PER_TILE) * (TILE_THREADS / WAVE) + w;
+    const int ntx = (A.W + TILE - 1) / TILE;
+    const PixelCtx P = pixel_at(tile, slot, ntx, A.H, A.W, A.cx, A.cy);
+    if (!P.valid) return;                       // whole wave: one pixel per wave
+    const size_t S = A.S;
+    const int keff = A.keff[P.q];
+    const size_t p = (size_t)P.pi * A.W + P.pj;
+    if (lane < keff) {
+        const int rank = A.kl_r[(size_t)lane * S + P.q];
+        double l, q2, a;
+        trace_one(A.rec[rank], P.u, P.v, l, q2, a);
+        s_l[w][lane] = l;
+        s_a[w][lane] = a;
+        s_m[w][lane] = exp(-0.5 * q2);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double t0 = 0.0, t1 = 0.0, msum = 0.0;
+    for (int m = 0; m < keff; ++m) {
+        const double r = 9.0 / sqrt(s_a[w][m]);
+        t0 = m == 0 ? s_l[w][m] - r : fmin(t0, s_l[w][m] - r);
+        t1 = m == 0 ? s_l[w][m] + r : fmax(t1, s_l[w][m] + r);
+        msum += s_m[w][m];
+    }
+    double acc[KB];
+#pragma unroll
+    for (int m = 0; m < KB; ++m) acc[m] = 0.0;
+    if (keff > 0) {
+        const int n = out.n_samples;
+        const double h = (t1 - t0) / (double)(n - 1);
+        for (int s = lane; s < n; s += WAVE) {
+            const double t = t0 + h * (double)s;
+            const double wgt = (s == 0 || s == n - 1) ? 0.5 * h : h;
+            double E = 0.0;
+            for (int m = 0; m < keff; ++m) E += s_m[w][m] * 0.5 * (1.0 + erf((t - s_l[w][m]) * sqrt(s_a[w][m])));
+            const double T = exp(-E);
+#pragma unroll
+            for (int m = 0; m < KB; ++m) {
+                if (m < keff) {
+                    const double d = t - s_l[w][m];
+                    acc[m] += wgt * T * s_m[w][m] * sqrt(s_a[w][m] / M_PI) * exp(-s_a[w][m] * d * d);
+                }
+            }
+        }
+    }
+    double sum_exact = 0.0;
+#pragma unroll
+    for (int m = 0; m < KB; ++m) {
+        if (m < keff) {
+            const double v = wave_sum(acc[m]);
+            sum_exact += v;
+            if (lane == 0) out.w_exact[p * A.K + m] = v;
+        }
+    }
+    // the closed form of Eq. 7-8 in FP64, lane m for kernel m
+    for (int m = lane; m < A.K; m += WAVE) {
+        double wa = 0.0;
+        if (m < keff) {
+            double E = 0.0;
+            for (int j = 0; j < keff; ++j)
+                E += s_m[w][j] * 0.5 * (1.0 + erf((s_l[w][m] - s_l[w][j]) * sqrt(s_a[w][j])));
+            wa = exp(-E) * s_m[w][m];
+        } else {
+            out.w_exact[p * A.K + m] = 0.0;
+        }
+        out.w_approx[p * A.K + m] = wa;
+        if (out.kept) out.kept[p * A.K + m] = m < keff ? A.kl_i[(size_t)m * S + P.q] : -1;
+    }
+    if (lane == 0) {
+        out.total[2 * p] = sum_exact;
+        out.total[2 * p + 1] = 1.0 - exp(-msum);
+    }
+}
+
 // ------------------------------------------------------------------ kernels
 // A workgroup takes a tile of the group, finds the tile's item and renders
 // the item-local tile with a copy of the item's view.  The copy is read
@@ -1048,6 +1146,19 @@ hipError_t launch_bwd(const GroupDev& g, int kb, hipStream_t s) { return dispatc
 hipError_t launch_bwd_reduce(const GroupDev& g, int kb, hipStream_t s) { return dispatch(3, g, kb, s); }
 hipError_t launch_blend_sample(const GroupDev& g, int kb, int max_c, hipStream_t s) {
     return dispatch(4, g, kb, s, max_c);
+}
+
+hipError_t launch_quadrature(const GroupDev& g, int kb, const QuadOut& out, hipStream_t s) {
+    const int nb = g.n_tiles * QUAD_BLOCKS_PER_TILE;
+    if (nb <= 0) return hipSuccess;
+    switch (kb) {
+        case 8: hipLaunchKernelGGL(k_quadrature<8>, dim3(nb), dim3(TILE_THREADS), 0, s, g, out); break;
+        case 16: hipLaunchKernelGGL(k_quadrature<16>, dim3(nb), dim3(TILE_THREADS), 0, s, g, out); break;
+        case 20: hipLaunchKernelGGL(k_quadrature<20>, dim3(nb), dim3(TILE_THREADS), 0, s, g, out); break;
+        case 32: hipLaunchKernelGGL(k_quadrature<32>, dim3(nb), dim3(TILE_THREADS), 0, s, g, out); break;
+        default: hipLaunchKernelGGL(k_quadrature<64>, dim3(nb), dim3(TILE_THREADS), 0, s, g, out); break;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_phi(const float* x, float* y, int n, hipStream_t s) {

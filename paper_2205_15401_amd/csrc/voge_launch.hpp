@@ -32,6 +32,7 @@ struct TraceArgs {
     const GeoRec* geo;
     int N, H, W, K, C;
     int n_tiles;
+    int grad_mode;             // backward ablation bits: 1 no gradient through T, 2 none through e^q of Eq. 8
     size_t S;                  // list stride: n_tiles * 256
     float F, cx, cy;
     double rad2;               // 2 ln(1/eta) = -2 ln(eta)
@@ -97,6 +98,16 @@ struct GroupDev {
     int single;                // the group's item when it has only one, else -1
     int tile0, n_tiles;        // the group's global tiles
     int order;                 // block -> tile order: 0 banded per XCD, 1 plain
+};
+
+// Outputs of the exact-integral mode (one item): per pixel and kept slot,
+// [H*W*K] doubles, and per pixel [H*W*2] totals.
+struct QuadOut {
+    double* w_exact;
+    double* w_approx;
+    double* total;
+    int32_t* kept;             // optional
+    int n_samples;
 };
 
 // Execution choices of a call, picked by the autotuner per shape.
@@ -172,6 +183,7 @@ hipError_t launch_bwd_reduce(const GroupDev& g, int kb, hipStream_t s);   // til
 // blend plus the sampler; max_c: the largest channel count of the group's items
 hipError_t launch_blend_sample(const GroupDev& g, int kb, int max_c, hipStream_t s);
 hipError_t launch_phi(const float* x, float* y, int n, hipStream_t s);
+hipError_t launch_quadrature(const GroupDev& g, int kb, const QuadOut& out, hipStream_t s);   // one item
 hipError_t launch_epilogue(const BatchDev& b, int total_epi, hipStream_t s);
 hipError_t launch_sample_epilogue(const BatchDev& b, int total_epi, hipStream_t s);
 

@@ -111,8 +111,11 @@ def render_forward(means: torch.Tensor, covs: torch.Tensor, attrs: torch.Tensor,
 
 def render_backward(means: torch.Tensor, covs: torch.Tensor, attrs: torch.Tensor, cam: nat.VogeCamera,
                     grad_image: torch.Tensor, K: int = 20, eta: float = 0.01,
-                    workspace: Optional[torch.Tensor] = None, reuse: bool = False, with_camera: bool = True):
-    """Gradients (means [N,3], covs [N,6], attrs [N,C], camera [15] or None)."""
+                    workspace: Optional[torch.Tensor] = None, reuse: bool = False, with_camera: bool = True,
+                    block_t: bool = False, block_rho: bool = False):
+    """Gradients (means [N,3], covs [N,6], attrs [N,C], camera [15] or None).
+    block_t / block_rho: the ablated gradients without the path through T or
+    through the factor e^q of Eq. 8."""
     _check_inputs(means, covs, attrs)
     dev = means.device
     N, C = means.shape[0], attrs.shape[1]
@@ -130,7 +133,9 @@ def render_backward(means: torch.Tensor, covs: torch.Tensor, attrs: torch.Tensor
     ga = torch.empty((N, C), dtype=torch.float32, device=dev)
     gk = torch.empty(15, dtype=torch.float32, device=dev) if with_camera else None
     nat.voge_render_backward(context(dev), _ptr(means), _ptr(covs), _ptr(attrs), N, C, cam, par, _ptr(g),
-                             _ptr(gm), _ptr(gc), _ptr(ga), _ptr(gk), nat.VOGE_REUSE_PREP if reuse else 0,
+                             _ptr(gm), _ptr(gc), _ptr(ga), _ptr(gk),
+                             (nat.VOGE_REUSE_PREP if reuse else 0) | (nat.VOGE_BLOCK_T if block_t else 0)
+                             | (nat.VOGE_BLOCK_RHO if block_rho else 0),
                              _ptr(workspace), workspace.numel(), _stream(dev))
     return gm, gc, ga, gk
 
@@ -165,6 +170,33 @@ def sample(means: torch.Tensor, covs: torch.Tensor, features: torch.Tensor, cam:
     nat.voge_sample(context(dev), _ptr(means), _ptr(covs), N, C, cam, par, _ptr(f), _ptr(alpha), _ptr(wk),
                     nat.VOGE_REUSE_PREP if reuse else 0, _ptr(workspace), workspace.numel(), _stream(dev))
     return alpha, wk, workspace
+
+
+def quadrature(means: torch.Tensor, covs: torch.Tensor, cam: nat.VogeCamera, K: int = 20, eta: float = 0.01,
+               n_samples: int = 4001, workspace: Optional[torch.Tensor] = None, reuse: bool = False):
+    """Exact-integral mode: per pixel and kept slot the quadrature weight and
+    the closed form (float64 [H,W,K] each), totals [H,W,2] and the kept
+    kernels [H,W,K] int32 (voge_quadrature)."""
+    for name, t, cols in (("means", means, 3), ("covs", covs, 6)):
+        if not t.is_cuda or t.dtype != torch.float32 or t.dim() != 2 or t.shape[1] != cols or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float32 device tensor of shape (N, {cols})")
+    dev = means.device
+    N = means.shape[0]
+    H, W = cam.height, cam.width
+    par = params_struct(K, eta)
+    need = workspace_bytes(N, 1, cam, par, False)
+    if workspace is None or workspace.numel() < need:
+        if reuse:
+            raise ValueError("reuse needs the forward's workspace")
+        workspace = new_workspace(need, dev)
+    f64 = dict(dtype=torch.float64, device=dev)
+    we, wa = torch.empty((H, W, K), **f64), torch.empty((H, W, K), **f64)
+    tot = torch.empty((H, W, 2), **f64)
+    kept = torch.empty((H, W, K), dtype=torch.int32, device=dev)
+    nat.voge_quadrature(context(dev), _ptr(means), _ptr(covs), N, cam, par, n_samples, _ptr(we), _ptr(wa),
+                        _ptr(tot), _ptr(kept), nat.VOGE_REUSE_PREP if reuse else 0, _ptr(workspace),
+                        workspace.numel(), _stream(dev))
+    return we, wa, tot, kept
 
 
 def status(workspace: torch.Tensor) -> int:
@@ -308,9 +340,12 @@ class Batch:
         return flags | (nat.VOGE_REUSE_PREP if reuse else 0)
 
     def run(self, forward: bool = True, backward: bool = False, reuse: bool = False, graph: bool = False,
-            tuned: bool = False, stream: Optional[int] = None, sample: bool = False) -> None:
-        """One call of voge_render_batch on ``stream`` (default: torch's current stream)."""
+            tuned: bool = False, stream: Optional[int] = None, sample: bool = False, block_t: bool = False,
+            block_rho: bool = False) -> None:
+        """One call of voge_render_batch on ``stream`` (default: torch's current stream);
+        block_t / block_rho: the backward's gradient ablations."""
         flags = self._flags(forward, backward, reuse, sample)
+        flags |= (nat.VOGE_BLOCK_T if block_t else 0) | (nat.VOGE_BLOCK_RHO if block_rho else 0)
         flags |= (nat.VOGE_GRAPH if graph else 0) | (nat.VOGE_TUNED if tuned else 0)
         s = _stream(self.device) if stream is None else stream
         nat.voge_render_batch(context(self.device), self.arr, flags, _ptr(self.workspace), self.ws_bytes, s)

@@ -44,7 +44,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_version(lib):
-    assert nat.voge_version() == 10200
+    assert nat.voge_version() == 10300
 
 
 def cam(h=64, w=64, f=64.0):
@@ -118,6 +118,31 @@ def test_sampler_rejects_bad_arguments_on_the_host(lib):
     assert "C" in rejected(C=0)
     assert "workspace" in rejected(workspace=None)
     assert "aligned" in rejected(workspace=300)
+
+
+def test_quadrature_and_ablation_flags_are_checked_on_the_host(lib):
+    fake_ctx = ctypes.c_void_p(1).value
+
+    def quad(**kw):
+        a = dict(ctx=fake_ctx, means=256, covs=256, N=10, cam=cam(), params=par(), n_samples=101, w_exact=256,
+                 w_approx=256, total=256, kept=None, flags=0, workspace=256, workspace_bytes=1 << 30, stream=None)
+        a.update(kw)
+        with pytest.raises(nat.VogeError) as e:
+            nat.voge_quadrature(*a.values())
+        assert e.value.code == nat.VOGE_EINVAL
+        return nat.voge_last_error()
+
+    assert "n_samples" in quad(n_samples=2)
+    assert "w_exact" in quad(total=None)
+    assert "flags" in quad(flags=nat.VOGE_BLOCK_T)
+    assert "ctx" in quad(ctx=None)
+    # the ablations go with a backward only
+    with pytest.raises(nat.VogeError) as e:
+        nat.voge_render_batch(fake_ctx, [item()], nat.VOGE_FORWARD | nat.VOGE_BLOCK_T, 256, 1 << 30, None)
+    assert "VOGE_BACKWARD" in nat.voge_last_error()
+    with pytest.raises(nat.VogeError):
+        nat.voge_render_backward(fake_ctx, 256, 256, 256, 10, 3, cam(), par(), 256, 256, 256, 256, None, 1 << 10,
+                                 256, 1 << 30, None)
 
 
 def test_bad_eta_is_rejected_before_any_device_work(lib):
