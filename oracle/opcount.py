@@ -55,6 +55,8 @@ def count(jobs, name: str) -> dict:
         "flop_kept": O.flop_kept(C),
         "flop_bpair": O.FLOP_BPAIR,
         "flop_bkept": O.flop_bkept(C),
+        "flop_quad_pair": O.FLOP_QUAD_PAIR,
+        "flop_quad_sample": O.FLOP_QUAD_SAMPLE,
     }
     out["flop_select"] = O.FLOP_TRACE * out["sum_n_pass"]
     out["flop_blend"] = O.FLOP_PAIR * out["sum_k_eff_sq"] + O.flop_kept(C) * out["sum_k_eff"]

@@ -30,6 +30,11 @@ the arithmetic of the formulas as evaluated here, per unit of work:
       symmetric dL/dS (40), dL/dD (20), accumulate M and S gradients (9 minus 3
       counted above).  Of these, 2C + 4 (G.c_k, dm, dE, dq) belong with the
       per-pixel pair work and 106 + 2C with the per-kernel chain.
+  Exact-integral mode (the quadrature of Eq. 1 for a kept set), per sample
+  point t and kept kernel m: FLOP_QUAD_PAIR = 16 -- optical depth term
+  (t - l, x sqrt(a), erf, +1, x1/2, x e^q, accumulate: 7) and weight term
+  (t - l, square, x a, exp, x sqrt(a/pi), x e^q, x T, x trapezoid weight,
+  accumulate: 9); FLOP_QUAD_SAMPLE = 3 per sample point (t, exp(-E), +).
   Sampler (Sec. 3.4, Eq. 10; the kept sets and T given by the forward):
   FLOP_SAMPLE = 2 + 2C per kept kernel: W = T e^q (1), accumulate W phi (2C)
       and W (1); the C divisions per kernel are per-kernel work, not counted.
@@ -57,6 +62,8 @@ FLAG_ETA = 2
 FLOP_TRACE = 53
 FLOP_PAIR = 7
 FLOP_BPAIR = 20
+FLOP_QUAD_PAIR = 16
+FLOP_QUAD_SAMPLE = 3
 
 
 def flop_kept(C: int) -> int:
