@@ -159,22 +159,16 @@ __device__ __forceinline__ double key_upper_l(uint64_t key) {
     return __longlong_as_double((long long)(key | RANK_MASK));
 }
 
-template <int KB>
-__device__ __forceinline__ uint64_t kth_key(const uint64_t (&key)[KB], int K) {
-    uint64_t kk = key[KB - 1];
-#pragma unroll
-    for (int s = 0; s < KB; ++s)
-        if (s == K - 1) kk = key[s];
-    return kk;
-}
-
 // Insertion of a key into the sorted K-buffer (a compare-exchange network)
 // over slots 0..ub only, ub being a wave-uniform bound of the filled slots:
 // slots past a lane's fill count hold the empty key, so the new key settles
 // at or before the first of them.  Groups of four slots under uniform
-// branches.
-template <int KB>
-__device__ __forceinline__ void kbuf_insert_upto(uint64_t (&key)[KB], uint64_t nk, int ub) {
+// branches.  CAPTURE: returns the new key of slot km1 (wave-uniform) if the
+// network reached it, else the empty key; a lane that holds more than km1
+// keys after the insertion always has it reached (km1 <= its old count <= ub).
+template <int KB, bool CAPTURE>
+__device__ __forceinline__ uint64_t kbuf_insert_upto(uint64_t (&key)[KB], uint64_t nk, int ub, int km1) {
+    uint64_t kk = ~0ull;
 #pragma unroll
     for (int s0 = 0; s0 < KB; s0 += 4) {
         if (s0 <= ub) {
@@ -184,9 +178,11 @@ __device__ __forceinline__ void kbuf_insert_upto(uint64_t (&key)[KB], uint64_t n
                 const bool lt = nk < cur;
                 key[s] = lt ? nk : cur;
                 nk = lt ? cur : nk;
+                if (CAPTURE && s == km1) kk = key[s];
             }
         }
     }
+    return kk;
 }
 
 // Block -> tile.  Workgroups are dealt round-robin to the 8 XCDs (block b
@@ -211,26 +207,28 @@ __device__ __forceinline__ int wave_max_keff(int keff) {
 // ------------------------------------------------------------------ select
 // Each wave owns one 8x8 block of the tile and works alone (no workgroup
 // barriers: waves with fewer candidates do not wait for the others).  It
-// scans the depth-ordered cull records 64 at a time, compacts those whose
-// screen box meets its block into a wave-private list, and traces them in
-// order; the records of listed candidates come through the scalar cache.
-template <int KB>
+// scans the depth-ordered cull records 64 at a time; the records whose
+// screen box meets its block are the set bits of a ballot, taken in record
+// order with scalar bit scans, and traced one after the other.  Their trace
+// records come through the scalar cache, the next candidate's while the
+// current one is inserted; nothing in the candidate loop touches LDS, so
+// waiting for the current record never waits for anything else.
+template <int KB, bool KFULL>
 __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
-    __shared__ int s_list[TILE_THREADS / WAVE][WAVE];
     const int tid = threadIdx.x, lane = tid % WAVE;
     const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);   // uniform in the wave
     const int ntx = (A.W + TILE - 1) / TILE;
     const PixelCtx P = pixel_of(tile, ntx, A.H, A.W, A.cx, A.cy);
     const int bi0 = (tile / ntx) * TILE + (wave >> 1) * 8;            // this wave's block
     const int bj0 = (tile % ntx) * TILE + (wave & 1) * 8;
-    const uint64_t lt = lanemask_lt();
-    int* list = s_list[wave];
+    const ConstRecPtr crec = const_rec(A.rec);
 
     uint64_t key[KB];
 #pragma unroll
     for (int s = 0; s < KB; ++s) key[s] = ~0ull;
     uint64_t kth = ~0ull;                        // the K-th smallest key so far
     int nkey = 0;                                // filled slots (saturates at KB)
+    int ub = 0;                                  // the wave's largest nkey (uniform)
     bool done = !P.valid;
     CullRec nxt;
     if (lane < A.N) nxt = A.cull[lane];
@@ -239,38 +237,44 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
         const CullRec c = nxt;
         if (r + WAVE < A.N) nxt = A.cull[r + WAVE];                  // prefetch the next step
         const bool hit = r < A.N && c.i0 <= bi0 + 7 && c.i1 >= bi0 && c.j0 <= bj0 + 7 && c.j1 >= bj0;
-        const uint64_t m = __ballot(hit);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");   // earlier reads of the list are done
-        __builtin_amdgcn_wave_barrier();
-        if (hit) list[__popcll(m & lt)] = r;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int n = __popcll(m);
-        for (int ci = 0; ci < n; ++ci) {
-            if (__all(done)) break;
-            const int rank = __builtin_amdgcn_readfirstlane(list[ci]);
-            const TraceRec R = load_rec(const_rec(A.rec) + rank);
-            if (!done && kth != ~0ull && (double)R.tlo > key_upper_l(kth)) done = true;
-            bool ins = false;
-            uint64_t nk = 0;
-            if (!done) {
-                double l, q2, a;
-                trace_one(R, P.u, P.v, l, q2, a);
-                if (q2 < A.rad2 && l > 0.0) {
-                    nk = ((uint64_t)__double_as_longlong(l) & ~RANK_MASK) | (uint64_t)rank;
-                    ins = nk < kth;
+        uint64_t mm = __ballot(hit);             // this step's candidates, one bit per record
+        if (mm != 0) {
+            int rank = base + (int)__builtin_ctzll(mm);
+            mm &= mm - 1;
+            TraceRec R = load_rec(crec + rank);
+            for (;;) {
+                if (__all(done)) break;
+                if (!done && kth != ~0ull && (double)R.tlo > key_upper_l(kth)) done = true;
+                bool ins = false;
+                uint64_t nk = 0;
+                if (!done) {
+                    double l, q2, a;
+                    trace_one(R, P.u, P.v, l, q2, a);
+                    if (q2 < A.rad2 && l > 0.0) {
+                        nk = ((uint64_t)__double_as_longlong(l) & ~RANK_MASK) | (uint64_t)rank;
+                        ins = nk < kth;
+                    }
                 }
-            }
-            if (__any(ins)) {
-                int ub = nkey;
-                for (int off = WAVE / 2; off > 0; off >>= 1) ub = max(ub, __shfl_xor(ub, off));
-                ub = __builtin_amdgcn_readfirstlane(ub);
-                if (ins) {
-                    kbuf_insert_upto<KB>(key, nk, ub);
-                    nkey = min(nkey + 1, KB);
-                    kth = nkey >= A.K ? kth_key<KB>(key, A.K) : ~0ull;
+                // the next candidate's record is in flight while this one is inserted
+                const bool more = mm != 0;
+                const int rank_n = more ? base + (int)__builtin_ctzll(mm) : rank;
+                mm &= mm - 1;
+                __builtin_amdgcn_sched_barrier(0);
+                const TraceRec Rn = load_rec(crec + rank_n);
+                if (__any(ins)) {
+                    // the wave's largest fill count grows by one when a lane at it inserts
+                    const bool grow = ub < KB && __any(ins && nkey == ub);
+                    if (ins) {
+                        // KFULL (K = KB): the K-th key sits in the last slot
+                        const uint64_t kk = kbuf_insert_upto<KB, !KFULL>(key, nk, ub, A.K - 1);
+                        nkey = min(nkey + 1, KB);
+                        kth = nkey >= A.K ? (KFULL ? key[KB - 1] : kk) : ~0ull;
+                    }
+                    ub += grow ? 1 : 0;
                 }
+                if (!more) break;
+                R = Rn;
+                rank = rank_n;
             }
         }
         // the block is done when every pixel is, or holds K kernels nearer
@@ -1058,7 +1062,10 @@ template <int KB>
 __global__ __launch_bounds__(TILE_THREADS, select_waves<KB>()) void k_select(GroupDev g) {
     int tile;
     const TraceArgs A = item_view(g, tile);
-    select_body<KB>(A, tile);
+    if (A.K == KB)
+        select_body<KB, true>(A, tile);
+    else
+        select_body<KB, false>(A, tile);
 }
 
 template <int KB>
