@@ -250,7 +250,6 @@ BatchPlan plan_batch(const ItemShape* shapes, int n) {
     p.off_camP = take(sizeof(double) * 12 * (size_t)(p.total_epi > 0 ? p.total_epi : 1));
     p.off_bw = take(16 * nl);
     p.off_bwl = take(4 * nl);
-    p.off_pairs = take(32 * nl);    // PairRec
     p.bwd_bytes = off;
     return p;
 }
@@ -324,7 +323,6 @@ struct BatchWs {
     double* camP;
     float4* bw;
     float* bwl;
-    voge::PairRec* pairs;
 };
 
 BatchWs carve_batch(void* ws, const voge::BatchPlan& p) {
@@ -357,7 +355,6 @@ BatchWs carve_batch(void* ws, const voge::BatchPlan& p) {
     w.camP = reinterpret_cast<double*>(b + p.off_camP);
     w.bw = reinterpret_cast<float4*>(b + p.off_bw);
     w.bwl = reinterpret_cast<float*>(b + p.off_bwl);
-    w.pairs = reinterpret_cast<voge::PairRec*>(b + p.off_pairs);
     return w;
 }
 
@@ -402,7 +399,6 @@ voge::ItemDev item_record(const voge::BatchPlan& p, int j, const voge_item_t& sr
         t.grad_image = src.features;
         t.gW = gM + 3 * k0;
         t.gA = gA + ip.attr_off;
-        t.pairs = w.pairs + lo;
         d.sampled = src.sampled;
         d.sample_weight = src.sample_weight;
     }
@@ -418,7 +414,6 @@ voge::ItemDev item_record(const voge::BatchPlan& p, int j, const voge_item_t& sr
         t.tileD = w.tileD + 3 * (size_t)ip.tile_start;
         t.bw = w.bw + lo;
         t.bwl = w.bwl + lo;
-        t.pairs = w.pairs + lo;
         d.grad_means = src.grad_means;
         d.grad_covs = src.grad_covs;
         d.grad_attrs = src.grad_attrs;

@@ -516,9 +516,10 @@ __device__ __forceinline__ void blend_body(const TraceArgs& A, int tile, unsigne
 //
 // Reduction over pixels without float atomics in LDS: the pixel lanes leave
 // per-pair scalars (dq, dl, da, W) in the list scratch, a counting sort in
-// LDS groups the tile's (pixel, slot) pairs by kernel, and one lane per kernel
-// walks its pairs, runs the chain in FP64 and accumulates in registers; each
-// (tile, kernel) then makes one global atomic add per output value.
+// LDS orders the tile's (pixel, slot) pairs by kernel (16-bit indices in
+// LDS), and lanes walk runs of pairs, gather their scalars, run the chain in
+// FP64 and accumulate in registers; each (tile, kernel) then makes one global
+// atomic add per output value.
 
 __device__ __forceinline__ int hash_slot(int* s_hkey, int hmask, int rank) {
     int h = (int)(((uint32_t)rank * 2654435761u) >> 7) & hmask;
@@ -537,18 +538,21 @@ __device__ __forceinline__ double wave_sum(double x) {
 
 // The chain for one (pixel, kernel) pair: camera-space gradient of the
 // centre (out[0..2]) and of the symmetric inverse covariance (out[3..8],
-// xx xy xz yy yz zz), and dL/dD' added to gD.
-__device__ __forceinline__ void pair_chain(const GeoRec& G, double D0, double D1, double D2, double l, double dq,
+// xx xy xz yy yz zz), and dL/dD' added to gD.  The peak depth
+// l = D'^T S M / D'^T S D' is recomputed here in FP64 from the kernel's
+// camera-space record.
+__device__ __forceinline__ void pair_chain(const GeoRec& G, double D0, double D1, double D2, double dq,
                                            double dlt, double dat, double out[9], double gD[3]) {
     const double s0 = G.S[0], s1 = G.S[1], s2 = G.S[2], s3 = G.S[3], s4 = G.S[4], s5 = G.S[5];
-    const double V0 = G.M[0] - l * D0, V1 = G.M[1] - l * D1, V2 = G.M[2] - l * D2;
-    const double SV0 = s0 * V0 + s1 * V1 + s2 * V2;
-    const double SV1 = s1 * V0 + s3 * V1 + s4 * V2;
-    const double SV2 = s2 * V0 + s4 * V1 + s5 * V2;
     const double SD0 = s0 * D0 + s1 * D1 + s2 * D2;
     const double SD1 = s1 * D0 + s3 * D1 + s4 * D2;
     const double SD2 = s2 * D0 + s4 * D1 + s5 * D2;
     const double ia = 1.0 / (D0 * SD0 + D1 * SD1 + D2 * SD2);
+    const double l = (G.M[0] * SD0 + G.M[1] * SD1 + G.M[2] * SD2) * ia;
+    const double V0 = G.M[0] - l * D0, V1 = G.M[1] - l * D1, V2 = G.M[2] - l * D2;
+    const double SV0 = s0 * V0 + s1 * V1 + s2 * V2;
+    const double SV1 = s1 * V0 + s3 * V1 + s4 * V2;
+    const double SV2 = s2 * V0 + s4 * V1 + s5 * V2;
     const double dlk = dlt * ia;
     const double hq = -0.5 * dq;
     out[0] = -dq * SV0 + dlk * SD0;
@@ -565,22 +569,29 @@ __device__ __forceinline__ void pair_chain(const GeoRec& G, double D0, double D1
     gD[2] += dq * l * SV2 + dlk * (SV2 - l * SD2) + 2.0 * dat * SD2;
 }
 
-// LDS of k_bwd: hash keys, pair counts, offsets and the compact list of
-// used table entries (hcap ints each).
-size_t bwd_lds_bytes(int hcap, int KB) {
-    (void)KB;
+// Attribute channels per reduction pass: fewer at the deepest K-buffer, so
+// that the partial sums and the pair indices fit 64 KB of LDS.
+__host__ __device__ constexpr int red_ch(int KB) { return KB >= 64 ? 4 : 8; }
+
+// LDS of k_bwd_red: the hash table (keys, pair counts, offsets and the
+// compact list of used entries, hcap ints each), later reused for the
+// reduction's partial sums (head and tail runs of every lane); then the
+// tile's pairs in kernel order as 16-bit indices (256 * KB of them).
+__host__ __device__ inline size_t bwd_table_bytes(int hcap, int KB) {
     const size_t table = (size_t)hcap * 4 * sizeof(int);
-    const size_t partials = (size_t)TILE_THREADS * (2 * (9 + 8) * sizeof(float) + 2 * sizeof(int));
-    return table > partials ? table : partials;
+    const size_t partials = (size_t)TILE_THREADS * (2 * (9 + red_ch(KB)) * sizeof(float) + 2 * sizeof(int));
+    return ((table > partials ? table : partials) + 15) & ~(size_t)15;
 }
 
-constexpr int RED_CH = 8;              // attribute channels per reduction pass
-constexpr int RED_NV = 9 + RED_CH;     // values per partial sum
+size_t bwd_lds_bytes(int hcap, int KB) {
+    return bwd_table_bytes(hcap, KB) + (size_t)TILE_THREADS * KB * sizeof(uint16_t);
+}
 
 // Add one kernel's partial sums to global memory: the 9 geometric values
 // (pass 0 only) and attribute channels c0 .. c0+nc-1.
 __device__ __forceinline__ void flush_values(const TraceArgs& A, int rank, const float* v, bool geom, int c0,
                                              int nc) {
+    // v: the 9 geometric values, then nc channels
     if (geom) {
 #pragma unroll
         for (int q = 0; q < 3; ++q) unsafeAtomicAdd(&A.gM[(size_t)rank * 3 + q], v[q]);
@@ -734,11 +745,11 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
     }
     const int keff = P.valid ? A.keff[P.q] : 0;
     const size_t p = (size_t)P.pi * A.W + P.pj;
-    const double* pl = A.kl_l + P.q;
-    float4* pbw = A.bw + P.q;
-    const float* pbl = A.bwl + P.q;
     const float* Gp = A.grad_image + p * C;
-    PairRec* tile_pairs = A.pairs + (size_t)tile * TILE_THREADS * A.K;
+    const size_t q0 = (size_t)tile * TILE_THREADS;            // the tile's first list index
+    constexpr int RED_CH = red_ch(KB);          // attribute channels per reduction pass
+    constexpr int RED_NV = 9 + RED_CH;           // values per partial sum
+    uint16_t* s_pair = reinterpret_cast<uint16_t*>(smem + bwd_table_bytes(hcap, KB));
     __syncthreads();   // table initialised
 
     // counting sort of the tile's pairs by kernel; sp[k] = table slot << 16 | position.
@@ -802,24 +813,17 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
     for (int k = 0; k < KB; ++k) {
         if (k < keff) {
             if (sp[k] >= 0) {
-                const size_t o = (size_t)k * S;
-                const float4 sc = pbw[o];
-                PairRec r;
-                r.dq = sc.x;
-                r.dl = sc.y + pbl[o];
-                r.da = sc.z;
-                r.w = sc.w;
-                r.l = pl[o];
-                r.pt = tid;
-                r.rank = rk[k];
-                tile_pairs[s_off[sp[k] >> 16] + (sp[k] & 0xFFFF)] = r;
+                // the pair (slot k, pixel tid) at its place in kernel order; bit
+                // 15 marks the first pair of a kernel's run
+                const int pos = sp[k] & 0xFFFF;
+                s_pair[s_off[sp[k] >> 16] + pos] = (uint16_t)((pos == 0 ? 0x8000 : 0) | (k << 8) | tid);
             } else {
                 // table full: this pair goes straight to global memory
-                const size_t o = (size_t)k * S;
+                const size_t o = (size_t)k * S + P.q;
                 const int rank = rk[k];
-                const float4 sc = pbw[o];
+                const float4 sc = A.bw[o];
                 double out[9];
-                pair_chain(A.geo[rank], P.u, P.v, (double)A.F, pl[o], sc.x, sc.y + pbl[o], sc.z, out, gD);
+                pair_chain(A.geo[rank], P.u, P.v, (double)A.F, sc.x, sc.y + A.bwl[o], sc.z, out, gD);
 #pragma unroll
                 for (int e = 0; e < 3; ++e) unsafeAtomicAdd(&A.gM[(size_t)rank * 3 + e], (float)out[e]);
 #pragma unroll
@@ -847,6 +851,31 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
     int* s_tk = s_hk + TILE_THREADS;
     const int per = (n_pairs + TILE_THREADS - 1) / TILE_THREADS;
     const int j0 = min(n_pairs, tid * per), j1 = min(n_pairs, j0 + per);
+    // pair j in kernel order: its scalars gathered from the slot-major lists
+    // (the chain's three only in pass 0); its kernel's rank where a run
+    // starts, or at the chunk's first pair (-1: same kernel as before)
+    struct Pair {
+        float dq, dl, da, w;
+        int rank, pt;
+    };
+    auto load_pair = [&](int j, bool geom) {
+        const int e = s_pair[j];
+        const size_t o = (size_t)((e >> 8) & 63) * S + q0 + (e & 255);
+        Pair r;
+        if (geom) {
+            const float4 sc = A.bw[o];
+            r.dq = sc.x;
+            r.dl = sc.y + A.bwl[o];
+            r.da = sc.z;
+            r.w = sc.w;
+        } else {
+            r.dq = r.dl = r.da = 0.f;
+            r.w = reinterpret_cast<const float*>(A.bw + o)[3];
+        }
+        r.rank = ((e & 0x8000) || j == j0) ? A.kl_r[o] : -1;
+        r.pt = e & 255;
+        return r;
+    };
     for (int c0 = 0; c0 == 0 || c0 < C; c0 += RED_CH) {
         const bool geom = c0 == 0;
         const int nc = max(0, min(RED_CH, C - c0));
@@ -858,12 +887,12 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
         GeoRec G;
         s_hk[tid] = -1;
         s_tk[tid] = -1;
-        PairRec nxt = j0 < j1 ? tile_pairs[j0] : PairRec{};
+        Pair nxt = j0 < j1 ? load_pair(j0, geom) : Pair{};
         for (int j = j0; j <= j1; ++j) {
             const bool end = j == j1;
-            const PairRec r = nxt;
-            if (j + 1 < j1) nxt = tile_pairs[j + 1];
-            if (end || r.rank != cur) {
+            const Pair r = nxt;
+            if (j + 1 < j1) nxt = load_pair(j + 1, geom);
+            if (end || (r.rank >= 0 && r.rank != cur)) {
                 if (cur >= 0) {
                     if (nseg == 0) {                                   // first run: may continue
                         s_hk[tid] = cur;
@@ -886,8 +915,8 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
             const int row = ti0 + (w >> 1) * 8 + (ln >> 3), col = tj0 + (w & 1) * 8 + (ln & 7);
             if (geom) {
                 double out[9];
-                pair_chain(G, (double)row - (double)A.cy, (double)col - (double)A.cx, (double)A.F, r.l, r.dq, r.dl,
-                           r.da, out, gD);
+                pair_chain(G, (double)row - (double)A.cy, (double)col - (double)A.cx, (double)A.F, r.dq, r.dl, r.da,
+                           out, gD);
 #pragma unroll
                 for (int q = 0; q < 9; ++q) acc[q] += (float)out[q];
             }

@@ -57,15 +57,6 @@ struct __align__(8) GeoRec {
 };
 static_assert(sizeof(GeoRec) == 72, "GeoRec is 72 bytes");
 
-// One (pixel, kernel) pair of a tile in the backward, stored kernel-sorted.
-struct __align__(16) PairRec {
-    float dq, dl, da, w;      // dL/dq, dL/dl (D' units), dL/da, W
-    double l;                 // depth l (D' units)
-    int pt;                   // pixel within the tile (lane id)
-    int rank;                 // kernel rank
-};
-static_assert(sizeof(PairRec) == 32, "PairRec is 32 bytes");
-
 struct CamDev {               // camera as passed to kernels
     float R[9], T[3];
     float F, cx, cy;

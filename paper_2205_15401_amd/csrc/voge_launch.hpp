@@ -58,7 +58,6 @@ struct TraceArgs {
     double* tileD;             // [n_tiles][3] per-tile sums of dL/dD'
     float4* bw;                // per-slot backward scalars (dq, dl m-side, da, W), slot-major like the lists
     float* bwl;                // per-slot k-side part of dL/dl, slot-major
-    PairRec* pairs;            // per-tile pair records, kernel-sorted [tiles][256 * K]
 };
 
 // Per-item record in the workspace.
@@ -148,7 +147,7 @@ struct BatchPlan {
     size_t off_items, off_tile_item, off_pblk_item, off_epi_item;
     size_t off_keys, off_vals, off_keys2, off_vals2, off_hist, off_cull, off_rec, off_geo;
     size_t off_keff, off_kl_l, off_kl_m, off_kl_s, off_kl_T, off_kl_r, off_kl_i;
-    size_t off_grads, off_tileD, off_camP, off_bw, off_bwl, off_pairs;
+    size_t off_grads, off_tileD, off_camP, off_bw, off_bwl;
     size_t fwd_bytes, bwd_bytes;
 };
 
