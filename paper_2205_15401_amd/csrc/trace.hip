@@ -91,7 +91,7 @@ __device__ __forceinline__ int balanced_slot(const TraceArgs& A, int tile, int n
     __shared__ int s_perm[TILE_THREADS];
     const int tid = threadIdx.x;
     const PixelCtx P = pixel_of(tile, ntx, A.H, A.W, A.cx, A.cy);
-    const int ke = P.valid ? A.keff[P.q] : 0;
+    const int ke = P.valid ? gp(A.keff)[P.q] : 0;
     const int bin = MAX_K - ke;                  // descending counts
     if (tid < MAX_K + 2) s_bin[tid] = 0;
     __syncthreads();
@@ -230,12 +230,13 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
     int nkey = 0;                                // filled slots (saturates at KB)
     int ub = 0;                                  // the wave's largest nkey (uniform)
     bool done = !P.valid;
+    const auto cull = gp(A.cull);
     CullRec nxt;
-    if (lane < A.N) nxt = A.cull[lane];
+    if (lane < A.N) nxt = load_cull(cull + lane);
     for (int base = 0; base < A.N; base += WAVE) {
         const int r = base + lane;
         const CullRec c = nxt;
-        if (r + WAVE < A.N) nxt = A.cull[r + WAVE];                  // prefetch the next step
+        if (r + WAVE < A.N) nxt = load_cull(cull + r + WAVE);        // prefetch the next step
         const bool hit = r < A.N && c.i0 <= bi0 + 7 && c.i1 >= bi0 && c.j0 <= bj0 + 7 && c.j1 >= bj0;
         uint64_t mm = __ballot(hit);             // this step's candidates, one bit per record
         if (mm != 0) {
@@ -299,15 +300,15 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
             double l, q2, a;
             trace_one(R, P.u, P.v, l, q2, a);
             const size_t o = (size_t)s * S + P.q;
-            A.kl_l[o] = l;
-            A.kl_m[o] = expf(-0.5f * (float)q2);
-            A.kl_s[o] = (float)sqrt(a);
-            A.kl_r[o] = rank;
-            A.kl_i[o] = (int)R.idx;
+            gp(A.kl_l)[o] = l;
+            gp(A.kl_m)[o] = expf(-0.5f * (float)q2);
+            gp(A.kl_s)[o] = (float)sqrt(a);
+            gp(A.kl_r)[o] = rank;
+            gp(A.kl_i)[o] = (int)R.idx;
             ++keff;
         }
     }
-    A.keff[P.q] = keff;
+    gp(A.keff)[P.q] = keff;
 }
 
 // ----------------------------------------------------------------- sampler
@@ -350,10 +351,10 @@ __device__ __forceinline__ void sample_tile(const TraceArgs& A, bool valid, size
     for (int i = tid; i < SAMPLE_HCAP; i += TILE_THREADS) s_key[i] = -1;
     for (int i = tid; i < SAMPLE_HCAP * nv; i += TILE_THREADS) s_val[i] = 0.f;
     __syncthreads();
-    const float* phi = A.grad_image + p * C;
-    const float* pT = A.kl_T + q;
-    const float* pm = A.kl_m + q;
-    const int* pi = A.kl_i + q;
+    const auto phi = gp(A.grad_image) + p * C;
+    const auto pT = gp(A.kl_T) + q;
+    const auto pm = gp(A.kl_m) + q;
+    const auto pi = gp(A.kl_i) + q;
     for (int c0 = 0; c0 == 0 || c0 < C; c0 += SAMPLE_CH) {
         const int nc = min(SAMPLE_CH, C - c0);
         if (c0 > 0) {
@@ -384,10 +385,10 @@ __device__ __forceinline__ void sample_tile(const TraceArgs& A, bool valid, size
                 for (int c = 0; c < SAMPLE_CH; ++c)
                     if (c < nc) atomicAdd(v + 1 + c, w * f[c]);
             } else {
-                if (c0 == 0) unsafeAtomicAdd(&A.gW[key], w);
+                if (c0 == 0) global_add(&A.gW[key], w);
 #pragma unroll
                 for (int c = 0; c < SAMPLE_CH; ++c)
-                    if (c < nc) unsafeAtomicAdd(&A.gA[(size_t)key * C + c0 + c], w * f[c]);
+                    if (c < nc) global_add(&A.gA[(size_t)key * C + c0 + c], w * f[c]);
             }
         }
         __syncthreads();
@@ -395,8 +396,8 @@ __device__ __forceinline__ void sample_tile(const TraceArgs& A, bool valid, size
             const int key = s_key[i];
             if (key < 0) continue;
             const float* v = s_val + i * nv;
-            if (c0 == 0) unsafeAtomicAdd(&A.gW[key], v[0]);
-            for (int c = 0; c < nc; ++c) unsafeAtomicAdd(&A.gA[(size_t)key * C + c0 + c], v[1 + c]);
+            if (c0 == 0) global_add(&A.gW[key], v[0]);
+            for (int c = 0; c < nc; ++c) global_add(&A.gA[(size_t)key * C + c0 + c], v[1 + c]);
         }
         if (c0 + SAMPLE_CH < C) __syncthreads();
     }
@@ -409,11 +410,11 @@ __device__ __forceinline__ void blend_body(const TraceArgs& A, int tile, unsigne
     const int ntx = (A.W + TILE - 1) / TILE;
     const PixelCtx P = pixel_at(tile, balanced_slot(A, tile, ntx), ntx, A.H, A.W, A.cx, A.cy);
     const size_t S = A.S;
-    const int keff = P.valid ? A.keff[P.q] : 0;
+    const int keff = P.valid ? gp(A.keff)[P.q] : 0;
     const int kmax = wave_max_keff(keff);
-    const double* pl = A.kl_l + P.q;
-    const float* pm = A.kl_m + P.q;
-    const float* ps = A.kl_s + P.q;
+    const auto pl = gp(A.kl_l) + P.q;
+    const auto pm = gp(A.kl_m) + P.q;
+    const auto ps = gp(A.kl_s) + P.q;
 
     double lk[KB];
     float E[KB];
@@ -456,49 +457,68 @@ __device__ __forceinline__ void blend_body(const TraceArgs& A, int tile, unsigne
         Wt[k] = 0.f;
         ik[k] = 0;
         if (k < keff) {
-            const size_t o = (size_t)k * S + P.q;
+            const size_t o = (size_t)k * S;
             const float T = expf(-E[k]);
-            A.kl_T[o] = T;
-            Wt[k] = T * A.kl_m[o];
-            ik[k] = A.kl_i[o];
+            gp(A.kl_T)[o + P.q] = T;
+            Wt[k] = T * pm[o];
+            ik[k] = gp(A.kl_i)[o + P.q];
             ws += Wt[k];
         }
     }
     if (SAMPLE) sample_tile(A, P.valid, P.q, p, keff, smem);
     if (!P.valid) return;
-    if (A.image) {
+    // the colour sum: the gathers of each group of four slots are issued
+    // together (slots past keff gather row 0 with weight 0; kmax > 0 implies
+    // a kernel set with rows)
+    if (A.image && kmax > 0) {
         if ((A.C & 3) == 0) {
             // four channels per load and store
             const int C4 = A.C >> 2;
-            const float4* a4 = reinterpret_cast<const float4*>(A.attrs);
-            float4* o4 = reinterpret_cast<float4*>(A.image) + p * C4;
+            const auto a4 = gp(reinterpret_cast<const float4*>(A.attrs));
+            const auto o4 = gp(reinterpret_cast<float4*>(A.image)) + p * C4;
             for (int c = 0; c < C4; ++c) {
                 float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-                for (int k = 0; k < KB; ++k) {
-                    if (k < keff) {
-                        const float4 v = a4[(size_t)ik[k] * C4 + c];
-                        acc.x = fmaf(Wt[k], v.x, acc.x);
-                        acc.y = fmaf(Wt[k], v.y, acc.y);
-                        acc.z = fmaf(Wt[k], v.z, acc.z);
-                        acc.w = fmaf(Wt[k], v.w, acc.w);
+                for (int k0 = 0; k0 < KB; k0 += 4) {
+                    if (k0 < kmax) {
+                        float4 v[4];
+#pragma unroll
+                        for (int k = k0; k < k0 + 4 && k < KB; ++k) v[k - k0] = ld_f4(a4 + (size_t)ik[k] * C4 + c);
+#pragma unroll
+                        for (int k = k0; k < k0 + 4 && k < KB; ++k) {
+                            acc.x = fmaf(Wt[k], v[k - k0].x, acc.x);
+                            acc.y = fmaf(Wt[k], v[k - k0].y, acc.y);
+                            acc.z = fmaf(Wt[k], v[k - k0].z, acc.z);
+                            acc.w = fmaf(Wt[k], v[k - k0].w, acc.w);
+                        }
                     }
                 }
-                o4[c] = acc;
+                st_f4(o4 + c, acc);
             }
         } else {
+            const auto at = gp(A.attrs);
+            const auto img = gp(A.image);
             for (int c = 0; c < A.C; ++c) {
                 float acc = 0.f;
 #pragma unroll
-                for (int k = 0; k < KB; ++k)
-                    if (k < keff) acc = fmaf(Wt[k], A.attrs[(size_t)ik[k] * A.C + c], acc);
-                A.image[p * A.C + c] = acc;
+                for (int k0 = 0; k0 < KB; k0 += 4) {
+                    if (k0 < kmax) {
+                        float v[4];
+#pragma unroll
+                        for (int k = k0; k < k0 + 4 && k < KB; ++k) v[k - k0] = at[(size_t)ik[k] * A.C + c];
+#pragma unroll
+                        for (int k = k0; k < k0 + 4 && k < KB; ++k) acc = fmaf(Wt[k], v[k - k0], acc);
+                    }
+                }
+                img[p * A.C + c] = acc;
             }
         }
+    } else if (A.image) {
+        for (int c = 0; c < A.C; ++c) gp(A.image)[p * A.C + c] = 0.f;
     }
-    if (A.wsum) A.wsum[p] = ws;
+    if (A.wsum) gp(A.wsum)[p] = ws;
     if (A.kept) {
-        for (int s = 0; s < A.K; ++s) A.kept[p * A.K + s] = s < keff ? A.kl_i[(size_t)s * S + P.q] : -1;
+        for (int s = 0; s < A.K; ++s) gp(A.kept)[p * A.K + s] = s < keff ? gp(A.kl_i)[(size_t)s * S + P.q] : -1;
     }
 }
 
@@ -594,11 +614,11 @@ __device__ __forceinline__ void flush_values(const TraceArgs& A, int rank, const
     // v: the 9 geometric values, then nc channels
     if (geom) {
 #pragma unroll
-        for (int q = 0; q < 3; ++q) unsafeAtomicAdd(&A.gM[(size_t)rank * 3 + q], v[q]);
+        for (int q = 0; q < 3; ++q) global_add(&A.gM[(size_t)rank * 3 + q], v[q]);
 #pragma unroll
-        for (int q = 0; q < 6; ++q) unsafeAtomicAdd(&A.gS[(size_t)rank * 6 + q], v[3 + q]);
+        for (int q = 0; q < 6; ++q) global_add(&A.gS[(size_t)rank * 6 + q], v[3 + q]);
     }
-    for (int q = 0; q < nc; ++q) unsafeAtomicAdd(&A.gA[(size_t)rank * A.C + c0 + q], v[9 + q]);
+    for (int q = 0; q < nc; ++q) global_add(&A.gA[(size_t)rank * A.C + c0 + q], v[9 + q]);
 }
 
 // Backward, pixel phase: per-pair scalars (dq, dl, da, W) into the scratch list.
@@ -609,16 +629,16 @@ __device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile) {
     const size_t S = A.S;
     const int C = A.C;
 
-    const int keff = P.valid ? A.keff[P.q] : 0;
+    const int keff = P.valid ? gp(A.keff)[P.q] : 0;
     const int kmax = wave_max_keff(keff);
     const size_t p = (size_t)P.pi * A.W + P.pj;
-    const double* pl = A.kl_l + P.q;
-    const float* pm = A.kl_m + P.q;
-    const float* ps = A.kl_s + P.q;
-    const float* pT = A.kl_T + P.q;
-    const int* pi = A.kl_i + P.q;
-    float4* pbw = A.bw + P.q;
-    const float* Gp = A.grad_image + p * C;
+    const auto pl = gp(A.kl_l) + P.q;
+    const auto pm = gp(A.kl_m) + P.q;
+    const auto ps = gp(A.kl_s) + P.q;
+    const auto pT = gp(A.kl_T) + P.q;
+    const auto pi = gp(A.kl_i) + P.q;
+    const auto pbw = gp(A.bw) + P.q;
+    const auto Gp = gp(A.grad_image) + p * C;
 
     double lk[KB];
     float dE[KB], dl[KB], dmd[KB];
@@ -635,31 +655,47 @@ __device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile) {
             ik[k] = pi[(size_t)k * S];
         }
     }
-    // g_k = G . c_k
+    // g_k = G . c_k; the gathers of each group of four slots are issued
+    // together (slots past keff gather row 0, unused; kmax > 0 implies a
+    // kernel set with rows)
     float g[KB];
 #pragma unroll
     for (int k = 0; k < KB; ++k) g[k] = 0.f;
-    if (keff > 0) {
+    if (kmax > 0) {
         if ((C & 3) == 0) {
-            const float4* G4 = reinterpret_cast<const float4*>(Gp);
-            const float4* A4 = reinterpret_cast<const float4*>(A.attrs);
+            const auto G4 = gp(reinterpret_cast<const float4*>(A.grad_image)) + p * (C >> 2);
+            const auto A4 = gp(reinterpret_cast<const float4*>(A.attrs));
             const int C4 = C >> 2;
             for (int c = 0; c < C4; ++c) {
-                const float4 Gc = G4[c];
+                float4 Gc = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (keff > 0) Gc = ld_f4(G4 + c);
 #pragma unroll
-                for (int k = 0; k < KB; ++k) {
-                    if (k < keff) {
-                        const float4 a = A4[(size_t)ik[k] * C4 + c];
-                        g[k] = fmaf(Gc.x, a.x, fmaf(Gc.y, a.y, fmaf(Gc.z, a.z, fmaf(Gc.w, a.w, g[k]))));
+                for (int k0 = 0; k0 < KB; k0 += 4) {
+                    if (k0 < kmax) {
+                        float4 a[4];
+#pragma unroll
+                        for (int k = k0; k < k0 + 4 && k < KB; ++k) a[k - k0] = ld_f4(A4 + (size_t)ik[k] * C4 + c);
+#pragma unroll
+                        for (int k = k0; k < k0 + 4 && k < KB; ++k)
+                            g[k] = fmaf(Gc.x, a[k - k0].x,
+                                        fmaf(Gc.y, a[k - k0].y, fmaf(Gc.z, a[k - k0].z, fmaf(Gc.w, a[k - k0].w, g[k]))));
                     }
                 }
             }
         } else {
+            const auto at = gp(A.attrs);
             for (int c = 0; c < C; ++c) {
-                const float Gc = Gp[c];
+                const float Gc = keff > 0 ? Gp[c] : 0.f;
 #pragma unroll
-                for (int k = 0; k < KB; ++k)
-                    if (k < keff) g[k] = fmaf(Gc, A.attrs[(size_t)ik[k] * C + c], g[k]);
+                for (int k0 = 0; k0 < KB; k0 += 4) {
+                    if (k0 < kmax) {
+                        float a[4];
+#pragma unroll
+                        for (int k = k0; k < k0 + 4 && k < KB; ++k) a[k - k0] = at[(size_t)ik[k] * C + c];
+#pragma unroll
+                        for (int k = k0; k < k0 + 4 && k < KB; ++k) g[k] = fmaf(Gc, a[k - k0], g[k]);
+                    }
+                }
             }
         }
     }
@@ -714,10 +750,10 @@ __device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile) {
         float dmd_m = 0.f;                       // dmd[m], m uniform in the wave
 #pragma unroll
         for (int k = 0; k < KB; ++k) dmd_m = k == m ? dmd[k] : dmd_m;
-        if (in) pbw[o] = make_float4((dmd_m + acc_dm) * mm, acc_dl, acc_da, tm * mm);
+        if (in) st_f4(pbw + o, make_float4((dmd_m + acc_dm) * mm, acc_dl, acc_da, tm * mm));
     }
     // the k-side part of dL/dl of each slot
-    float* pbl = A.bwl + P.q;
+    const auto pbl = gp(A.bwl) + P.q;
 #pragma unroll
     for (int k = 0; k < KB; ++k)
         if (k < keff) pbl[(size_t)k * S] = dl[k];
@@ -743,7 +779,7 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
         s_hkey[i] = -1;
         s_cnt[i] = 0;
     }
-    const int keff = P.valid ? A.keff[P.q] : 0;
+    const int keff = P.valid ? gp(A.keff)[P.q] : 0;
     const size_t p = (size_t)P.pi * A.W + P.pj;
     const float* Gp = A.grad_image + p * C;
     const size_t q0 = (size_t)tile * TILE_THREADS;            // the tile's first list index
@@ -757,7 +793,7 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
     // factor) then probe on.
     int sp[KB], rk[KB];
 #pragma unroll
-    for (int k = 0; k < KB; ++k) rk[k] = k < keff ? A.kl_r[P.q + (size_t)k * S] : -1;
+    for (int k = 0; k < KB; ++k) rk[k] = k < keff ? gp(A.kl_r)[P.q + (size_t)k * S] : -1;
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
         sp[k] = -1;
@@ -825,10 +861,10 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
                 double out[9];
                 pair_chain(A.geo[rank], P.u, P.v, (double)A.F, sc.x, sc.y + A.bwl[o], sc.z, out, gD);
 #pragma unroll
-                for (int e = 0; e < 3; ++e) unsafeAtomicAdd(&A.gM[(size_t)rank * 3 + e], (float)out[e]);
+                for (int e = 0; e < 3; ++e) global_add(&A.gM[(size_t)rank * 3 + e], (float)out[e]);
 #pragma unroll
-                for (int e = 0; e < 6; ++e) unsafeAtomicAdd(&A.gS[(size_t)rank * 6 + e], (float)out[3 + e]);
-                for (int c = 0; c < C; ++c) unsafeAtomicAdd(&A.gA[(size_t)rank * C + c], sc.w * Gp[c]);
+                for (int e = 0; e < 6; ++e) global_add(&A.gS[(size_t)rank * 6 + e], (float)out[3 + e]);
+                for (int c = 0; c < C; ++c) global_add(&A.gA[(size_t)rank * C + c], sc.w * Gp[c]);
             }
         }
     }
@@ -863,16 +899,16 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
         const size_t o = (size_t)((e >> 8) & 63) * S + q0 + (e & 255);
         Pair r;
         if (geom) {
-            const float4 sc = A.bw[o];
+            const float4 sc = ld_f4(gp(A.bw) + o);
             r.dq = sc.x;
-            r.dl = sc.y + A.bwl[o];
+            r.dl = sc.y + gp(A.bwl)[o];
             r.da = sc.z;
             r.w = sc.w;
         } else {
             r.dq = r.dl = r.da = 0.f;
-            r.w = reinterpret_cast<const float*>(A.bw + o)[3];
+            r.w = gp(reinterpret_cast<const float*>(A.bw + o))[3];
         }
-        r.rank = ((e & 0x8000) || j == j0) ? A.kl_r[o] : -1;
+        r.rank = ((e & 0x8000) || j == j0) ? gp(A.kl_r)[o] : -1;
         r.pt = e & 255;
         return r;
     };
@@ -909,7 +945,7 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
 #pragma unroll
                 for (int q = 0; q < RED_NV; ++q) acc[q] = 0.f;
                 cur = r.rank;
-                if (geom) G = A.geo[cur];
+                if (geom) G = load_geo(gp(A.geo) + cur);
             }
             const int w = r.pt / WAVE, ln = r.pt % WAVE;
             const int row = ti0 + (w >> 1) * 8 + (ln >> 3), col = tj0 + (w & 1) * 8 + (ln & 7);
@@ -920,11 +956,11 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
 #pragma unroll
                 for (int q = 0; q < 9; ++q) acc[q] += (float)out[q];
             }
-            const float* Gq = A.grad_image + ((size_t)row * A.W + col) * C + c0;
+            const auto Gq = gp(A.grad_image) + ((size_t)row * A.W + col) * C + c0;
             if (nc == RED_CH && (C & 3) == 0) {
 #pragma unroll
                 for (int q = 0; q < RED_CH; q += 4) {
-                    const float4 g4 = *reinterpret_cast<const float4*>(Gq + q);
+                    const float4 g4 = ld_f4((gptr<const float4>)(Gq + q));
                     acc[9 + q] = fmaf(r.w, g4.x, acc[9 + q]);
                     acc[10 + q] = fmaf(r.w, g4.y, acc[10 + q]);
                     acc[11 + q] = fmaf(r.w, g4.z, acc[11 + q]);

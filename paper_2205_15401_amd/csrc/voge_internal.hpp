@@ -74,6 +74,43 @@ __device__ __forceinline__ uint32_t float_order_key(float f) {
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
+// The same address as a pointer into the global address space: loads and
+// stores through it are global accesses, not flat ones (a flat access also
+// counts against the LDS / scalar-load wait counter, so waiting for it
+// waits for those too).  For pointers read from memory, whose address space
+// the compiler cannot infer.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> gp(T* p) {
+    return (gptr<T>)p;
+}
+
+// Whole-record loads and stores through global pointers (the records'
+// implicit copy operators take generic references, which a global object
+// cannot bind to): 16-byte vectors as one access, records member by member.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float4 ld_f4(gptr<const float4> p) {
+    const f32x4 v = *(gptr<const f32x4>)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ void st_f4(gptr<float4> p, float4 a) {
+    f32x4 v;
+    v.x = a.x;
+    v.y = a.y;
+    v.z = a.z;
+    v.w = a.w;
+    *(gptr<f32x4>)p = v;
+}
+
+// Float atomic add to global memory (no return value).
+__device__ __forceinline__ void global_add(float* p, float v) {
+    __builtin_amdgcn_global_atomic_fadd_f32(gp(p), v);
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
     const int lane = __lane_id();
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -115,6 +152,26 @@ __device__ __forceinline__ void rotate_sym(const double R[9], const double A[6],
     auto e = [&](int r, int c) { return RA[3 * r] * R[3 * c] + RA[3 * r + 1] * R[3 * c + 1] + RA[3 * r + 2] * R[3 * c + 2]; };
     B[0] = e(0, 0); B[1] = e(0, 1); B[2] = e(0, 2);
     B[3] = e(1, 1); B[4] = e(1, 2); B[5] = e(2, 2);
+}
+
+__device__ __forceinline__ CullRec load_cull(gptr<const CullRec> p) {
+    CullRec c;
+    c.i0 = p->i0;
+    c.i1 = p->i1;
+    c.j0 = p->j0;
+    c.j1 = p->j1;
+    c.tlo = p->tlo;
+    c.pad = 0;
+    return c;
+}
+
+__device__ __forceinline__ GeoRec load_geo(gptr<const GeoRec> p) {
+    GeoRec g;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) g.M[i] = p->M[i];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) g.S[i] = p->S[i];
+    return g;
 }
 
 }  // namespace voge
