@@ -857,14 +857,15 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
                 // table full: this pair goes straight to global memory
                 const size_t o = (size_t)k * S + P.q;
                 const int rank = rk[k];
-                const float4 sc = A.bw[o];
+                const float4 sc = ld_f4(gp(A.bw) + o);
                 double out[9];
-                pair_chain(A.geo[rank], P.u, P.v, (double)A.F, sc.x, sc.y + A.bwl[o], sc.z, out, gD);
+                pair_chain(load_geo(gp(A.geo) + rank), P.u, P.v, (double)A.F, sc.x, sc.y + gp(A.bwl)[o], sc.z, out,
+                           gD);
 #pragma unroll
                 for (int e = 0; e < 3; ++e) global_add(&A.gM[(size_t)rank * 3 + e], (float)out[e]);
 #pragma unroll
                 for (int e = 0; e < 6; ++e) global_add(&A.gS[(size_t)rank * 6 + e], (float)out[3 + e]);
-                for (int c = 0; c < C; ++c) global_add(&A.gA[(size_t)rank * C + c], sc.w * Gp[c]);
+                for (int c = 0; c < C; ++c) global_add(&A.gA[(size_t)rank * C + c], sc.w * gp(Gp)[c]);
             }
         }
     }
@@ -1005,7 +1006,7 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
     if (tid < 3) {
         double sum = 0.0;
         for (int w = 0; w < TILE_THREADS / WAVE; ++w) sum += s_red[w][tid];
-        A.tileD[(size_t)tile * 3 + tid] = sum;
+        gp(A.tileD)[(size_t)tile * 3 + tid] = sum;
     }
 }
 
