@@ -595,16 +595,19 @@ __host__ __device__ constexpr int red_ch(int KB) { return KB >= 64 ? 4 : 8; }
 
 // LDS of k_bwd_red: the hash table (keys, pair counts, offsets and the
 // compact list of used entries, hcap ints each), later reused for the
-// reduction's partial sums (head and tail runs of every lane); then the
-// tile's pairs in kernel order as 16-bit indices (256 * KB of them).
-__host__ __device__ inline size_t bwd_table_bytes(int hcap, int KB) {
+// reduction's partial sums (head and tail runs of every lane, nv values
+// each: the 9 geometric ones and one pass's channels); then the tile's pairs
+// in kernel order as 16-bit indices (256 * KB of them).
+__host__ __device__ inline int bwd_partial_values(int C, int KB) { return 9 + (C < red_ch(KB) ? C : red_ch(KB)); }
+
+__host__ __device__ inline size_t bwd_table_bytes(int hcap, int nv) {
     const size_t table = (size_t)hcap * 4 * sizeof(int);
-    const size_t partials = (size_t)TILE_THREADS * (2 * (9 + red_ch(KB)) * sizeof(float) + 2 * sizeof(int));
+    const size_t partials = (size_t)TILE_THREADS * (2 * nv * sizeof(float) + 2 * sizeof(int));
     return ((table > partials ? table : partials) + 15) & ~(size_t)15;
 }
 
-size_t bwd_lds_bytes(int hcap, int KB) {
-    return bwd_table_bytes(hcap, KB) + (size_t)TILE_THREADS * KB * sizeof(uint16_t);
+size_t bwd_lds_bytes(int hcap, int KB, int max_c) {
+    return bwd_table_bytes(hcap, bwd_partial_values(max_c, KB)) + (size_t)TILE_THREADS * KB * sizeof(uint16_t);
 }
 
 // Add one kernel's partial sums to global memory: the 9 geometric values
@@ -784,8 +787,9 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
     const float* Gp = A.grad_image + p * C;
     const size_t q0 = (size_t)tile * TILE_THREADS;            // the tile's first list index
     constexpr int RED_CH = red_ch(KB);          // attribute channels per reduction pass
-    constexpr int RED_NV = 9 + RED_CH;           // values per partial sum
-    uint16_t* s_pair = reinterpret_cast<uint16_t*>(smem + bwd_table_bytes(hcap, KB));
+    constexpr int RED_NV = 9 + RED_CH;           // values per partial sum (registers)
+    const int nvs = bwd_partial_values(C, KB);   // values per partial sum in LDS
+    uint16_t* s_pair = reinterpret_cast<uint16_t*>(smem + bwd_table_bytes(hcap, nvs));
     __syncthreads();   // table initialised
 
     // counting sort of the tile's pairs by kernel; sp[k] = table slot << 16 | position.
@@ -883,8 +887,8 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
     const int n_pairs = s_off[hcap - 1] + s_cnt[hcap - 1];
     __syncthreads();   // the table's LDS becomes the partial-sum buffers
     float* s_head = reinterpret_cast<float*>(smem);
-    float* s_tail = s_head + TILE_THREADS * RED_NV;
-    int* s_hk = reinterpret_cast<int*>(s_tail + TILE_THREADS * RED_NV);
+    float* s_tail = s_head + TILE_THREADS * nvs;
+    int* s_hk = reinterpret_cast<int*>(s_tail + TILE_THREADS * nvs);
     int* s_tk = s_hk + TILE_THREADS;
     const int per = (n_pairs + TILE_THREADS - 1) / TILE_THREADS;
     const int j0 = min(n_pairs, tid * per), j1 = min(n_pairs, j0 + per);
@@ -933,10 +937,14 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
                 if (cur >= 0) {
                     if (nseg == 0) {                                   // first run: may continue
                         s_hk[tid] = cur;
-                        for (int q = v0; q < RED_NV; ++q) s_head[tid * RED_NV + q] = acc[q];
+#pragma unroll
+                        for (int q = 0; q < RED_NV; ++q)
+                            if (q >= v0 && q < nvs) s_head[tid * nvs + q] = acc[q];
                     } else if (end) {                                  // last run: may continue
                         s_tk[tid] = cur;
-                        for (int q = v0; q < RED_NV; ++q) s_tail[tid * RED_NV + q] = acc[q];
+#pragma unroll
+                        for (int q = 0; q < RED_NV; ++q)
+                            if (q >= v0 && q < nvs) s_tail[tid * nvs + q] = acc[q];
                     } else {                                           // complete run
                         flush_values(A, cur, acc, geom, c0, nc);
                     }
@@ -980,13 +988,15 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
                 const int prev = s_tk[tid - 1] >= 0 ? s_tk[tid - 1] : s_hk[tid - 1];
                 if (prev == k) continue;                               // started in an earlier chunk
             }
-            const float* own = (which == 0 ? s_head : s_tail) + tid * RED_NV;
+            const float* own = (which == 0 ? s_head : s_tail) + tid * nvs;
             float sum[RED_NV];
 #pragma unroll
-            for (int q = 0; q < RED_NV; ++q) sum[q] = q >= v0 ? own[q] : 0.f;
+            for (int q = 0; q < RED_NV; ++q) sum[q] = (q >= v0 && q < nvs) ? own[q] : 0.f;
             for (int t2 = tid + 1; t2 < TILE_THREADS && s_hk[t2] == k; ++t2) {
                 if (which == 0 && s_tk[tid] >= 0) break;              // own head run ended in this chunk
-                for (int q = v0; q < RED_NV; ++q) sum[q] += s_head[t2 * RED_NV + q];
+#pragma unroll
+                for (int q = 0; q < RED_NV; ++q)
+                    if (q >= v0 && q < nvs) sum[q] += s_head[t2 * nvs + q];
                 if (s_tk[t2] >= 0) break;                             // the run ends inside chunk t2
             }
             flush_values(A, k, sum, geom, c0, nc);
@@ -1196,7 +1206,7 @@ static hipError_t run_kb(int which, const GroupDev& g, hipStream_t s, int max_c 
         hipLaunchKernelGGL(k_bwd_pix<KB>, dim3(nt), dim3(TILE_THREADS), 0, s, g);
     } else if (which == 3) {
         const int hcap = table_capacity(0);
-        hipLaunchKernelGGL(k_bwd_red<KB>, dim3(nt), dim3(TILE_THREADS), bwd_lds_bytes(hcap, KB), s, g, hcap);
+        hipLaunchKernelGGL(k_bwd_red<KB>, dim3(nt), dim3(TILE_THREADS), bwd_lds_bytes(hcap, KB, max_c), s, g, hcap);
     } else {
         hipLaunchKernelGGL(k_blend_sample<KB>, dim3(nt), dim3(TILE_THREADS), sample_lds_bytes(max_c), s, g);
     }
@@ -1216,7 +1226,9 @@ static hipError_t dispatch(int which, const GroupDev& g, int kb, hipStream_t s, 
 hipError_t launch_select(const GroupDev& g, int kb, hipStream_t s) { return dispatch(0, g, kb, s); }
 hipError_t launch_blend(const GroupDev& g, int kb, hipStream_t s) { return dispatch(1, g, kb, s); }
 hipError_t launch_bwd(const GroupDev& g, int kb, hipStream_t s) { return dispatch(2, g, kb, s); }
-hipError_t launch_bwd_reduce(const GroupDev& g, int kb, hipStream_t s) { return dispatch(3, g, kb, s); }
+hipError_t launch_bwd_reduce(const GroupDev& g, int kb, int max_c, hipStream_t s) {
+    return dispatch(3, g, kb, s, max_c);
+}
 hipError_t launch_blend_sample(const GroupDev& g, int kb, int max_c, hipStream_t s) {
     return dispatch(4, g, kb, s, max_c);
 }

@@ -158,7 +158,7 @@ constexpr size_t PREFIX_BYTES = OFF_STATUS + sizeof(int) * MAX_BATCH;
 int pick_kbuf(int K);        // compiled K-buffer depth for a requested K
 int sort_blocks(int N);
 int table_capacity(int C);   // entries of the per-tile gradient table
-size_t bwd_lds_bytes(int hcap, int KB);
+size_t bwd_lds_bytes(int hcap, int KB, int max_c);
 
 // Items first .. first+count-1: writes their table records from the launch
 // arguments (from_args, count <= INIT_ITEMS) or reads them from the table,
@@ -178,7 +178,7 @@ void launch_prep(const BatchDev& b, int total_pblk, int total_kern, int max_n, u
 hipError_t launch_select(const GroupDev& g, int kb, hipStream_t s);
 hipError_t launch_blend(const GroupDev& g, int kb, hipStream_t s);
 hipError_t launch_bwd(const GroupDev& g, int kb, hipStream_t s);          // pixel phase
-hipError_t launch_bwd_reduce(const GroupDev& g, int kb, hipStream_t s);   // tile reduction
+hipError_t launch_bwd_reduce(const GroupDev& g, int kb, int max_c, hipStream_t s);   // tile reduction
 // blend plus the sampler; max_c: the largest channel count of the group's items
 hipError_t launch_blend_sample(const GroupDev& g, int kb, int max_c, hipStream_t s);
 hipError_t launch_phi(const float* x, float* y, int n, hipStream_t s);
