@@ -35,27 +35,28 @@ __global__ __launch_bounds__(EPI_THREADS) void k_epilogue(BatchDev B) {
 #pragma unroll
     for (int e = 0; e < 12; ++e) part[e] = 0.0;
     if (r < A.N) {
-        const size_t n = A.rec[r].idx;
+        const size_t n = (gp(A.rec) + r)->idx;
         double gm[3] = {0.0, 0.0, 0.0};
         double gc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         double M0[3], Sig[6], S0[6];
         bool ok = true;
         for (int d = 0; d < 3; ++d) {
-            M0[d] = (double)it.means[n * 3 + d];
+            M0[d] = (double)gp(it.means)[n * 3 + d];
             ok = ok && isfinite(M0[d]);
         }
         for (int e = 0; e < 6; ++e) {
-            Sig[e] = (double)it.covs[n * 6 + e];
+            Sig[e] = (double)gp(it.covs)[n * 6 + e];
             ok = ok && isfinite(Sig[e]);
         }
         ok = ok && spd_inverse6(Sig, S0);
         if (ok) {
             double R[9];
             for (int e = 0; e < 9; ++e) R[e] = (double)it.cam.R[e];
-            const double g0 = A.gM[(size_t)r * 3], g1 = A.gM[(size_t)r * 3 + 1], g2 = A.gM[(size_t)r * 3 + 2];
+            const auto gM = gp(A.gM) + (size_t)r * 3;
+            const double g0 = gM[0], g1 = gM[1], g2 = gM[2];
             double G[9];
             {
-                const float* q = A.gS + (size_t)r * 6;
+                const auto q = gp(A.gS) + (size_t)r * 6;
                 G[0] = q[0]; G[1] = q[1]; G[2] = q[2];
                 G[3] = q[1]; G[4] = q[3]; G[5] = q[4];
                 G[6] = q[2]; G[7] = q[4]; G[8] = q[5];
@@ -99,11 +100,11 @@ __global__ __launch_bounds__(EPI_THREADS) void k_epilogue(BatchDev B) {
                 part[11] = g2;
             }
         }
-        for (int d = 0; d < 3; ++d) it.grad_means[n * 3 + d] = (float)gm[d];
-        for (int e = 0; e < 6; ++e) it.grad_covs[n * 6 + e] = (float)gc[e];
+        for (int d = 0; d < 3; ++d) gp(it.grad_means)[n * 3 + d] = (float)gm[d];
+        for (int e = 0; e < 6; ++e) gp(it.grad_covs)[n * 6 + e] = (float)gc[e];
         const int C = A.C;
-        const float* ga = A.gA + (size_t)r * C;
-        float* go = it.grad_attrs + n * C;
+        const auto ga = gp(A.gA) + (size_t)r * C;
+        const auto go = gp(it.grad_attrs) + n * C;
         for (int c = 0; c < C; ++c) go[c] = ga[c];
     }
     if (want_cam) {
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(EPI_THREADS) void k_epilogue(BatchDev B) {
         if (threadIdx.x < 12) {
             double s = 0.0;
             for (int w = 0; w < EPI_THREADS / WAVE; ++w) s += s_red[w][threadIdx.x];
-            it.camP[(size_t)lb * 12 + threadIdx.x] = s;
+            gp(it.camP)[(size_t)lb * 12 + threadIdx.x] = s;
         }
     }
 }
@@ -154,15 +155,15 @@ __global__ __launch_bounds__(EPI_THREADS) void k_sample_epilogue(BatchDev B) {
     if (r >= A.N) return;
     const size_t n = r;
     const int C = A.C;
-    const float den = A.gW[n];
-    const float* num = A.gA + n * C;
-    float* out = it.sampled + n * C;
+    const float den = gp(A.gW)[n];
+    const auto num = gp(A.gA) + n * C;
+    const auto out = gp(it.sampled) + n * C;
     if (den > 0.f) {
         for (int c = 0; c < C; ++c) out[c] = num[c] / den;
     } else {
         for (int c = 0; c < C; ++c) out[c] = 0.f;
     }
-    if (it.sample_weight) it.sample_weight[n] = den;
+    if (it.sample_weight) gp(it.sample_weight)[n] = den;
 }
 
 hipError_t launch_sample_epilogue(const BatchDev& b, int total_epi, hipStream_t s) {

@@ -22,12 +22,14 @@ __device__ __forceinline__ double depth_bound(double Mz, double Szz, double rad2
 __device__ __forceinline__ bool load_kernel(const float* __restrict__ means, const float* __restrict__ covs, int n,
                                             double M0[3], double Sig[6]) {
     bool ok = true;
+    const auto m = gp(means) + 3 * (size_t)n;
+    const auto c = gp(covs) + 6 * (size_t)n;
     for (int d = 0; d < 3; ++d) {
-        M0[d] = (double)means[3 * (size_t)n + d];
+        M0[d] = (double)m[d];
         ok = ok && isfinite(M0[d]);
     }
     for (int e = 0; e < 6; ++e) {
-        Sig[e] = (double)covs[6 * (size_t)n + e];
+        Sig[e] = (double)c[e];
         ok = ok && isfinite(Sig[e]);
     }
     return ok;
