@@ -20,22 +20,21 @@ __device__ __forceinline__ double wave_sum_d(double x) {
     return x;
 }
 
-// One thread per kernel rank of an item; a block belongs to one item.  The
-// attribute gradients, accumulated in rank order, go to the caller's buffer
-// in original order.
+// One thread per kernel of an item, in original order (the accumulators
+// are kept in that order); a block belongs to one item.
 __global__ __launch_bounds__(EPI_THREADS) void k_epilogue(BatchDev B) {
     __shared__ double s_red[EPI_THREADS / WAVE][12];
     const int item = B.n_items == 1 ? 0 : B.epi_item[blockIdx.x];
     const ItemDev it = B.items[item];     // a copy, read before any store
     const TraceArgs& A = it.t;
     const int lb = blockIdx.x - it.epi_start;
-    const int r = lb * EPI_THREADS + threadIdx.x;
+    const int r = lb * EPI_THREADS + threadIdx.x;       // the kernel's original index
     const bool want_cam = it.grad_camera != nullptr;
     double part[12];
 #pragma unroll
     for (int e = 0; e < 12; ++e) part[e] = 0.0;
     if (r < A.N) {
-        const size_t n = (gp(A.rec) + r)->idx;
+        const size_t n = r;
         double gm[3] = {0.0, 0.0, 0.0};
         double gc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         double M0[3], Sig[6], S0[6];
@@ -52,11 +51,11 @@ __global__ __launch_bounds__(EPI_THREADS) void k_epilogue(BatchDev B) {
         if (ok) {
             double R[9];
             for (int e = 0; e < 9; ++e) R[e] = (double)it.cam.R[e];
-            const auto gM = gp(A.gM) + (size_t)r * 3;
+            const auto gM = gp(A.gM) + n * 3;
             const double g0 = gM[0], g1 = gM[1], g2 = gM[2];
             double G[9];
             {
-                const auto q = gp(A.gS) + (size_t)r * 6;
+                const auto q = gp(A.gS) + n * 6;
                 G[0] = q[0]; G[1] = q[1]; G[2] = q[2];
                 G[3] = q[1]; G[4] = q[3]; G[5] = q[4];
                 G[6] = q[2]; G[7] = q[4]; G[8] = q[5];
@@ -103,7 +102,7 @@ __global__ __launch_bounds__(EPI_THREADS) void k_epilogue(BatchDev B) {
         for (int d = 0; d < 3; ++d) gp(it.grad_means)[n * 3 + d] = (float)gm[d];
         for (int e = 0; e < 6; ++e) gp(it.grad_covs)[n * 6 + e] = (float)gc[e];
         const int C = A.C;
-        const auto ga = gp(A.gA) + (size_t)r * C;
+        const auto ga = gp(A.gA) + n * C;
         const auto go = gp(it.grad_attrs) + n * C;
         for (int c = 0; c < C; ++c) go[c] = ga[c];
     }

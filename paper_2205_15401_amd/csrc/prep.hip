@@ -112,6 +112,7 @@ __global__ __launch_bounds__(PREP_THREADS) void k_prep_records(BatchDev B, int t
     cr.tlo = INFINITY;
     cr.pad = 0;
     GeoRec g = {};
+    g.idx = n;
     if (!culled) {
         const CamDev& cam = it.cam;
         const double rad2 = it.t.rad2;

@@ -610,18 +610,25 @@ size_t bwd_lds_bytes(int hcap, int KB, int max_c) {
     return bwd_table_bytes(hcap, bwd_partial_values(max_c, KB)) + (size_t)TILE_THREADS * KB * sizeof(uint16_t);
 }
 
+// The original index of the kernel of a rank (the accumulators are kept in
+// original order, so the epilogue reads and writes every array in order).
+__device__ __forceinline__ size_t kernel_index(const TraceArgs& A, int rank) {
+    return (gp(A.geo) + rank)->idx;
+}
+
 // Add one kernel's partial sums to global memory: the 9 geometric values
-// (pass 0 only) and attribute channels c0 .. c0+nc-1.
-__device__ __forceinline__ void flush_values(const TraceArgs& A, int rank, const float* v, bool geom, int c0,
+// (pass 0 only) and attribute channels c0 .. c0+nc-1, at the kernel's
+// original index n.
+__device__ __forceinline__ void flush_values(const TraceArgs& A, size_t n, const float* v, bool geom, int c0,
                                              int nc) {
     // v: the 9 geometric values, then nc channels
     if (geom) {
 #pragma unroll
-        for (int q = 0; q < 3; ++q) global_add(&A.gM[(size_t)rank * 3 + q], v[q]);
+        for (int q = 0; q < 3; ++q) global_add(&A.gM[n * 3 + q], v[q]);
 #pragma unroll
-        for (int q = 0; q < 6; ++q) global_add(&A.gS[(size_t)rank * 6 + q], v[3 + q]);
+        for (int q = 0; q < 6; ++q) global_add(&A.gS[n * 6 + q], v[3 + q]);
     }
-    for (int q = 0; q < nc; ++q) global_add(&A.gA[(size_t)rank * A.C + c0 + q], v[9 + q]);
+    for (int q = 0; q < nc; ++q) global_add(&A.gA[n * A.C + c0 + q], v[9 + q]);
 }
 
 // Backward, pixel phase: per-pair scalars (dq, dl, da, W) into the scratch list.
@@ -862,14 +869,15 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
                 const size_t o = (size_t)k * S + P.q;
                 const int rank = rk[k];
                 const float4 sc = ld_f4(gp(A.bw) + o);
+                const GeoRec G = load_geo(gp(A.geo) + rank);
                 double out[9];
-                pair_chain(load_geo(gp(A.geo) + rank), P.u, P.v, (double)A.F, sc.x, sc.y + gp(A.bwl)[o], sc.z, out,
-                           gD);
+                pair_chain(G, P.u, P.v, (double)A.F, sc.x, sc.y + gp(A.bwl)[o], sc.z, out, gD);
+                const size_t n = G.idx;
 #pragma unroll
-                for (int e = 0; e < 3; ++e) global_add(&A.gM[(size_t)rank * 3 + e], (float)out[e]);
+                for (int e = 0; e < 3; ++e) global_add(&A.gM[n * 3 + e], (float)out[e]);
 #pragma unroll
-                for (int e = 0; e < 6; ++e) global_add(&A.gS[(size_t)rank * 6 + e], (float)out[3 + e]);
-                for (int c = 0; c < C; ++c) global_add(&A.gA[(size_t)rank * C + c], sc.w * gp(Gp)[c]);
+                for (int e = 0; e < 6; ++e) global_add(&A.gS[n * 6 + e], (float)out[3 + e]);
+                for (int c = 0; c < C; ++c) global_add(&A.gA[n * C + c], sc.w * gp(Gp)[c]);
             }
         }
     }
@@ -925,6 +933,7 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
 #pragma unroll
         for (int q = 0; q < RED_NV; ++q) acc[q] = 0.f;
         int cur = -1, nseg = 0;
+        size_t cur_n = 0;
         GeoRec G;
         s_hk[tid] = -1;
         s_tk[tid] = -1;
@@ -946,7 +955,7 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
                         for (int q = 0; q < RED_NV; ++q)
                             if (q >= v0 && q < nvs) s_tail[tid * nvs + q] = acc[q];
                     } else {                                           // complete run
-                        flush_values(A, cur, acc, geom, c0, nc);
+                        flush_values(A, cur_n, acc, geom, c0, nc);
                     }
                     ++nseg;
                 }
@@ -954,7 +963,12 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
 #pragma unroll
                 for (int q = 0; q < RED_NV; ++q) acc[q] = 0.f;
                 cur = r.rank;
-                if (geom) G = load_geo(gp(A.geo) + cur);
+                if (geom) {
+                    G = load_geo(gp(A.geo) + cur);
+                    cur_n = G.idx;
+                } else {
+                    cur_n = kernel_index(A, cur);
+                }
             }
             const int w = r.pt / WAVE, ln = r.pt % WAVE;
             const int row = ti0 + (w >> 1) * 8 + (ln >> 3), col = tj0 + (w & 1) * 8 + (ln & 7);
@@ -999,7 +1013,7 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
                     if (q >= v0 && q < nvs) sum[q] += s_head[t2 * nvs + q];
                 if (s_tk[t2] >= 0) break;                             // the run ends inside chunk t2
             }
-            flush_values(A, k, sum, geom, c0, nc);
+            flush_values(A, kernel_index(A, k), sum, geom, c0, nc);
         }
         __syncthreads();
     }

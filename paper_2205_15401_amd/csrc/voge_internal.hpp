@@ -54,8 +54,10 @@ static_assert(sizeof(TraceRec) == 96, "TraceRec is 96 bytes");
 struct __align__(8) GeoRec {
     double M[3];              // camera-space centre
     double S[6];              // camera-space inverse covariance xx, xy, xz, yy, yz, zz
+    uint32_t idx;             // original kernel index
+    uint32_t pad;
 };
-static_assert(sizeof(GeoRec) == 72, "GeoRec is 72 bytes");
+static_assert(sizeof(GeoRec) == 80, "GeoRec is 80 bytes");
 
 struct CamDev {               // camera as passed to kernels
     float R[9], T[3];
@@ -171,6 +173,8 @@ __device__ __forceinline__ GeoRec load_geo(gptr<const GeoRec> p) {
     for (int i = 0; i < 3; ++i) g.M[i] = p->M[i];
 #pragma unroll
     for (int i = 0; i < 6; ++i) g.S[i] = p->S[i];
+    g.idx = p->idx;
+    g.pad = 0;
     return g;
 }
 

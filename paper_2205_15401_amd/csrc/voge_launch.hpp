@@ -51,10 +51,10 @@ struct TraceArgs {
     int32_t* kept;
     // backward, and the sampler of Sec. 3.4 (Eq. 10)
     const float* grad_image;   // per-pixel map reduced onto the kernels: dL/dC, or phi when sampling
-    float* gA;                 // [N][C] attribute gradients in rank order (sampling: sum_p W phi, original order)
+    float* gA;                 // [N][C] attribute gradients (sampling: sum_p W phi), original kernel order
     float* gW;                 // [N] sampling: sum_p W, original order (shares gM's storage)
-    float* gM;                 // [N][3] camera-space centre gradients, rank order
-    float* gS;                 // [N][6] camera-space inverse-covariance gradients
+    float* gM;                 // [N][3] camera-space centre gradients, original order
+    float* gS;                 // [N][6] camera-space inverse-covariance gradients, original order
     double* tileD;             // [n_tiles][3] per-tile sums of dL/dD'
     float4* bw;                // per-slot backward scalars (dq, dl m-side, da, W), slot-major like the lists
     float* bwl;                // per-slot k-side part of dL/dl, slot-major
