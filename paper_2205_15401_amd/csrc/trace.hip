@@ -159,30 +159,42 @@ __device__ __forceinline__ double key_upper_l(uint64_t key) {
     return __longlong_as_double((long long)(key | RANK_MASK));
 }
 
-// Insertion of a key into the sorted K-buffer (a compare-exchange network)
-// over slots 0..ub only, ub being a wave-uniform bound of the filled slots:
-// slots past a lane's fill count hold the empty key, so the new key settles
-// at or before the first of them.  Groups of four slots under uniform
-// branches.  CAPTURE: returns the new key of slot km1 (wave-uniform) if the
-// network reached it, else the empty key; a lane that holds more than km1
-// keys after the insertion always has it reached (km1 <= its old count <= ub).
-template <int KB, bool CAPTURE>
-__device__ __forceinline__ uint64_t kbuf_insert_upto(uint64_t (&key)[KB], uint64_t nk, int ub, int km1) {
-    uint64_t kk = ~0ull;
+// The K-buffer of a pixel: its kept keys in slots 0 .. n-1, in no order
+// (what uses the kept set -- the transmittance sums, the blend and the
+// backward -- does not depend on the order).  Slot loops run over groups of
+// four under wave-uniform branches up to a uniform bound of the fill counts.
+
+// Write key nk into slot t (lanes with ins): a lane holding n < K keys
+// appends at t = n, a full lane overwrites the slot of its largest key.  One
+// in-place pass over slots 0 .. lim (lim wave-uniform: the largest fill
+// count, or K-1 when a full lane inserts).
+template <int KB>
+__device__ __forceinline__ void kbuf_put(uint64_t (&key)[KB], uint64_t nk, bool ins, int t, int lim) {
 #pragma unroll
     for (int s0 = 0; s0 < KB; s0 += 4) {
-        if (s0 <= ub) {
+        if (s0 <= lim) {
+#pragma unroll
+            for (int s = s0; s < s0 + 4 && s < KB; ++s) key[s] = (ins && s == t) ? nk : key[s];
+        }
+    }
+}
+
+// The largest of the K keys in slots 0 .. K-1 (a full buffer) and its slot.
+template <int KB>
+__device__ __forceinline__ void kbuf_max(const uint64_t (&key)[KB], int K, uint64_t& mx, int& ms) {
+    mx = 0;
+    ms = 0;
+#pragma unroll
+    for (int s0 = 0; s0 < KB; s0 += 4) {
+        if (s0 < K) {
 #pragma unroll
             for (int s = s0; s < s0 + 4 && s < KB; ++s) {
-                const uint64_t cur = key[s];
-                const bool lt = nk < cur;
-                key[s] = lt ? nk : cur;
-                nk = lt ? cur : nk;
-                if (CAPTURE && s == km1) kk = key[s];
+                const bool gt = s < K && key[s] > mx;
+                mx = gt ? key[s] : mx;
+                ms = gt ? s : ms;
             }
         }
     }
-    return kk;
 }
 
 // Block -> tile.  Workgroups are dealt round-robin to the 8 XCDs (block b
@@ -213,7 +225,7 @@ __device__ __forceinline__ int wave_max_keff(int keff) {
 // records come through the scalar cache, the next candidate's while the
 // current one is inserted; nothing in the candidate loop touches LDS, so
 // waiting for the current record never waits for anything else.
-template <int KB, bool KFULL>
+template <int KB>
 __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
     const int tid = threadIdx.x, lane = tid % WAVE;
     const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);   // uniform in the wave
@@ -226,9 +238,10 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
     uint64_t key[KB];
 #pragma unroll
     for (int s = 0; s < KB; ++s) key[s] = ~0ull;
-    uint64_t kth = ~0ull;                        // the K-th smallest key so far
-    int nkey = 0;                                // filled slots (saturates at KB)
+    uint64_t kth = ~0ull;                        // the largest kept key once K are kept
+    int nkey = 0;                                // kept keys (at most K)
     int ub = 0;                                  // the wave's largest nkey (uniform)
+    int kslot = 0;                               // the slot of kth
     bool done = !P.valid;
     const auto cull = gp(A.cull);
     CullRec nxt;
@@ -263,13 +276,20 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
                 __builtin_amdgcn_sched_barrier(0);
                 const TraceRec Rn = load_rec(crec + rank_n);
                 if (__any(ins)) {
-                    // the wave's largest fill count grows by one when a lane at it inserts
-                    const bool grow = ub < KB && __any(ins && nkey == ub);
-                    if (ins) {
-                        // KFULL (K = KB): the K-th key sits in the last slot
-                        const uint64_t kk = kbuf_insert_upto<KB, !KFULL>(key, nk, ub, A.K - 1);
-                        nkey = min(nkey + 1, KB);
-                        kth = nkey >= A.K ? (KFULL ? key[KB - 1] : kk) : ~0ull;
+                    // the wave's largest fill count grows by one when a lane at it appends
+                    const bool grow = __any(ins && nkey == ub && nkey < A.K);
+                    const int lim = __any(ins && nkey >= A.K) ? A.K - 1 : ub;
+                    kbuf_put<KB>(key, nk, ins, nkey < A.K ? nkey : kslot, lim);
+                    if (ins && nkey < A.K) ++nkey;
+                    // the largest key (and its slot) of every lane that is full now
+                    if (__any(ins && nkey >= A.K)) {
+                        uint64_t mx;
+                        int ms;
+                        kbuf_max<KB>(key, A.K, mx, ms);
+                        if (ins && nkey >= A.K) {
+                            kth = mx;
+                            kslot = ms;
+                        }
                     }
                     ub += grow ? 1 : 0;
                 }
@@ -518,7 +538,20 @@ __device__ __forceinline__ void blend_body(const TraceArgs& A, int tile, unsigne
     }
     if (A.wsum) gp(A.wsum)[p] = ws;
     if (A.kept) {
-        for (int s = 0; s < A.K; ++s) gp(A.kept)[p * A.K + s] = s < keff ? gp(A.kl_i)[(size_t)s * S + P.q] : -1;
+        // the kept indices in ascending depth (the list itself is unordered):
+        // slot k goes to the number of kept kernels nearer than it (equal
+        // depths in slot order)
+        const auto kp = gp(A.kept) + p * A.K;
+        for (int s = keff; s < A.K; ++s) kp[s] = -1;
+        for (int k = 0; k < keff; ++k) {
+            const double l = pl[(size_t)k * S];
+            int pos = 0;
+            for (int m = 0; m < keff; ++m) {
+                const double lm = pl[(size_t)m * S];
+                pos += (lm < l || (lm == l && m < k)) ? 1 : 0;
+            }
+            kp[pos] = gp(A.kl_i)[(size_t)k * S + P.q];
+        }
     }
 }
 
@@ -1152,10 +1185,7 @@ template <int KB>
 __global__ __launch_bounds__(TILE_THREADS, select_waves<KB>()) void k_select(GroupDev g) {
     int tile;
     const TraceArgs A = item_view(g, tile);
-    if (A.K == KB)
-        select_body<KB, true>(A, tile);
-    else
-        select_body<KB, false>(A, tile);
+    select_body<KB>(A, tile);
 }
 
 template <int KB>
