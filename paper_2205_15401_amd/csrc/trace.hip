@@ -164,17 +164,18 @@ __device__ __forceinline__ double key_upper_l(uint64_t key) {
 // backward -- does not depend on the order).  Slot loops run over groups of
 // four under wave-uniform branches up to a uniform bound of the fill counts.
 
-// Write key nk into slot t (lanes with ins): a lane holding n < K keys
-// appends at t = n, a full lane overwrites the slot of its largest key.  One
-// in-place pass over slots 0 .. lim (lim wave-uniform: the largest fill
-// count, or K-1 when a full lane inserts).
+// Write key nk into slot t (t = -1: this lane inserts nothing): a lane
+// holding n < K keys appends at t = n, a full lane overwrites the slot of its
+// largest key.  One in-place pass over slots 0 .. lim (lim wave-uniform: the
+// largest fill count, or K-1 when a full lane inserts), one compare and two
+// selects per slot.
 template <int KB>
-__device__ __forceinline__ void kbuf_put(uint64_t (&key)[KB], uint64_t nk, bool ins, int t, int lim) {
+__device__ __forceinline__ void kbuf_put(uint64_t (&key)[KB], uint64_t nk, int t, int lim) {
 #pragma unroll
     for (int s0 = 0; s0 < KB; s0 += 4) {
         if (s0 <= lim) {
 #pragma unroll
-            for (int s = s0; s < s0 + 4 && s < KB; ++s) key[s] = (ins && s == t) ? nk : key[s];
+            for (int s = s0; s < s0 + 4 && s < KB; ++s) key[s] = s == t ? nk : key[s];
         }
     }
 }
@@ -224,9 +225,18 @@ __device__ __forceinline__ int wave_max_keff(int keff) {
 // order with scalar bit scans, and traced one after the other.  Their trace
 // records come through the scalar cache, the next candidate's while the
 // current one is inserted; nothing in the candidate loop touches LDS, so
-// waiting for the current record never waits for anything else.
+// waiting for the current record never waits for anything else.  Per-lane
+// decisions stay lane masks, combined with bitwise operators and wave votes
+// on the masks rather than branches: the loop is bound by instruction issue,
+// and exec-mask bookkeeping had cost as many scalar instructions as the
+// trace's vector ones.
+// Cull steps loaded ahead in select (one at the deepest K-buffer, whose
+// registers are all taken by the keys).
+__host__ __device__ constexpr int cull_ahead(int KB) { return KB >= 64 ? 1 : 3; }
+
 template <int KB>
 __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
+    constexpr int CULL_AHEAD = cull_ahead(KB);
     const int tid = threadIdx.x, lane = tid % WAVE;
     const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);   // uniform in the wave
     const int ntx = (A.W + TILE - 1) / TILE;
@@ -243,53 +253,47 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
     int ub = 0;                                  // the wave's largest nkey (uniform)
     int kslot = 0;                               // the slot of kth
     bool done = !P.valid;
-    const auto cull = gp(A.cull);
-    CullRec nxt;
-    if (lane < A.N) nxt = load_cull(cull + lane);
-    for (int base = 0; base < A.N; base += WAVE) {
-        const int r = base + lane;
-        const CullRec c = nxt;
-        if (r + WAVE < A.N) nxt = load_cull(cull + r + WAVE);        // prefetch the next step
-        const bool hit = r < A.N && c.i0 <= bi0 + 7 && c.i1 >= bi0 && c.j0 <= bj0 + 7 && c.j1 >= bj0;
-        uint64_t mm = __ballot(hit);             // this step's candidates, one bit per record
+    // One step: the records base .. base+63 whose boxes meet the block
+    // (hit); returns true once the block is done.
+    auto step = [&](const int base, const bool hit) -> bool {
+        uint64_t mm = wave_ballot(hit);          // this step's candidates, one bit per record
         if (mm != 0) {
             int rank = base + (int)__builtin_ctzll(mm);
             mm &= mm - 1;
             TraceRec R = load_rec(crec + rank);
             for (;;) {
-                if (__all(done)) break;
-                if (!done && kth != ~0ull && (double)R.tlo > key_upper_l(kth)) done = true;
-                bool ins = false;
-                uint64_t nk = 0;
-                if (!done) {
-                    double l, q2, a;
-                    trace_one(R, P.u, P.v, l, q2, a);
-                    if (q2 < A.rad2 && l > 0.0) {
-                        nk = ((uint64_t)__double_as_longlong(l) & ~RANK_MASK) | (uint64_t)rank;
-                        ins = nk < kth;
-                    }
+                // a lane's early exit needs a full buffer (ub < K: none is, and
+                // done has kept its initial value)
+                if (ub >= A.K) {
+                    if (wave_all(done)) break;
+                    done = done | ((kth != ~0ull) & ((double)R.tlo > key_upper_l(kth)));
                 }
+                // every lane traces (a branch around the trace would cost more
+                // than the finished lanes' share of it)
+                double l, q2, a;
+                trace_one(R, P.u, P.v, l, q2, a);
+                const uint64_t nk = ((uint64_t)__double_as_longlong(l) & ~RANK_MASK) | (uint64_t)rank;
+                const bool ins = !done & (q2 < A.rad2) & (l > 0.0) & (nk < kth);
                 // the next candidate's record is in flight while this one is inserted
                 const bool more = mm != 0;
                 const int rank_n = more ? base + (int)__builtin_ctzll(mm) : rank;
                 mm &= mm - 1;
                 __builtin_amdgcn_sched_barrier(0);
                 const TraceRec Rn = load_rec(crec + rank_n);
-                if (__any(ins)) {
+                if (wave_any(ins)) {
                     // the wave's largest fill count grows by one when a lane at it appends
-                    const bool grow = __any(ins && nkey == ub && nkey < A.K);
-                    const int lim = __any(ins && nkey >= A.K) ? A.K - 1 : ub;
-                    kbuf_put<KB>(key, nk, ins, nkey < A.K ? nkey : kslot, lim);
-                    if (ins && nkey < A.K) ++nkey;
+                    const bool grow = wave_any(ins & (nkey == ub) & (nkey < A.K));
+                    const int lim = wave_any(ins & (nkey >= A.K)) ? A.K - 1 : ub;
+                    kbuf_put<KB>(key, nk, !ins ? -1 : nkey < A.K ? nkey : kslot, lim);
+                    nkey += (ins & (nkey < A.K)) ? 1 : 0;
                     // the largest key (and its slot) of every lane that is full now
-                    if (__any(ins && nkey >= A.K)) {
+                    if (wave_any(ins & (nkey >= A.K))) {
                         uint64_t mx;
                         int ms;
                         kbuf_max<KB>(key, A.K, mx, ms);
-                        if (ins && nkey >= A.K) {
-                            kth = mx;
-                            kslot = ms;
-                        }
+                        const bool full = ins & (nkey >= A.K);
+                        kth = full ? mx : kth;
+                        kslot = full ? ms : kslot;
                     }
                     ub += grow ? 1 : 0;
                 }
@@ -299,14 +303,44 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
             }
         }
         // the block is done when every pixel is, or holds K kernels nearer
-        // than the next record's depth bound (lane 0 prefetched that record)
+        // than the next record's depth bound (possible once a buffer is full)
         const int nb = base + WAVE;
         bool fin = done;
-        if (!fin && nb < A.N) {
-            const float next_tlo = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(nxt.tlo)));
-            fin = kth != ~0ull && (double)next_tlo > key_upper_l(kth);
+        if (ub >= A.K && nb < A.N) {
+            const float next_tlo = crec[nb].tlo;
+            fin = fin | ((kth != ~0ull) & ((double)next_tlo > key_upper_l(kth)));
         }
-        if (__all(fin)) break;
+        return wave_all(fin);
+    };
+
+    // The screen boxes of the next CULL_AHEAD steps are in flight (a step
+    // with no candidate is a few instructions, far shorter than a load).  The
+    // loop is unrolled by CULL_AHEAD so that each box keeps its registers and
+    // is reloaded right after its use, and every lane loads (lanes past the
+    // last record reload that record, and r < N rejects them), so that
+    // waiting for the oldest load leaves the younger ones in flight.
+    const int n_scan = wave_all(done) ? 0 : A.N;   // a block wholly outside the image scans nothing
+    const int last = A.N - 1;
+    const auto cull = gp(A.cull);
+    CullBox ahead[CULL_AHEAD];
+    if (n_scan > 0) {
+#pragma unroll
+        for (int d = 0; d < CULL_AHEAD; ++d) ahead[d] = load_box(cull + min(lane + d * WAVE, last));
+    }
+    bool stop = n_scan == 0;
+    for (int base0 = 0; !stop; base0 += CULL_AHEAD * WAVE) {
+#pragma unroll
+        for (int d = 0; d < CULL_AHEAD; ++d) {
+            const int base = base0 + d * WAVE, r = base + lane;
+            const CullBox c = ahead[d];
+            ahead[d] = load_box(cull + min(r + CULL_AHEAD * WAVE, last));   // on every path
+            if (!stop && base < n_scan) {
+                const bool hit = (r < A.N) & (c.i0 <= bi0 + 7) & (c.i1 >= bi0) & (c.j0 <= bj0 + 7) & (c.j1 >= bj0);
+                stop = step(base, hit);
+            } else {
+                stop = true;
+            }
+        }
     }
 
     // write the kept list: FP64 depth, e^q, sqrt(a), rank, original index

@@ -5,7 +5,7 @@
 // written by the prep kernels; the items' slices are concatenated):
 //   CullRec  cull[N]  16 B  screen bbox + depth-bucket floor, in depth order
 //   TraceRec rec[N]   96 B  per-kernel ray-tracing coefficients, same order
-//   GeoRec   geo[N]   72 B  camera-space centre and inverse covariance (backward)
+//   GeoRec   geo[N]   80 B  camera-space centre and inverse covariance (backward)
 // Within an item the order is ascending in the lower bound of the ray
 // parameter of the kernel's eta-ellipsoid (bucketed), so a block of pixels
 // can stop scanning once every pixel holds K kernels that are all nearer
@@ -113,6 +113,12 @@ __device__ __forceinline__ void global_add(float* p, float v) {
     __builtin_amdgcn_global_atomic_fadd_f32(gp(p), v);
 }
 
+// Wave votes over the active lanes, taken on the lane mask itself (no
+// round trip of the predicate through a vector register).
+__device__ __forceinline__ uint64_t wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+__device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
+__device__ __forceinline__ bool wave_all(bool p) { return __builtin_amdgcn_ballot_w64(!p) == 0; }
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
     const int lane = __lane_id();
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -154,6 +160,20 @@ __device__ __forceinline__ void rotate_sym(const double R[9], const double A[6],
     auto e = [&](int r, int c) { return RA[3 * r] * R[3 * c] + RA[3 * r + 1] * R[3 * c + 1] + RA[3 * r + 2] * R[3 * c + 2]; };
     B[0] = e(0, 0); B[1] = e(0, 1); B[2] = e(0, 2);
     B[3] = e(1, 1); B[4] = e(1, 2); B[5] = e(2, 2);
+}
+
+// The screen box of a cull record alone (its first 8 bytes).
+struct CullBox {
+    int16_t i0, i1, j0, j1;
+};
+
+__device__ __forceinline__ CullBox load_box(gptr<const CullRec> p) {
+    CullBox c;
+    c.i0 = p->i0;
+    c.i1 = p->i1;
+    c.j0 = p->j0;
+    c.j1 = p->j1;
+    return c;
 }
 
 __device__ __forceinline__ CullRec load_cull(gptr<const CullRec> p) {
