@@ -660,6 +660,13 @@ __device__ __forceinline__ void pair_chain(const GeoRec& G, double D0, double D1
 // that the partial sums and the pair indices fit 64 KB of LDS.
 __host__ __device__ constexpr int red_ch(int KB) { return KB >= 64 ? 4 : 8; }
 
+// Whether the reduction stages the tile's upstream gradient in LDS (4
+// channels per pixel slot): with at most 4 channels and all but the deepest
+// K-buffer, where the 4 KB keep three workgroups per CU.  Wider gradients
+// are read from global memory pair by pair.
+constexpr int GRAD_STAGE_CH = 4;
+__host__ __device__ constexpr bool red_stage_grad(int KB, int max_c) { return KB < 64 && max_c <= GRAD_STAGE_CH; }
+
 // LDS of k_bwd_red: the hash table (keys, pair counts, offsets and the
 // compact list of used entries, hcap ints each), later reused for the
 // reduction's partial sums (head and tail runs of every lane, nv values
@@ -674,7 +681,8 @@ __host__ __device__ inline size_t bwd_table_bytes(int hcap, int nv) {
 }
 
 size_t bwd_lds_bytes(int hcap, int KB, int max_c) {
-    return bwd_table_bytes(hcap, bwd_partial_values(max_c, KB)) + (size_t)TILE_THREADS * KB * sizeof(uint16_t);
+    const size_t grad = red_stage_grad(KB, max_c) ? (size_t)TILE_THREADS * GRAD_STAGE_CH * sizeof(float) : 0;
+    return bwd_table_bytes(hcap, bwd_partial_values(max_c, KB)) + (size_t)TILE_THREADS * KB * sizeof(uint16_t) + grad;
 }
 
 // The original index of the kernel of a rank (the accumulators are kept in
@@ -838,7 +846,7 @@ __device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile) {
 
 // Backward, tile phase: group the tile's pairs by kernel and reduce them.
 template <int KB>
-__device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int tile, unsigned char* smem) {
+__device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, bool stage, int tile, unsigned char* smem) {
     __shared__ double s_red[TILE_THREADS / WAVE][3];
     __shared__ int s_scan[TILE_THREADS];
     __shared__ int s_scan2[TILE_THREADS];
@@ -864,6 +872,9 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
     constexpr int RED_NV = 9 + RED_CH;           // values per partial sum (registers)
     const int nvs = bwd_partial_values(C, KB);   // values per partial sum in LDS
     uint16_t* s_pair = reinterpret_cast<uint16_t*>(smem + bwd_table_bytes(hcap, nvs));
+    // the tile's upstream gradient (stage: C <= GRAD_STAGE_CH, one pass),
+    // GRAD_STAGE_CH values per pixel slot
+    float* s_g = reinterpret_cast<float*>(s_pair + (size_t)TILE_THREADS * KB);
     __syncthreads();   // table initialised
 
     // counting sort of the tile's pairs by kernel; sp[k] = table slot << 16 | position.
@@ -1004,6 +1015,15 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
         GeoRec G;
         s_hk[tid] = -1;
         s_tk[tid] = -1;
+        if (stage) {
+            // the channels of the lane's own pixel (zeros past channel C and
+            // outside the image): the pairs below read them from LDS
+            float g[GRAD_STAGE_CH];
+#pragma unroll
+            for (int q = 0; q < GRAD_STAGE_CH; ++q) g[q] = (P.valid && q < nc) ? gp(Gp)[q] : 0.f;
+            reinterpret_cast<float4*>(s_g)[tid] = make_float4(g[0], g[1], g[2], g[3]);
+            __syncthreads();
+        }
         Pair nxt = j0 < j1 ? load_pair(j0, geom) : Pair{};
         for (int j = j0; j <= j1; ++j) {
             const bool end = j == j1;
@@ -1046,18 +1066,26 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
 #pragma unroll
                 for (int q = 0; q < 9; ++q) acc[q] += (float)out[q];
             }
-            const auto Gq = gp(A.grad_image) + ((size_t)row * A.W + col) * C + c0;
-            if (nc == RED_CH && (C & 3) == 0) {
-#pragma unroll
-                for (int q = 0; q < RED_CH; q += 4) {
-                    const float4 g4 = ld_f4((gptr<const float4>)(Gq + q));
-                    acc[9 + q] = fmaf(r.w, g4.x, acc[9 + q]);
-                    acc[10 + q] = fmaf(r.w, g4.y, acc[10 + q]);
-                    acc[11 + q] = fmaf(r.w, g4.z, acc[11 + q]);
-                    acc[12 + q] = fmaf(r.w, g4.w, acc[12 + q]);
-                }
+            if (stage) {
+                const float4 g4 = reinterpret_cast<const float4*>(s_g)[r.pt];
+                acc[9] = fmaf(r.w, g4.x, acc[9]);
+                acc[10] = fmaf(r.w, g4.y, acc[10]);
+                acc[11] = fmaf(r.w, g4.z, acc[11]);
+                acc[12] = fmaf(r.w, g4.w, acc[12]);
             } else {
-                for (int q = 0; q < nc; ++q) acc[9 + q] = fmaf(r.w, Gq[q], acc[9 + q]);
+                const auto Gq = gp(A.grad_image) + ((size_t)row * A.W + col) * C + c0;
+                if (nc == RED_CH && (C & 3) == 0) {
+#pragma unroll
+                    for (int q = 0; q < RED_CH; q += 4) {
+                        const float4 g4 = ld_f4((gptr<const float4>)(Gq + q));
+                        acc[9 + q] = fmaf(r.w, g4.x, acc[9 + q]);
+                        acc[10 + q] = fmaf(r.w, g4.y, acc[10 + q]);
+                        acc[11 + q] = fmaf(r.w, g4.z, acc[11 + q]);
+                        acc[12 + q] = fmaf(r.w, g4.w, acc[12 + q]);
+                    }
+                } else {
+                    for (int q = 0; q < nc; ++q) acc[9 + q] = fmaf(r.w, Gq[q], acc[9 + q]);
+                }
             }
         }
         __syncthreads();
@@ -1245,11 +1273,11 @@ __global__ __launch_bounds__(TILE_THREADS) void k_bwd_pix(GroupDev g) {
 }
 
 template <int KB>
-__global__ __launch_bounds__(TILE_THREADS) void k_bwd_red(GroupDev g, int hcap) {
+__global__ __launch_bounds__(TILE_THREADS) void k_bwd_red(GroupDev g, int hcap, int stage_grad) {
     extern __shared__ __align__(16) unsigned char smem[];
     int tile;
     const TraceArgs A = item_view(g, tile);
-    bwd_red_body<KB>(A, hcap, tile, smem);
+    bwd_red_body<KB>(A, hcap, stage_grad != 0, tile, smem);
 }
 
 // Diagnostics: the device Phi on an array.
@@ -1284,7 +1312,8 @@ static hipError_t run_kb(int which, const GroupDev& g, hipStream_t s, int max_c 
         hipLaunchKernelGGL(k_bwd_pix<KB>, dim3(nt), dim3(TILE_THREADS), 0, s, g);
     } else if (which == 3) {
         const int hcap = table_capacity(0);
-        hipLaunchKernelGGL(k_bwd_red<KB>, dim3(nt), dim3(TILE_THREADS), bwd_lds_bytes(hcap, KB, max_c), s, g, hcap);
+        hipLaunchKernelGGL(k_bwd_red<KB>, dim3(nt), dim3(TILE_THREADS), bwd_lds_bytes(hcap, KB, max_c), s, g, hcap,
+                           red_stage_grad(KB, max_c) ? 1 : 0);
     } else {
         hipLaunchKernelGGL(k_blend_sample<KB>, dim3(nt), dim3(TILE_THREADS), sample_lds_bytes(max_c), s, g);
     }
