@@ -549,6 +549,33 @@ __device__ __forceinline__ void blend_body(const TraceArgs& A, int tile, unsigne
                 }
                 st_f4(o4 + c, acc);
             }
+        } else if (A.C == 3) {
+            // rows of three channels: one three-dword load per kept kernel
+            const auto at = gp(A.attrs);
+            const auto img = gp(A.image);
+            float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+#pragma unroll
+            for (int k0 = 0; k0 < KB; k0 += 2) {
+                if (k0 < kmax) {
+                    float r[2][3];
+#pragma unroll
+                    for (int k = k0; k < k0 + 2 && k < KB; ++k) {
+                        const auto row = at + (size_t)ik[k] * 3;
+                        r[k - k0][0] = row[0];
+                        r[k - k0][1] = row[1];
+                        r[k - k0][2] = row[2];
+                    }
+#pragma unroll
+                    for (int k = k0; k < k0 + 2 && k < KB; ++k) {
+                        a0 = fmaf(Wt[k], r[k - k0][0], a0);
+                        a1 = fmaf(Wt[k], r[k - k0][1], a1);
+                        a2 = fmaf(Wt[k], r[k - k0][2], a2);
+                    }
+                }
+            }
+            img[p * 3] = a0;
+            img[p * 3 + 1] = a1;
+            img[p * 3 + 2] = a2;
         } else {
             const auto at = gp(A.attrs);
             const auto img = gp(A.image);
@@ -765,6 +792,26 @@ __device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile) {
                             g[k] = fmaf(Gc.x, a[k - k0].x,
                                         fmaf(Gc.y, a[k - k0].y, fmaf(Gc.z, a[k - k0].z, fmaf(Gc.w, a[k - k0].w, g[k]))));
                     }
+                }
+            }
+        } else if (C == 3) {
+            // rows of three channels: one three-dword load per kept kernel
+            const auto at = gp(A.attrs);
+            const float G0 = keff > 0 ? Gp[0] : 0.f, G1 = keff > 0 ? Gp[1] : 0.f, G2 = keff > 0 ? Gp[2] : 0.f;
+#pragma unroll
+            for (int k0 = 0; k0 < KB; k0 += 2) {
+                if (k0 < kmax) {
+                    float r[2][3];
+#pragma unroll
+                    for (int k = k0; k < k0 + 2 && k < KB; ++k) {
+                        const auto row = at + (size_t)ik[k] * 3;
+                        r[k - k0][0] = row[0];
+                        r[k - k0][1] = row[1];
+                        r[k - k0][2] = row[2];
+                    }
+#pragma unroll
+                    for (int k = k0; k < k0 + 2 && k < KB; ++k)
+                        g[k] = fmaf(G0, r[k - k0][0], fmaf(G1, r[k - k0][1], fmaf(G2, r[k - k0][2], g[k])));
                 }
             }
         } else {
