@@ -388,6 +388,35 @@ def test_channel_counts_through_both_attribute_paths():
         check_item(batch, i, scenes[si], cam, K, eta, grads[i], pixs[i], frefs[i])
 
 
+def test_gradient_staging_on_and_off_match_the_oracle():
+    """The backward's tile reduction stages the upstream gradient in LDS when
+    every item of a K-buffer group has at most 4 channels, and reads it from
+    global memory otherwise: the same 3-channel item alone (staged) and next
+    to a 5-channel item with the same K (not staged) both match the oracle
+    and each other."""
+    rng = np.random.default_rng(77)
+    three = S.torus_scene(rng, 1800, 3, centre=(0.0, 0.0, 3.0))
+    five = S.cloud_scene(rng, 900, 5)
+    cam3 = S.identity_camera(56, focal=60.0, height=40)
+    cam5 = S.identity_camera(32)
+    alone, g_a, p_a, f_a, _ = run_checked_batch([three], [(0, cam3, 20, 0.01)], rng, n_pix=100_000)
+    check_item(alone, 0, three, cam3, 20, 0.01, g_a[0], p_a[0], f_a[0])
+    dev = torch.device("cuda:0")
+    mixed = R.Batch([dev_scene(three), dev_scene(five)],
+                    [(0, R.camera_struct(cam3), 20, 0.01), (1, R.camera_struct(cam5), 20, 0.01)], dev,
+                    backward=True, with_wsum=True, with_kept=True, with_camera=True)
+    G5, _, _ = sparse_gradient(rng, five, cam5, 20, 0.01, 100_000)
+    mixed.set_grad_image(0, torch.from_numpy(g_a[0]))
+    mixed.set_grad_image(1, torch.from_numpy(G5))
+    mixed.run(forward=True, backward=True)
+    torch.cuda.synchronize()
+    check_item(mixed, 0, three, cam3, 20, 0.01, g_a[0], p_a[0], f_a[0])
+    bref = grad_floors(three, cam3, 20, 0.01, g_a[0])
+    assert_grads_close([(alone.grad_means[0], mixed.grad_means[0]), (alone.grad_covs[0], mixed.grad_covs[0]),
+                        (alone.grad_attrs[0], mixed.grad_attrs[0]), (alone.grad_cameras[0], mixed.grad_cameras[0])],
+                       bref, "staged vs global upstream gradient")
+
+
 def test_device_calls_reject_bad_workspaces_and_pointers():
     dev = torch.device("cuda:0")
     ctx = R.context(dev)
