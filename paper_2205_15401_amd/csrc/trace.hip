@@ -17,7 +17,8 @@
 //     and keeps e^q > eta, l > 0, the K smallest l (Sec. 3.3; App. A.3).
 //     A candidate is a 64-bit key: the bits of l (a positive double) with the
 //     low 24 bits replaced by the kernel's rank, so one unsigned compare
-//     orders by (l, rank) and the K-buffer is a register insertion network.
+//     orders by (l, rank); the K-buffer holds the kept keys in registers, in
+//     no order (a full buffer's largest key is the one a nearer key replaces).
 //     A pixel is done once its K-th entry is nearer than the next record's
 //     depth floor; the wave stops when all its pixels are done.
 //   k_blend -- E_k = sum_m e^{q_m} Phi((l_k - l_m) sqrt(a_m)) (Eq. 7 at
@@ -698,7 +699,8 @@ __host__ __device__ constexpr bool red_stage_grad(int KB, int max_c) { return KB
 // compact list of used entries, hcap ints each), later reused for the
 // reduction's partial sums (head and tail runs of every lane, nv values
 // each: the 9 geometric ones and one pass's channels); then the tile's pairs
-// in kernel order as 16-bit indices (256 * KB of them).
+// in kernel order as 16-bit indices (256 * KB of them); then, when staged,
+// the tile's upstream gradient (GRAD_STAGE_CH floats per pixel slot).
 __host__ __device__ inline int bwd_partial_values(int C, int KB) { return 9 + (C < red_ch(KB) ? C : red_ch(KB)); }
 
 __host__ __device__ inline size_t bwd_table_bytes(int hcap, int nv) {
