@@ -107,9 +107,9 @@ def _lib():
             I = ctypes.c_int
             L = ctypes.c_int64
             Dbl = ctypes.c_double
-            lib.oracle_forward.argtypes = [P, P, P, I, I, P, I, I, Dbl, I, P, L, I, P, P, P, P, P, P, P]
+            lib.oracle_forward.argtypes = [P, P, P, I, I, P, I, I, Dbl, I, P, L, I, P, P, P, P, P, P, P, P]
             lib.oracle_forward.restype = I
-            lib.oracle_backward.argtypes = [P, P, P, I, I, P, I, I, Dbl, I, P, L, P, I, P, P, P, P, P, P, P, P, I]
+            lib.oracle_backward.argtypes = [P, P, P, I, I, P, I, I, Dbl, I, P, L, P, I, P, P, P, P, P, P, P, P, I, P]
             lib.oracle_backward.restype = I
             lib.oracle_quadrature.argtypes = [P, P, I, P, I, I, Dbl, I, P, L, I, I, P, P, P]
             lib.oracle_quadrature.restype = I
@@ -155,17 +155,30 @@ class ForwardResult:
         return (self.kept_idx >= 0).sum(axis=1)
 
 
+def _given(given, n: int, K: int):
+    if given is None:
+        return None
+    g = np.ascontiguousarray(np.asarray(given, np.int32))
+    if g.shape != (n, K):
+        raise ValueError(f"given kept sets must be ({n}, {K}), got {g.shape}")
+    return g
+
+
 def forward(means, covs, attrs, cam_vec, H: int, W: int, K: int, eta: float = 0.01,
-            pixels: Optional[Sequence[int]] = None, threads: int = 0) -> ForwardResult:
-    """Render the given pixels (linear i*W + j; None = every pixel, row-major)."""
+            pixels: Optional[Sequence[int]] = None, threads: int = 0, given=None) -> ForwardResult:
+    """Render the given pixels (linear i*W + j; None = every pixel, row-major).
+    given: optional (n_pix, K) kept sets chosen elsewhere (-1 padded); the
+    selection (step 4) is then skipped and the blend runs on exactly those
+    sets (n_pass = -1, flags = 0)."""
     m, c, a, cv = _f64(means), _f64(covs), _f64(attrs), _f64(cam_vec)
     N, C = m.shape[0], a.shape[1]
     assert c.shape == (N, 6) and a.shape[0] == N and cv.size == 15
     pix, n = _pix(pixels, H, W)
+    gv = _given(given, n, K)
     r = ForwardResult(n, C, K)
     rc = _lib().oracle_forward(_ptr(m), _ptr(c), _ptr(a), N, C, _ptr(cv), H, W, float(eta), K,
                                _ptr(pix), n, threads, _ptr(r.image), _ptr(r.wsum), _ptr(r.absum),
-                               _ptr(r.kept_idx), _ptr(r.kept_rec), _ptr(r.n_pass), _ptr(r.flags))
+                               _ptr(r.kept_idx), _ptr(r.kept_rec), _ptr(r.n_pass), _ptr(r.flags), _ptr(gv))
     if rc < 0:
         raise ValueError("oracle_forward: bad arguments")
     r.n_invalid = rc
@@ -190,21 +203,24 @@ BLOCK_RHO = 2    # ablation: no gradient through the factor e^{q_k} of Eq. 8
 
 
 def backward(means, covs, attrs, cam_vec, H: int, W: int, K: int, grad, eta: float = 0.01,
-             pixels: Optional[Sequence[int]] = None, threads: int = 0, mode: int = 0) -> BackwardResult:
+             pixels: Optional[Sequence[int]] = None, threads: int = 0, mode: int = 0,
+             given=None) -> BackwardResult:
     """Gradients of sum_p <grad_p, C_p> over the given pixels (grad is
     (n_pix, C), or (H, W, C) when pixels is None).  mode: 0, or BLOCK_T and/or
     BLOCK_RHO, the gradient ablations of the paper's pose-estimation ablation
-    table ("w/o grad T(r)" and "w/o grad rho(r)")."""
+    table ("w/o grad T(r)" and "w/o grad rho(r)").  given: optional (n_pix, K)
+    kept sets, as for forward()."""
     m, c, a, cv = _f64(means), _f64(covs), _f64(attrs), _f64(cam_vec)
     N, C = m.shape[0], a.shape[1]
     pix, n = _pix(pixels, H, W)
+    gv = _given(given, n, K)
     g = np.ascontiguousarray(np.asarray(grad, np.float64).reshape(n, C))
     r = BackwardResult(N, C)
     rc = _lib().oracle_backward(_ptr(m), _ptr(c), _ptr(a), N, C, _ptr(cv), H, W, float(eta), K,
                                 _ptr(pix), n, _ptr(g), threads,
                                 _ptr(r.means), _ptr(r.covs), _ptr(r.attrs), _ptr(r.camera),
                                 _ptr(r.abs_means), _ptr(r.abs_covs), _ptr(r.abs_attrs), _ptr(r.abs_camera),
-                                int(mode))
+                                int(mode), _ptr(gv))
     if rc < 0:
         raise ValueError("oracle_backward: bad arguments")
     r.n_invalid = rc
@@ -222,18 +238,19 @@ class SampleResult:
 
 
 def sample(means, covs, cam_vec, H: int, W: int, K: int, features, eta: float = 0.01,
-           threads: int = 0) -> SampleResult:
+           threads: int = 0, given=None) -> SampleResult:
     """Inverse reconstruction of Sec. 3.4 (Eq. 10): every kernel takes the
     W-weighted mean of the feature map over the pixels that keep it,
     alpha_k = sum_p W_pk phi_p / sum_p W_pk, with W_pk = T(l_k) e^{q_k} the
     kernel-to-pixel weight of Eq. 8 (the forward's kept records).  features is
     (H, W, C) or (H*W, C).  A kernel that no pixel keeps has den = 0 and is
-    given alpha = 0 (the paper does not define the empty quotient)."""
+    given alpha = 0 (the paper does not define the empty quotient).  given:
+    optional (H*W, K) kept sets chosen elsewhere, as for forward()."""
     m = _f64(means)
     N = m.shape[0]
     phi = np.asarray(features, np.float64).reshape(H * W, -1)
     C = phi.shape[1]
-    fwd = forward(m, covs, np.zeros((N, 1)), cam_vec, H, W, K, eta, threads=threads)
+    fwd = forward(m, covs, np.zeros((N, 1)), cam_vec, H, W, K, eta, threads=threads, given=given)
     r = SampleResult(N, C)
     r.fwd = fwd
     pix, slot = np.nonzero(fwd.kept_idx >= 0)

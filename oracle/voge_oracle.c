@@ -247,6 +247,42 @@ static int select_kernels(const ker_t* ks, int N, const double D[3], double lnet
     return keff;
 }
 
+/* Step 4 replaced by a given kept set (the set another implementation
+ * selected for this pixel): `row` holds up to K kernel indices, -1 padded.
+ * Each listed kernel is traced as in step 3 and the set is put in (l, index)
+ * order; nothing is filtered, so steps 5-6 and the backward then run on
+ * exactly that set.  The caller has checked every index (see
+ * check_given).  Returns the set's size. */
+static int given_kernels(const ker_t* ks, const double D[3], const int32_t* row, int K, cand_t* out) {
+    int n = 0;
+    for (int s = 0; s < K; ++s) {
+        if (row[s] < 0) continue;
+        double l, q, a;
+        trace_kernel(&ks[row[s]], D, &l, &q, &a);
+        out[n].l = l;
+        out[n].q = q;
+        out[n].a = a;
+        out[n].idx = row[s];
+        ++n;
+    }
+    qsort(out, (size_t)n, sizeof(cand_t), cand_cmp);
+    return n;
+}
+
+/* A given kept set may only name valid kernels, each at most once per pixel. */
+static int check_given(const ker_t* ks, int N, const int32_t* given, int64_t npx, int K) {
+    for (int64_t p = 0; p < npx; ++p) {
+        const int32_t* row = given + p * K;
+        for (int s = 0; s < K; ++s) {
+            if (row[s] < 0) continue;
+            if (row[s] >= N || !ks[row[s]].valid) return -1;
+            for (int t = 0; t < s; ++t)
+                if (row[t] == row[s]) return -1;
+        }
+    }
+    return 0;
+}
+
 /* Steps 5-6 (Eq. 7-8): T_k = exp(-E(l_k)), W_k = T_k e^{q_k}. */
 static void blend_weights(const cand_t* kept, int keff, double* E, double* Wt) {
     for (int k = 0; k < keff; ++k) {
@@ -283,13 +319,17 @@ static int nthreads_of(int req) {
  *   kept_rec[n_pix*K*5]   (l, q, a, E(l_k), W_k) of each kept entry
  *   n_pass[n_pix]    number of kernels with e^q > eta and l > 0
  *   flags[n_pix]     OR_FLAG_TIE | OR_FLAG_ETA
+ * given[n_pix*K] (optional): kept sets chosen elsewhere (-1 padded).  Step 4
+ * is then skipped and steps 5-6 run on exactly these sets (n_pass = -1,
+ * flags = 0); an index out of range, of a skipped kernel or repeated within
+ * a pixel is a bad argument.
  * Returns the number of skipped (non-SPD / non-finite) kernels, or -1 on bad
  * arguments. */
 int oracle_forward(const double* means, const double* covs, const double* attrs, int N, int C,
                    const double* cam15, int H, int W, double eta, int K,
                    const int64_t* pix, int64_t n_pix, int nthreads,
                    double* image, double* wsum, double* absum, int32_t* kept_idx, double* kept_rec,
-                   int32_t* n_pass, int32_t* flags) {
+                   int32_t* n_pass, int32_t* flags, const int32_t* given) {
     if (check_args(N, C, H, W, eta, K)) return -1;
     cam_t cam;
     load_camera(cam15, H, W, &cam);
@@ -297,6 +337,10 @@ int oracle_forward(const double* means, const double* covs, const double* attrs,
     int n_invalid = prepare_kernels(means, covs, N, &cam, ks);
     const double lneta = log(eta);
     const int64_t npx = pix ? n_pix : (int64_t)H * W;
+    if (given && check_given(ks, N, given, npx, K)) {
+        free(ks);
+        return -1;
+    }
 
 #pragma omp parallel num_threads(nthreads_of(nthreads))
     {
@@ -309,8 +353,9 @@ int oracle_forward(const double* means, const double* covs, const double* attrs,
             int i = (int)(lin / W), j = (int)(lin % W);
             double D[3];
             pixel_ray(&cam, i, j, D);
-            int np_, fl;
-            int keff = select_kernels(ks, N, D, lneta, K, scratch, &np_, &fl);
+            int np_ = -1, fl = 0;
+            int keff = given ? given_kernels(ks, D, given + p * K, K, scratch)
+                             : select_kernels(ks, N, D, lneta, K, scratch, &np_, &fl);
             blend_weights(scratch, keff, E, Wt);
             double ws = 0.0;
             for (int k = 0; k < keff; ++k) ws += Wt[k];
@@ -377,12 +422,15 @@ void oracle_transmittance(const double* rec, int n, const double* t, int nt, dou
  * per-pair contributions to that element.
  * grad_mode: 0, or ORACLE_BLOCK_T and/or ORACLE_BLOCK_RHO (the gradient
  * ablations of the paper's pose-estimation ablation table).
+ * given (optional): kept sets chosen elsewhere, as for oracle_forward; the
+ * gradients are then those of the forward on exactly these sets.
  * Returns the number of skipped kernels or -1. */
 int oracle_backward(const double* means, const double* covs, const double* attrs, int N, int C,
                     const double* cam15, int H, int W, double eta, int K,
                     const int64_t* pix, int64_t n_pix, const double* grad_pix, int nthreads,
                     double* g_means, double* g_covs, double* g_attrs, double* g_cam,
-                    double* a_means, double* a_covs, double* a_attrs, double* a_cam, int grad_mode) {
+                    double* a_means, double* a_covs, double* a_attrs, double* a_cam, int grad_mode,
+                    const int32_t* given) {
     if (check_args(N, C, H, W, eta, K)) return -1;
     cam_t cam;
     load_camera(cam15, H, W, &cam);
@@ -390,6 +438,10 @@ int oracle_backward(const double* means, const double* covs, const double* attrs
     int n_invalid = prepare_kernels(means, covs, N, &cam, ks);
     const double lneta = log(eta);
     const int64_t npx = pix ? n_pix : (int64_t)H * W;
+    if (given && check_given(ks, N, given, npx, K)) {
+        free(ks);
+        return -1;
+    }
     const int nt = nthreads_of(nthreads);
     const size_t per = (size_t)N * (3 + 6 + (size_t)C) + 15;   /* one thread's accumulators */
     double* acc = (double*)calloc(per * (size_t)nt * 2, sizeof(double));
@@ -430,7 +482,8 @@ int oracle_backward(const double* means, const double* covs, const double* attrs
             double D[3];
             pixel_ray(&cam, i, j, D);
             int np_, fl;
-            int keff = select_kernels(ks, N, D, lneta, K, kept, &np_, &fl);
+            int keff = given ? given_kernels(ks, D, given + p * K, K, kept)
+                             : select_kernels(ks, N, D, lneta, K, kept, &np_, &fl);
             if (keff == 0) continue;
             blend_weights(kept, keff, E, Wt);
             /* C = sum_k W_k c_k:  dL/dc_k = W_k G;  dL/dW_k = G . c_k */

@@ -562,3 +562,126 @@ def test_p10_ablations_split_the_gradient():
         assert np.abs(getattr(br, name) - g).max() > 1e-6 * scale
         assert np.all(getattr(both, name) == 0.0)
     np.testing.assert_allclose(both.attrs, full.attrs, rtol=1e-12, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# P11: steps 5-6 and the backward on a kept set chosen elsewhere (the GPU's
+#      set at pixels where a near tie or a near-threshold kernel makes more
+#      than one set correct)
+# ---------------------------------------------------------------------------
+
+def test_p11_given_sets_equal_to_the_selection_reproduce_it():
+    """Handing the oracle its own kept sets (in any order) skips the
+    selection and must give the selection's results bit for bit."""
+    job = S.config_poses(n_poses=1, size=48)[0]
+    sc, cam = job.scene, job.camera
+    cv = cam.as_vector()
+    H, W, K = cam.height, cam.width, 20
+    own = O.forward(sc.means, sc.covs, sc.attrs, cv, H, W, K, threads=1)
+    assert (own.k_eff > 3).sum() > 200
+    rng = np.random.default_rng(111)
+    shuffled = np.array([rng.permutation(row) for row in own.kept_idx], np.int32)
+    for given in (own.kept_idx, shuffled):
+        r = O.forward(sc.means, sc.covs, sc.attrs, cv, H, W, K, threads=1, given=given)
+        for name in ("image", "absum", "wsum", "kept_idx", "kept_rec"):
+            assert np.array_equal(getattr(r, name), getattr(own, name)), name
+        assert np.all(r.n_pass == -1) and np.all(r.flags == 0)
+    G = rng.standard_normal((H * W, sc.channels))
+    b0 = O.backward(sc.means, sc.covs, sc.attrs, cv, H, W, K, G, threads=1)
+    b1 = O.backward(sc.means, sc.covs, sc.attrs, cv, H, W, K, G, threads=1, given=shuffled)
+    for name in ("means", "covs", "attrs", "camera", "abs_means", "abs_covs", "abs_attrs", "abs_camera"):
+        assert np.array_equal(getattr(b0, name), getattr(b1, name)), name
+
+
+def test_p11_given_subset_equals_a_scene_of_only_that_subset():
+    """A given subset X of a pixel's passing kernels blends like a scene that
+    holds only X (where the selection keeps all of X): an independent route
+    through the pinned selection.  A kernel below the threshold, given alone,
+    follows the lone-kernel closed form W = m e^{-m/2} (P2)."""
+    means, covs, attrs = tiny_scene(41, n=8)
+    means[:, :2] *= 0.3
+    cv = cam_vec(F=20.0, cx=10.0, cy=10.0)
+    H = W = 20
+    K = 8
+    own = O.forward(means, covs, attrs, cv, H, W, K)
+    rng = np.random.default_rng(42)
+    pix = np.flatnonzero(own.k_eff >= 3)
+    assert pix.size > 20
+    given = np.full((pix.size, K), -1, np.int32)
+    for r_, p in enumerate(pix):
+        ks = own.kept_idx[p][own.kept_idx[p] >= 0]
+        sub = rng.choice(ks, rng.integers(1, ks.size), replace=False)
+        given[r_, :sub.size] = rng.permutation(sub)
+    got = O.forward(means, covs, attrs, cv, H, W, K, pixels=pix, given=given)
+    for r_, p in enumerate(pix):
+        sub = given[r_][given[r_] >= 0]
+        ref = O.forward(means[sub], covs[sub], attrs[sub], cv, H, W, K, pixels=[p])
+        assert ref.k_eff[0] == sub.size
+        np.testing.assert_allclose(got.image[r_], ref.image[0], rtol=1e-13, atol=1e-15)
+        np.testing.assert_allclose(got.wsum[r_], ref.wsum[0], rtol=1e-13, atol=1e-15)
+        assert sorted(got.kept_idx[r_][got.kept_idx[r_] >= 0]) == sorted(sub[ref.kept_idx[0][:sub.size]])
+    # a kernel the threshold rejects at a pixel, given alone there
+    far = O.forward(means, covs, attrs, cv, H, W, K, eta=0.999999)
+    outside = [p for p in range(H * W) if far.k_eff[p] == 0 and own.k_eff[p] == 0][:5]
+    assert outside
+    g1 = np.full((len(outside), K), -1, np.int32)
+    g1[:, 0] = 3
+    r1 = O.forward(means, covs, attrs, cv, H, W, K, pixels=outside, given=g1)
+    q = r1.kept_rec[:, 0, 1]
+    assert np.all(q <= math.log(0.01))
+    m = np.exp(q)
+    np.testing.assert_allclose(r1.wsum, m * np.exp(-m / 2), rtol=1e-13, atol=1e-300)
+
+
+def test_p11_given_set_gradients_match_finite_differences():
+    """With the kept sets fixed by hand the forward is smooth in every
+    parameter; the backward on those sets must match its central
+    differences (no coordinate is skipped)."""
+    means, covs, attrs = tiny_scene(51, n=6)
+    R = rot([0.1, 1.0, 0.3], 0.2)
+    T = np.array([0.03, -0.02, 0.05])
+    H = W = 12
+    cv = cam_vec(R, T, F=12.0, cx=6.0, cy=5.5)
+    K = 4
+    own = O.forward(means, covs, attrs, cv, H, W, K)
+    rng = np.random.default_rng(52)
+    given = np.full((H * W, K), -1, np.int32)
+    for p in range(H * W):
+        ks = own.kept_idx[p][own.kept_idx[p] >= 0]
+        if ks.size:
+            sub = rng.choice(ks, rng.integers(1, ks.size + 1), replace=False)
+            given[p, :sub.size] = sub
+    G = rng.standard_normal((H * W, 2))
+    g = O.backward(means, covs, attrs, cv, H, W, K, G, given=given)
+
+    def loss(**kw):
+        args = dict(means=means, covs=covs, attrs=attrs, cv=cv)
+        args.update(kw)
+        r = O.forward(args["means"], args["covs"], args["attrs"], args["cv"], H, W, K, given=given)
+        return float((r.image * G).sum())
+
+    for name, arr, grad, scale in (("means", means, g.means, 1e-6), ("covs", covs, g.covs, 1e-8),
+                                   ("attrs", attrs, g.attrs, 1e-5), ("cv", cv, g.camera, 1e-6)):
+        flat = arr.reshape(-1)
+        for e in range(flat.size):
+            h = scale * max(1.0, abs(flat[e]))
+            plus, minus = flat.copy(), flat.copy()
+            plus[e] += h
+            minus[e] -= h
+            fd = (loss(**{name: plus.reshape(arr.shape)}) - loss(**{name: minus.reshape(arr.shape)})) / (2 * h)
+            an = grad.reshape(-1)[e]
+            assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-2) + 1e-8, (name, e, fd, an)
+
+
+def test_p11_given_sets_reject_bad_indices():
+    means, covs, attrs = tiny_scene(61, n=4)
+    cv = cam_vec(F=8.0, cx=4.0, cy=4.0)
+    for bad in ([4, -1], [1, 1], [-5, 2]):
+        g = np.full((1, 2), -1, np.int32)
+        g[0, :len(bad)] = bad
+        if bad[0] == -5:
+            g[0] = [-1, 2]          # negative entries are padding: valid
+            O.forward(means, covs, attrs, cv, 8, 8, 2, pixels=[0], given=g)
+            continue
+        with pytest.raises(ValueError):
+            O.forward(means, covs, attrs, cv, 8, 8, 2, pixels=[0], given=g)
