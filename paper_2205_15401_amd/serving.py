@@ -13,7 +13,11 @@ image size arrive at any time.  The server
     batch and runs it with one ``voge_render_batch`` call on the slot's own
     stream (two slots: two batches in flight);
   * completes a batch's requests when its HIP event fires, releases their
-    memory from the budget, and records arrival-to-completion latency.
+    memory from the budget, and records arrival-to-completion latency;
+  * fails a request that passes its deadline (queued: it is never launched;
+    in flight: it completes at once as failed, its results are dropped, and
+    its memory returns to the budget when its batch ends), and cancels a
+    request on demand the same way -- the server keeps running.
 
 The scheduling logic is host code and does not touch the GPU: an executor
 does (``GpuExecutor``); tests drive the same scheduler with a simulated
@@ -44,6 +48,7 @@ class Request:
     grad_image: Any = None             # (H, W, C) upstream gradient, host or device, for backward
     arrival: float = 0.0               # server clock, seconds
     with_camera: bool = False          # also return dL/dcamera
+    deadline: Optional[float] = None   # server clock, seconds: fail the request if not done by then
     rid: int = -1
     # filled in by the server and executor
     nbytes: int = 0
@@ -139,23 +144,70 @@ class Server:
         if err is None and req.nbytes > self.budget:
             err = f"request needs {req.nbytes} bytes, more than the budget of {self.budget}"
         if err is not None:
-            req.error = err
-            req.done = self.ex.now()
-            self.completed.append(req)
-            if self.on_done:
-                self.on_done(req)
+            self._finish(req, err)
             return False
         self.queue.append(req)
         return True
+
+    @staticmethod
+    def _drop_outputs(r: Request) -> None:
+        r.image = r.grad_means = r.grad_covs = r.grad_attrs = r.grad_camera = None
+
+    def _finish(self, r: Request, error: Optional[str]) -> None:
+        r.done = self.ex.now()
+        if error is not None:
+            r.error = error
+            self._drop_outputs(r)        # a failed or cancelled request hands back no results
+        self.completed.append(r)
+        if self.on_done:
+            self.on_done(r)
+
+    def cancel(self, req: Request) -> bool:
+        """Cancel a request that is not done yet: a queued request leaves the
+        queue, an in-flight one completes now as cancelled (the device work
+        of its batch runs on; its memory is released when the batch ends).
+        Returns False if the request was already done or is unknown."""
+        if req.done is not None:
+            return False
+        for i, r in enumerate(self.queue):
+            if r is req:
+                del self.queue[i]
+                self._finish(req, "cancelled")
+                return True
+        for b in self.inflight.values():
+            if any(r is req for r in b.reqs):
+                self._finish(req, "cancelled")
+                return True
+        return False
+
+    def _expire(self) -> int:
+        """Fail every request past its deadline, queued or in flight."""
+        now = self.ex.now()
+        n = 0
+        late = [r for r in self.queue if r.deadline is not None and now >= r.deadline]
+        if late:
+            gone = {id(r) for r in late}
+            self.queue = collections.deque(r for r in self.queue if id(r) not in gone)
+            for r in late:
+                self._finish(r, "deadline exceeded")
+                n += 1
+        for b in self.inflight.values():
+            for r in b.reqs:
+                if r.done is None and r.deadline is not None and now >= r.deadline:
+                    self._finish(r, "deadline exceeded")
+                    n += 1
+        return n
 
     # -------------------------------------------------------------- progress
     def idle(self) -> bool:
         return not self.queue and not self.inflight
 
     def pump(self) -> int:
-        """Complete finished batches, then admit and launch while possible.
-        Returns the number of requests completed."""
+        """Complete finished batches, fail requests past their deadlines, then
+        admit and launch while possible.  Returns the number of requests
+        completed (successfully or not)."""
         n = self._complete()
+        n += self._expire()
         self._admit()
         return n
 
@@ -175,17 +227,14 @@ class Server:
                 self.ex.collect(b.handle)
             except Exception as e:
                 err = f"batch failed: {e}"
-            t = self.ex.now()
             for r in b.reqs:
-                r.done = t
-                if err is not None:
-                    r.error = err
-                self.completed.append(r)
-                if self.on_done:
-                    self.on_done(r)
+                if r.done is not None:          # cancelled or past its deadline already
+                    self._drop_outputs(r)
+                    continue
+                self._finish(r, err)
+                n += 1
             self.inflight_bytes -= b.nbytes
             del self.inflight[slot]
-            n += len(b.reqs)
         return n
 
     def _pick(self, backward: bool) -> List[Request]:
@@ -236,11 +285,7 @@ class Server:
                 handle = self.ex.launch(slot, batch)
             except Exception as e:
                 for r in batch:
-                    r.error = f"launch failed: {e}"
-                    r.done = self.ex.now()
-                    self.completed.append(r)
-                    if self.on_done:
-                        self.on_done(r)
+                    self._finish(r, f"launch failed: {e}")
                 continue
             self.inflight[slot] = _Batch(slot, batch, nbytes, handle)
             self.inflight_bytes += nbytes
@@ -318,8 +363,16 @@ class GpuExecutor(Executor):
         return b + nat.voge_batch_workspace_size([self._item(req)], req.backward)
 
     def launch(self, slot: int, reqs: List[Request]):
+        """Runs the batch on the slot's stream.  The slot stream first waits
+        for the caller's stream, so inputs the caller has just produced there
+        (upstream gradients, scene updates) are complete before the batch
+        reads them; every output is marked as used on the caller's stream, so
+        the caching allocator does not hand its memory to a later launch while
+        work the caller queues on it is still pending."""
         torch = self.torch
         s = self.streams[slot]
+        caller = torch.cuda.current_stream(self.device)
+        s.wait_stream(caller)
         arr = (nat.VogeItem * len(reqs))()
         keep = []
         f32 = dict(dtype=torch.float32, device=self.device)
@@ -350,7 +403,11 @@ class GpuExecutor(Executor):
             nat.voge_render_batch(self.ctx, arr, flags, ws.data_ptr(), ws_bytes, s.cuda_stream)
             ev = torch.cuda.Event()
             ev.record(s)
-        return {"event": ev, "ws": ws, "keep": keep, "reqs": reqs, "stream": s, "n": len(reqs)}
+        for r in reqs:
+            for t in (r.image, r.grad_means, r.grad_covs, r.grad_attrs, r.grad_camera):
+                if t is not None:
+                    t.record_stream(caller)
+        return {"event": ev, "ws": ws, "keep": keep, "reqs": reqs, "stream": s, "n": len(reqs), "caller": caller}
 
     def ready(self, handle) -> bool:
         return handle["event"].query()
@@ -359,3 +416,5 @@ class GpuExecutor(Executor):
         st = nat.voge_batch_status(handle["ws"].data_ptr(), handle["n"], handle["stream"].cuda_stream)
         for r, v in zip(handle["reqs"], st):
             r.status = int(v)
+        # the caller's later work on the outputs is ordered after the batch
+        handle["caller"].wait_event(handle["event"])

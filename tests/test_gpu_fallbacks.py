@@ -1,0 +1,201 @@
+"""Paths the common workloads never take, forced and checked against the
+FP64 oracle through the C ABI, and the largest serving shape.
+
+* Table-full paths.  The backward's tile reduction orders a tile's (pixel,
+  kernel) pairs through a hash table of 1,024 kernels in LDS, and the
+  sampler accumulates a tile's weights through an LDS table of the same
+  size; a kernel that finds its table full sends its pairs to global memory
+  one by one.  A scene of small kernels in six depth layers over a 32x32
+  image puts 1,250 (K = 20) to 1,700 (K = 64) distinct kept kernels in every
+  16x16 tile, so every tile overflows both tables.
+* The serving workload's largest request: a 1024x1024 image of the
+  200,000-kernel scene, forward and backward with a dense upstream gradient;
+  kept sets on sampled pixels, images and every gradient on all pixels.
+* The coarse stage's fallbacks: a tile whose bin holds more kernels than
+  select sorts in LDS, and tiles past the end of a full pair list, are
+  scanned over every record of their item.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2205_15401_amd import _native as nat
+from paper_2205_15401_amd import render as R
+from paper_2205_15401_amd import scenes as S
+
+from parity import RTOL, check_backward_vs_oracle, check_forward_vs_oracle, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    nat.load()
+    return torch.device("cuda:0")
+
+
+def layered_scene(seed=5, size=32, layers=6, px_sigma=0.4):
+    """One small isotropic kernel near every pixel's ray in each of `layers`
+    depth layers (depth U[2,4]); the kernel's screen-space sigma is
+    `px_sigma` pixels, so each one is kept by a handful of pixels and a 16x16
+    tile keeps well over a thousand distinct kernels."""
+    rng = np.random.default_rng(seed)
+    F = float(size)
+    ii, jj = np.meshgrid(np.arange(size), np.arange(size), indexing="ij")
+    pts = []
+    for _ in range(layers):
+        z = rng.uniform(2.0, 4.0, (size, size))
+        di = ii + rng.uniform(-0.3, 0.3, (size, size))
+        dj = jj + rng.uniform(-0.3, 0.3, (size, size))
+        pts.append(np.stack([(di - size / 2) / F * z, (dj - size / 2) / F * z, z], -1).reshape(-1, 3))
+    means = np.concatenate(pts).astype(np.float32)
+    sig = px_sigma * means[:, 2] / F
+    covs = np.zeros((means.shape[0], 6), np.float32)
+    covs[:, 0] = covs[:, 3] = covs[:, 5] = sig ** 2
+    attrs = rng.standard_normal((means.shape[0], 3)).astype(np.float32)
+    return S.Scene(means, covs, attrs), S.identity_camera(size, F)
+
+
+def distinct_per_tile(kept, H, W, K):
+    k = kept.reshape(H, W, K)
+    out = []
+    for ti in range(0, H, 16):
+        for tj in range(0, W, 16):
+            blk = k[ti:ti + 16, tj:tj + 16]
+            out.append(len(set(blk[blk >= 0].tolist())))
+    return out
+
+
+@pytest.mark.parametrize("K", [20, 64])
+def test_full_tables_backward_matches_the_oracle(K):
+    scene, cam = layered_scene()
+    H, W = cam.height, cam.width
+    rng = np.random.default_rng(60 + K)
+    G = rng.standard_normal((H, W, 3)).astype(np.float32)
+    m, c, a = to_dev(scene.means), to_dev(scene.covs), to_dev(scene.attrs)
+    cs = R.camera_struct(cam)
+    img, ws, kept, work = R.render_forward(m, c, a, cs, K, 0.01, with_wsum=True, with_kept=True, for_backward=True)
+    gm, gc, ga, gk = R.render_backward(m, c, a, cs, to_dev(G), K, 0.01, workspace=work, reuse=True)
+    torch.cuda.synchronize()
+    kept = kept.cpu().numpy().reshape(H * W, K)
+    assert min(distinct_per_tile(kept, H, W, K)) > 1024, "every tile must overflow the 1,024-entry table"
+    check_forward_vs_oracle(img.cpu().numpy(), ws.cpu().numpy(), kept, scene, cam, K,
+                            name=f"full tables K={K} forward")
+    check_backward_vs_oracle(dict(means=gm.cpu().numpy(), covs=gc.cpu().numpy(), attrs=ga.cpu().numpy(),
+                                  camera=gk.cpu().numpy()), scene, cam, K, G.reshape(-1, 3), kept,
+                             name=f"full tables K={K} backward")
+
+
+@pytest.mark.parametrize("K", [20, 64])
+def test_full_tables_sampler_matches_the_oracle(K):
+    scene, cam = layered_scene(seed=6)
+    H, W = cam.height, cam.width
+    rng = np.random.default_rng(70 + K)
+    phi = rng.standard_normal((H, W, 5)).astype(np.float32)
+    m, c, a = to_dev(scene.means), to_dev(scene.covs), to_dev(scene.attrs)
+    cs = R.camera_struct(cam)
+    _, _, kept, work = R.render_forward(m, c, a, cs, K, 0.01, with_kept=True, for_backward=True)
+    alpha, wk, _ = R.sample(m, c, torch.from_numpy(phi).cuda(), cs, K, 0.01, workspace=work, reuse=True,
+                            with_weight=True)
+    torch.cuda.synchronize()
+    kept = kept.cpu().numpy().reshape(H * W, K)
+    assert min(distinct_per_tile(kept, H, W, K)) > 1024
+    check_forward_vs_oracle(None, None, kept, scene, cam, K, name=f"full tables K={K} sampler kept sets")
+    ref = O.sample(scene.means, scene.covs, cam.as_vector(), H, W, K, phi, 0.01, given=kept)
+    absref = O.sample(scene.means, scene.covs, cam.as_vector(), H, W, K, np.abs(phi), 0.01, given=kept)
+    al, w = alpha.cpu().numpy().astype(np.float64), wk.cpu().numpy().astype(np.float64)
+    seen = ref.den > 0
+    assert seen.sum() > 0.9 * scene.n
+    assert np.all(al[~seen] == 0.0) and np.all(w[~seen] == 0.0)
+    bound = RTOL * (absref.num[seen] / ref.den[seen, None] + np.abs(ref.alpha[seen])) + 1e-30
+    ratio = np.abs(al[seen] - ref.alpha[seen]) / bound
+    assert ratio.max() <= 1.0, f"alpha, worst {ratio.max():.3g} of the bound"
+    wr = np.abs(w[seen] - ref.den[seen]) / (RTOL * ref.den[seen])
+    assert wr.max() <= 1.0, f"weight sums, worst {wr.max():.3g} of the bound"
+
+
+def test_largest_serving_request_matches_the_oracle():
+    """1024x1024, the 200,000-kernel scene of the serving workload, a random
+    look-at pose, K = 20, forward + backward with a dense N(0,1) upstream
+    gradient: kept sets on 2,000 sampled pixels against the oracle's
+    selection; image, weight sum and every gradient over all 1,048,576
+    pixels against the oracle on the GPU's kept sets."""
+    scene = S.serving_scenes(sizes=(10_000, 25_000, 50_000, 100_000, 150_000, 200_000))[5]
+    assert scene.n == 200_000
+    rng = np.random.default_rng(80)
+    cam = S.random_pose(rng, 1024)
+    H, W = cam.height, cam.width
+    G = rng.standard_normal((H, W, 3)).astype(np.float32)
+    m, c, a = to_dev(scene.means), to_dev(scene.covs), to_dev(scene.attrs)
+    cs = R.camera_struct(cam)
+    img, ws, kept, work = R.render_forward(m, c, a, cs, 20, 0.01, with_wsum=True, with_kept=True, for_backward=True)
+    gm, gc, ga, gk = R.render_backward(m, c, a, cs, to_dev(G), 20, 0.01, workspace=work, reuse=True)
+    torch.cuda.synchronize()
+    assert R.status(work) == 0
+    kept = kept.cpu().numpy().reshape(H * W, 20)
+    assert (kept[:, 0] >= 0).mean() > 0.2
+    pix = np.sort(rng.choice(H * W, 2000, replace=False))
+    check_forward_vs_oracle(img.cpu().numpy(), ws.cpu().numpy(), kept, scene, cam, 20, pixels=pix,
+                            full_image=True, name="serving 200k 1024px forward")
+    check_backward_vs_oracle(dict(means=gm.cpu().numpy(), covs=gc.cpu().numpy(), attrs=ga.cpu().numpy(),
+                                  camera=gk.cpu().numpy()), scene, cam, 20, G.reshape(-1, 3), kept,
+                             name="serving 200k 1024px backward", floor_draws=1)
+
+
+def wide_scene(rng, n, sigma, size, centre_z=3.0, spread=0.6, C=3):
+    """n isotropic kernels of std `sigma` around (0, 0, centre_z): with sigma
+    large enough their eta-ellipsoids reach the camera plane, so their screen
+    boxes cover the whole image."""
+    means = np.column_stack([rng.uniform(-spread, spread, n), rng.uniform(-spread, spread, n),
+                             centre_z + rng.uniform(-0.5, 0.5, n)]).astype(np.float32)
+    s = (sigma * rng.uniform(0.8, 1.2, n)).astype(np.float32)
+    covs = np.zeros((n, 6), np.float32)
+    covs[:, 0] = covs[:, 3] = covs[:, 5] = s ** 2
+    return S.Scene(means, covs, rng.standard_normal((n, C)).astype(np.float32))
+
+
+def check_both(scene, cam, K, name, seed):
+    H, W = cam.height, cam.width
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((H, W, scene.attrs.shape[1])).astype(np.float32)
+    m, c, a = to_dev(scene.means), to_dev(scene.covs), to_dev(scene.attrs)
+    cs = R.camera_struct(cam)
+    img, ws, kept, work = R.render_forward(m, c, a, cs, K, 0.01, with_wsum=True, with_kept=True, for_backward=True)
+    gm, gc, ga, gk = R.render_backward(m, c, a, cs, to_dev(G), K, 0.01, workspace=work, reuse=True)
+    torch.cuda.synchronize()
+    kept = kept.cpu().numpy().reshape(H * W, K)
+    check_forward_vs_oracle(img.cpu().numpy(), ws.cpu().numpy(), kept, scene, cam, K, name=name + " forward")
+    check_backward_vs_oracle(dict(means=gm.cpu().numpy(), covs=gc.cpu().numpy(), attrs=ga.cpu().numpy(),
+                                  camera=gk.cpu().numpy()), scene, cam, K, G.reshape(-1, G.shape[2]), kept,
+                             name=name + " backward")
+    return kept
+
+
+def test_tiles_with_more_candidates_than_a_bin_holds():
+    """Select sorts a tile's bin in LDS when it holds at most 2,048 kernels and
+    scans every record of the item otherwise.  2,600 kernels whose boxes
+    cover the whole 48x40 image (every tile unbinned) next to the same image
+    with a 1,000-kernel scene of small kernels (every tile binned): both
+    against the oracle, K = 20 (buffers fill: the early exit is taken)."""
+    rng = np.random.default_rng(90)
+    wide = wide_scene(rng, 2600, 1.2, 48)
+    cam = S.identity_camera(48, 48.0, height=40)
+    kept = check_both(wide, cam, 20, "unbinned tiles", 91)
+    assert (kept >= 0).all()                      # every pixel keeps 20 of the 2,600
+    small = S.cloud_scene(rng, 1000, 3, std_range=(0.02, 0.06))
+    check_both(small, cam, 20, "binned tiles", 92)
+
+
+def test_pair_list_overflow_falls_back_per_tile():
+    """1,000 kernels whose boxes each cover all 256 tiles of a 256x256 image
+    give 256,000 (kernel, tile) pairs, more than the pair list holds (8 per
+    kernel + 64 per tile + 1,024 = 25,408): the first tiles are binned, the
+    rest scan every record; the whole image against the oracle."""
+    rng = np.random.default_rng(93)
+    wide = wide_scene(rng, 1000, 1.2, 256, spread=0.8)
+    cam = S.identity_camera(256, 256.0)
+    check_both(wide, cam, 8, "pair-list overflow", 94)

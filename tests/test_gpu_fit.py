@@ -11,9 +11,10 @@ import torch
 from oracle import oracle as O
 from paper_2205_15401_amd import _native as nat
 from paper_2205_15401_amd import fit as FIT
+from paper_2205_15401_amd import render as R
 from paper_2205_15401_amd import scenes as S
 
-from parity import compare_grad, compare_images, to_dev
+from parity import RTOL, check_forward_vs_oracle, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -48,23 +49,28 @@ def test_view_batch_gradients_match_the_oracle():
     views = FIT.Views(cams, K=20)
     m, c, a = (to_dev(x).requires_grad_(True) for x in (sc.means, sc.covs, sc.attrs))
     imgs = views.render(m, c, a)
-    G = []
+    G, kepts = [], []
     for v, cam in enumerate(cams):
-        ref = O.forward(sc.means, sc.covs, sc.attrs, cam.as_vector(), 48, 48, 20)
-        same = ref.flags == 0
-        assert compare_images(imgs[v].detach().cpu().numpy().reshape(-1, 3), ref.image, ref.absum,
-                              mask=same) <= 1.0, f"view {v}: image"
-        g = rng.standard_normal((48 * 48, 3)).astype(np.float32)
-        g[~same] = 0.0
-        G.append(g.reshape(48, 48, 3))
+        # the view's kept sets, from a single-camera forward of the same view
+        _, _, kept, _ = R.render_forward(m.detach(), c.detach(), a.detach(), R.camera_struct(cam), 20, 0.01,
+                                         with_kept=True)
+        kept = kept.cpu().numpy().reshape(-1, 20)
+        kepts.append(kept)
+        check_forward_vs_oracle(imgs[v].detach().cpu().numpy().reshape(-1, 3), None, kept, sc, cam, 20,
+                                name=f"fit view {v}")
+        G.append(rng.standard_normal((48, 48, 3)).astype(np.float32))
     (imgs * torch.from_numpy(np.stack(G)).cuda()).sum().backward()
-    refs = [O.backward(sc.means, sc.covs, sc.attrs, cam.as_vector(), 48, 48, 20, G[v].reshape(-1, 3))
-            for v, cam in enumerate(cams)]
-    for name, t, rv, av in (("means", m, "means", "abs_means"), ("covs", c, "covs", "abs_covs"),
-                            ("attrs", a, "attrs", "abs_attrs")):
-        r = sum(getattr(b, rv) for b in refs)
-        ab = sum(getattr(b, av) for b in refs)
-        elem, inf = compare_grad(t.grad.cpu().numpy(), r, ab)
+    # the view batch's gradient is the sum over views: one oracle check per
+    # view would need the per-view gradients, so the sum is checked against
+    # the sum of the oracle's per-view backward on the same kept sets
+    refs = [O.backward(sc.means, sc.covs, sc.attrs, cam.as_vector(), 48, 48, 20, G[v].reshape(-1, 3),
+                       given=kepts[v]) for v, cam in enumerate(cams)]
+    for name, t in (("means", m), ("covs", c), ("attrs", a)):
+        r = sum(getattr(b, name) for b in refs)
+        ab = sum(getattr(b, "abs_" + name) for b in refs)
+        err = np.abs(t.grad.cpu().numpy() - r)
+        elem = float((err / (RTOL * ab + 1e-30)).max())
+        inf = float(err.max() / (RTOL * np.abs(r).max() + 1e-30))
         assert elem <= 1.0 and inf <= 1.0, f"{name}: element {elem:.3g}, inf-norm {inf:.3g}"
 
 

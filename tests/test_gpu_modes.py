@@ -24,7 +24,7 @@ from paper_2205_15401_amd import _native as nat
 from paper_2205_15401_amd import render as R
 from paper_2205_15401_amd import scenes as S
 
-from parity import compare_grad, to_dev
+from parity import check_backward_vs_oracle, compare_grad, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -39,33 +39,26 @@ def gpu():
     return torch.device("cuda:0")
 
 
-def tie_free_gradient(rng, scene, cam, K, eta=0.01):
-    H, W, C = cam.height, cam.width, scene.attrs.shape[1]
-    ref = O.forward(scene.means, scene.covs, scene.attrs, cam.as_vector(), H, W, K, eta)
-    G = rng.standard_normal((H * W, C)).astype(np.float32)
-    G[ref.flags != 0] = 0.0
-    return G.reshape(H, W, C)
-
-
 @pytest.mark.parametrize("mode", [O.BLOCK_T, O.BLOCK_RHO, O.BLOCK_T | O.BLOCK_RHO])
 def test_ablated_gradients_match_the_oracle(mode):
     rng = np.random.default_rng(300 + mode)
     sc = S.torus_scene(rng, 2500, 3, centre=(0.0, 0.0, 3.0))
     cam = S.identity_camera(72, focal=70.0, height=56)
-    G = tie_free_gradient(rng, sc, cam, 20)
+    G = rng.standard_normal((56, 72, 3)).astype(np.float32)
     m, c, a = (to_dev(x) for x in (sc.means, sc.covs, sc.attrs))
     bt, br = bool(mode & O.BLOCK_T), bool(mode & O.BLOCK_RHO)
-    gm, gc, ga, gk = R.render_backward(m, c, a, R.camera_struct(cam), torch.from_numpy(G).cuda(), 20, 0.01,
-                                       block_t=bt, block_rho=br)
+    cs = R.camera_struct(cam)
+    _, _, kept, ws = R.render_forward(m, c, a, cs, 20, 0.01, with_kept=True, for_backward=True)
+    gm, gc, ga, gk = R.render_backward(m, c, a, cs, torch.from_numpy(G).cuda(), 20, 0.01, workspace=ws,
+                                       reuse=True, block_t=bt, block_rho=br)
     torch.cuda.synchronize()
-    ref = O.backward(sc.means, sc.covs, sc.attrs, cam.as_vector(), 56, 72, 20, G.reshape(-1, 3), mode=mode)
-    for name, g, r, ab in (("means", gm, ref.means, ref.abs_means), ("covs", gc, ref.covs, ref.abs_covs),
-                           ("attrs", ga, ref.attrs, ref.abs_attrs), ("camera", gk, ref.camera, ref.abs_camera)):
-        if mode == O.BLOCK_T | O.BLOCK_RHO and name != "attrs":
-            assert float(g.abs().max()) == 0.0, f"{name}: both paths blocked leaves no geometric gradient"
-            continue
-        elem, inf = compare_grad(g.cpu().numpy(), r, ab)
-        assert elem <= 1.0 and inf <= 1.0, f"mode {mode} {name}: element {elem:.3g}, inf-norm {inf:.3g}"
+    kept = kept.cpu().numpy().reshape(-1, 20)
+    grads = dict(means=gm.cpu().numpy(), covs=gc.cpu().numpy(), attrs=ga.cpu().numpy(), camera=gk.cpu().numpy())
+    if mode == O.BLOCK_T | O.BLOCK_RHO:
+        for name in ("means", "covs", "camera"):
+            assert float(np.abs(grads.pop(name)).max()) == 0.0, f"{name}: both paths blocked leaves no gradient"
+    check_backward_vs_oracle(grads, sc, cam, 20, G.reshape(-1, 3), kept, 0.01, mode=mode,
+                             name=f"ablation mode {mode}")
 
 
 def test_ablation_flags_in_a_batch():
@@ -77,19 +70,17 @@ def test_ablation_flags_in_a_batch():
                                                      target=(0.0, 0.0, 3.0))]
     dev = torch.device("cuda:0")
     m, c, a = (to_dev(x) for x in (sc.means, sc.covs, sc.attrs))
-    batch = R.Batch([(m, c, a)], [(0, R.camera_struct(cm), 16, 0.01) for cm in cams], dev, backward=True)
-    Gs = [tie_free_gradient(rng, sc, cm, 16) for cm in cams]
+    batch = R.Batch([(m, c, a)], [(0, R.camera_struct(cm), 16, 0.01) for cm in cams], dev, backward=True,
+                    with_kept=True)
+    Gs = [rng.standard_normal((cm.height, cm.width, 4)).astype(np.float32) for cm in cams]
     for i, G in enumerate(Gs):
         batch.set_grad_image(i, torch.from_numpy(G))
     batch.run(forward=True, backward=True, block_rho=True)
     torch.cuda.synchronize()
     for i, cm in enumerate(cams):
-        ref = O.backward(sc.means, sc.covs, sc.attrs, cm.as_vector(), cm.height, cm.width, 16, Gs[i].reshape(-1, 4),
-                         mode=O.BLOCK_RHO)
-        for name, g, r, ab in (("means", batch.grad_means[i], ref.means, ref.abs_means),
-                               ("covs", batch.grad_covs[i], ref.covs, ref.abs_covs)):
-            elem, inf = compare_grad(g.cpu().numpy(), r, ab)
-            assert elem <= 1.0 and inf <= 1.0, f"item {i} {name}: element {elem:.3g}, inf-norm {inf:.3g}"
+        grads = dict(means=batch.grad_means[i].cpu().numpy(), covs=batch.grad_covs[i].cpu().numpy())
+        check_backward_vs_oracle(grads, sc, cm, 16, Gs[i].reshape(-1, 4), batch.kepts[i].cpu().numpy(), 0.01,
+                                 mode=O.BLOCK_RHO, name=f"ablation batch item {i}")
 
 
 def by_kernel(idx_row, vals_row):

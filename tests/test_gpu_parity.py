@@ -2,9 +2,11 @@
 
 Sizes: the small sphere scene and a ragged 100x72 torus are compared at
 every pixel; the 512x512, 10,000-kernel torus (the benchmark workload, in
-the launch configuration the benchmark times) on sampled pixels, and its
-backward through an upstream gradient that is non-zero only on sampled
-pixels, so the oracle can compute every kernel's exact gradient.
+the launch configuration the benchmark times) on sampled pixels for the
+kept sets and at every pixel for the image and the full-image backward
+(the oracle blends and differentiates the GPU's own kept sets, so no pixel
+is left out: where a near tie or a near-threshold kernel makes more than one
+set correct, the difference itself is checked to be one).
 """
 
 import math
@@ -18,7 +20,7 @@ from paper_2205_15401_amd import _native as nat
 from paper_2205_15401_amd import render as R
 from paper_2205_15401_amd import scenes as S
 
-from parity import RTOL, compare_grad, compare_images, compare_kept, to_dev
+from parity import check_backward_vs_oracle, check_forward_vs_oracle, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -47,18 +49,12 @@ def oracle_forward(scene, cam, K, eta=0.01, pixels=None):
                      pixels=pixels)
 
 
-def check_forward(scene, cam, K, eta=0.01, pixels=None, max_flagged_frac=0.01):
+def check_forward(scene, cam, K, eta=0.01, pixels=None, max_flagged_frac=0.01, name="", full_image=False):
     img, wsum, kept, st = gpu_forward(scene, cam, K, eta)
-    ref = oracle_forward(scene, cam, K, eta, pixels)
-    sel = np.arange(cam.height * cam.width) if pixels is None else np.asarray(pixels)
-    n_bad, n_bad_unflagged, same = compare_kept(kept[sel], ref.kept_idx, ref.flags, ref.kept_rec[..., 0])
-    assert n_bad_unflagged == 0, f"{n_bad_unflagged} unflagged pixels with different kept sets"
-    assert n_bad <= max_flagged_frac * len(sel) + 1
-    r_img = compare_images(img[sel], ref.image, ref.absum, mask=same)
-    r_ws = compare_images(wsum[sel, None], ref.wsum[:, None], ref.wsum[:, None], mask=same)
-    assert r_img <= 1.0, f"image error {r_img:.3g} x tolerance"
-    assert r_ws <= 1.0, f"weight-sum error {r_ws:.3g} x tolerance"
-    return ref, img, kept, st
+    own, given = check_forward_vs_oracle(img, wsum, kept, scene, cam, K, eta, pixels, max_flagged_frac,
+                                         name=name or f"forward {cam.height}x{cam.width} N={scene.n} K={K}",
+                                         full_image=full_image)
+    return own, img, kept, st
 
 
 # ------------------------------------------------------------------ Phi
@@ -115,7 +111,8 @@ def test_torus_benchmark_size_sampled_pixels():
     job = S.config_torus()
     rng = np.random.default_rng(22)
     pix = rng.choice(512 * 512, 4000, replace=False)
-    ref, *_ = check_forward(job.scene, job.camera, job.K, pixels=pix)
+    ref, *_ = check_forward(job.scene, job.camera, job.K, pixels=pix, full_image=True,
+                            name="forward torus10000_512px_C16_K20")
     assert (ref.k_eff == 20).sum() > 1000
 
 
@@ -176,45 +173,32 @@ def test_principal_point_off_centre_and_nonsquare():
 # ------------------------------------------------------------- backward
 
 def gpu_backward(scene, cam, K, G, eta=0.01, reuse=True):
+    """GPU gradients and the kept sets they were taken on (the forward's)."""
     m, c, a = to_dev(scene.means), to_dev(scene.covs), to_dev(scene.attrs)
     cs = R.camera_struct(cam)
-    ws = None
-    if reuse:
-        _, _, _, ws = R.render_forward(m, c, a, cs, K, eta, for_backward=True)
-    gm, gc, ga, gk = R.render_backward(m, c, a, cs, to_dev(G), K, eta, workspace=ws, reuse=reuse)
+    _, _, kept, ws = R.render_forward(m, c, a, cs, K, eta, with_kept=True, for_backward=True)
+    gm, gc, ga, gk = R.render_backward(m, c, a, cs, to_dev(G), K, eta, workspace=ws if reuse else None,
+                                       reuse=reuse)
     torch.cuda.synchronize()
-    return gm.cpu().numpy(), gc.cpu().numpy(), ga.cpu().numpy(), gk.cpu().numpy()
+    kept = kept.cpu().numpy().reshape(-1, K)
+    return gm.cpu().numpy(), gc.cpu().numpy(), ga.cpu().numpy(), gk.cpu().numpy(), kept
 
 
-def check_backward(scene, cam, K, G_full, pixels, eta=0.01, reuse=True):
-    gm, gc, ga, gk = gpu_backward(scene, cam, K, G_full, eta, reuse)
+def check_backward(scene, cam, K, G_full, eta=0.01, reuse=True, name=""):
+    """Every pixel's upstream gradient, against the oracle's backward on the
+    GPU's kept sets."""
+    gm, gc, ga, gk, kept = gpu_backward(scene, cam, K, G_full, eta, reuse)
     C = scene.attrs.shape[1]
-    Gp = G_full.reshape(-1, C)[pixels]
-    ref = O.backward(scene.means, scene.covs, scene.attrs, cam.as_vector(), cam.height, cam.width, K, Gp, eta,
-                     pixels=pixels)
-    out = {}
-    for name, g, r, a in (("means", gm, ref.means, ref.abs_means), ("covs", gc, ref.covs, ref.abs_covs),
-                          ("attrs", ga, ref.attrs, ref.abs_attrs), ("camera", gk, ref.camera, ref.abs_camera)):
-        elem, inf = compare_grad(g, r, a)
-        out[name] = (elem, inf)
-        assert elem <= 1.0 and inf <= 1.0, f"{name}: element {elem:.3g}, inf-norm {inf:.3g} x tolerance"
-    return out
-
-
-def unflagged_pixels(scene, cam, K, eta=0.01, pixels=None):
-    ref = oracle_forward(scene, cam, K, eta, pixels)
-    sel = np.arange(cam.height * cam.width) if pixels is None else np.asarray(pixels)
-    return sel[ref.flags == 0]
+    return check_backward_vs_oracle(dict(means=gm, covs=gc, attrs=ga, camera=gk), scene, cam, K,
+                                    np.asarray(G_full).reshape(-1, C), kept, eta,
+                                    name=name or f"backward {cam.height}x{cam.width} N={scene.n} K={K}")
 
 
 def test_backward_small_every_pixel():
     job = S.config_small()
     rng = np.random.default_rng(31)
     G = rng.standard_normal((64, 64, 3)).astype(np.float32)
-    pix = unflagged_pixels(job.scene, job.camera, 16)
-    Gm = np.zeros_like(G).reshape(-1, 3)
-    Gm[pix] = G.reshape(-1, 3)[pix]
-    check_backward(job.scene, job.camera, 16, Gm.reshape(G.shape), pix)
+    check_backward(job.scene, job.camera, 16, G)
 
 
 def test_backward_rotated_camera_ragged():
@@ -222,20 +206,14 @@ def test_backward_rotated_camera_ragged():
     cam = S.Camera(job.camera.R, job.camera.T, 70.0, 33.5, 38.0, 75, 66)
     rng = np.random.default_rng(32)
     G = rng.standard_normal((75, 66, 3)).astype(np.float32)
-    pix = unflagged_pixels(job.scene, cam, 20)
-    Gm = np.zeros_like(G).reshape(-1, 3)
-    Gm[pix] = G.reshape(-1, 3)[pix]
-    check_backward(job.scene, cam, 20, Gm.reshape(G.shape), pix)
+    check_backward(job.scene, cam, 20, G)
 
 
-def test_backward_torus_benchmark_size_sparse_gradient():
+def test_backward_torus_benchmark_size_full_gradient():
+    """The 512x512, 10,000-kernel torus with its N(0,1) upstream gradient on
+    every pixel: every kernel and camera gradient against the oracle."""
     job = S.config_torus()
-    rng = np.random.default_rng(33)
-    cand = rng.choice(512 * 512, 3000, replace=False)
-    pix = unflagged_pixels(job.scene, job.camera, 20, pixels=cand)
-    G = np.zeros((512 * 512, 16), np.float32)
-    G[pix] = job.grad_image.reshape(-1, 16)[pix]
-    check_backward(job.scene, job.camera, 20, G.reshape(512, 512, 16), pix)
+    check_backward(job.scene, job.camera, 20, job.grad_image, name="backward torus10000_512px_C16_K20")
 
 
 def test_backward_without_reuse_matches_reuse():
@@ -244,7 +222,7 @@ def test_backward_without_reuse_matches_reuse():
     G = rng.standard_normal((64, 64, 3)).astype(np.float32)
     a = gpu_backward(job.scene, job.camera, 16, G, reuse=True)
     b = gpu_backward(job.scene, job.camera, 16, G, reuse=False)
-    for x, y in zip(a, b):
+    for x, y in zip(a[:4], b[:4]):
         np.testing.assert_allclose(x, y, rtol=1e-5, atol=1e-6 * (np.abs(x).max() + 1e-30))
 
 
@@ -254,10 +232,7 @@ def test_backward_k_buckets(K):
     scene = S.cloud_scene(rng, 700, 2, std_range=(0.02, 0.08))
     cam = S.identity_camera(40, 40.0, height=36)
     G = rng.standard_normal((36, 40, 2)).astype(np.float32)
-    pix = unflagged_pixels(scene, cam, K)
-    Gm = np.zeros_like(G).reshape(-1, 2)
-    Gm[pix] = G.reshape(-1, 2)[pix]
-    check_backward(scene, cam, K, Gm.reshape(G.shape), pix)
+    check_backward(scene, cam, K, G)
 
 
 def test_autograd_matches_direct_backward():
@@ -270,7 +245,7 @@ def test_autograd_matches_direct_backward():
     img = R.render(m, c, a, camv, K=16, height=64, width=64)
     G = torch.randn_like(img)
     (img * G).sum().backward()
-    gm, gc, ga, gk = gpu_backward(sc, job.camera, 16, G.cpu().numpy())
+    gm, gc, ga, gk, _ = gpu_backward(sc, job.camera, 16, G.cpu().numpy())
     np.testing.assert_allclose(m.grad.cpu().numpy(), gm, rtol=1e-5, atol=1e-6 * np.abs(gm).max())
     np.testing.assert_allclose(c.grad.cpu().numpy(), gc, rtol=1e-5, atol=1e-6 * np.abs(gc).max())
     np.testing.assert_allclose(a.grad.cpu().numpy(), ga, rtol=1e-5, atol=1e-6 * np.abs(ga).max())

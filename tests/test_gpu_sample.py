@@ -21,7 +21,7 @@ from paper_2205_15401_amd import _native as nat
 from paper_2205_15401_amd import render as R
 from paper_2205_15401_amd import scenes as S
 
-from parity import RTOL, to_dev
+from parity import RTOL, check_forward_vs_oracle, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -56,12 +56,20 @@ def check_sample(alpha_gpu, weight_gpu, scene, cam, K, eta, phi, kept_gpu=None, 
     """alpha (N, C) and weight sums (N,) of the GPU against the oracle."""
     N = scene.means.shape[0]
     H, W = cam.height, cam.width
-    ref = O.sample(scene.means, scene.covs, cam.as_vector(), H, W, K, phi, eta)
-    absref = O.sample(scene.means, scene.covs, cam.as_vector(), H, W, K, np.abs(phi), eta)
-    amb = ambiguous_kernels(ref.fwd, kept_gpu, K)
-    assert amb.size <= max(3, N // 50), f"{what}: {amb.size} kernels at near ties"
     keep = np.ones(N, bool)
-    keep[amb] = False
+    if kept_gpu is not None:
+        # the GPU's kept sets, checked against the oracle's selection, are the
+        # oracle sampler's sets: no kernel is left out
+        kg = np.asarray(kept_gpu).reshape(H * W, K)
+        check_forward_vs_oracle(None, None, kg, scene, cam, K, eta, name=f"sampler {what} kept sets")
+        ref = O.sample(scene.means, scene.covs, cam.as_vector(), H, W, K, phi, eta, given=kg)
+        absref = O.sample(scene.means, scene.covs, cam.as_vector(), H, W, K, np.abs(phi), eta, given=kg)
+    else:
+        ref = O.sample(scene.means, scene.covs, cam.as_vector(), H, W, K, phi, eta)
+        absref = O.sample(scene.means, scene.covs, cam.as_vector(), H, W, K, np.abs(phi), eta)
+        amb = ambiguous_kernels(ref.fwd, kept_gpu, K)
+        assert amb.size <= max(3, N // 50), f"{what}: {amb.size} kernels at near ties"
+        keep[amb] = False
     a = np.asarray(alpha_gpu, np.float64)
     seen = ref.den > 0
     unseen = keep & ~seen

@@ -75,7 +75,9 @@ def simulate(server, ex, reqs, check=None):
             check(server)
         ends = [b.handle["end"] for b in server.inflight.values()]
         nxt = [pending[i].arrival] if i < len(pending) else []
-        cand = [t for t in ends + nxt if t > ex.t]
+        waiting = list(server.queue) + [r for b in server.inflight.values() for r in b.reqs if r.done is None]
+        dls = [r.deadline for r in waiting if r.deadline is not None]
+        cand = [t for t in ends + nxt + dls if t > ex.t]
         if not cand:
             if server.idle() and i >= len(pending):
                 break
@@ -216,3 +218,67 @@ def test_serve_trace_in_real_time():
     assert len(srv.completed) == 200 and all(r.error is None for r in reqs)
     assert elapsed < 5.0
     assert all(r.latency >= 0 for r in reqs)
+
+
+def test_cancel_a_queued_and_an_inflight_request():
+    ex = FakeExecutor(SHAPES, n_slots=1, base=10e-3)
+    srv = Server(ex, 1 << 30)
+    a = Request(scene=0, camera=cam(32))
+    b = Request(scene=0, camera=cam(32))
+    assert srv.submit(a)
+    srv.pump()                                   # a is launched
+    assert srv.submit(b)                         # b waits for the slot
+    assert srv.cancel(b) and b.error == "cancelled" and b.done == ex.t
+    ex.t = 2e-3
+    assert srv.cancel(a) and a.error == "cancelled" and a.done == 2e-3 and a.image is None
+    assert srv.inflight_bytes > 0                # the batch still runs: its memory is held
+    assert not srv.cancel(a)                     # already done
+    c = Request(scene=0, camera=cam(16), arrival=3e-3)
+    simulate(srv, ex, [c])
+    assert c.error is None and c.image == ("image", c.rid)
+    assert [ids for _, _, ids, _ in ex.launches] == [[a.rid], [c.rid]]    # b never ran
+    assert a.image is None                       # the finished batch hands back nothing for a
+    assert srv.idle() and srv.inflight_bytes == 0
+    assert len(srv.completed) == 3
+
+
+def test_deadlines_fail_late_requests_and_the_server_runs_on():
+    ex = FakeExecutor(SHAPES, n_slots=1, base=10e-3)
+    long_ = Request(scene=0, camera=cam(32), arrival=0.0)
+    slow = Request(scene=0, camera=cam(32), arrival=0.0, deadline=4e-3)       # shares the first batch
+    queued = Request(scene=0, camera=cam(32), arrival=1e-3, deadline=5e-3)    # the slot is busy until 10 ms
+    fine = Request(scene=0, camera=cam(32), arrival=2e-3, deadline=1.0)
+    srv = Server(ex, 1 << 30)
+    simulate(srv, ex, [long_, slow, queued, fine])
+    assert slow.error == "deadline exceeded" and abs(slow.done - 4e-3) < 1e-12 and slow.image is None
+    assert queued.error == "deadline exceeded" and abs(queued.done - 5e-3) < 1e-12
+    assert long_.error is None and long_.image == ("image", long_.rid)
+    assert fine.error is None and fine.image == ("image", fine.rid)
+    launched = [rid for _, _, ids, _ in ex.launches for rid in ids]
+    assert queued.rid not in launched and slow.rid in launched
+    assert srv.idle() and srv.inflight_bytes == 0
+    st = latency_stats([long_, slow, queued, fine])
+    assert st["n"] == 2
+
+
+def test_admission_at_serving_sizes_under_a_tight_budget():
+    """The serving workload's shapes (scenes of 10k-200k kernels, 128^2 to
+    1024^2 images, half gradient requests) under a budget that holds little
+    more than one of the largest requests: the budget is never exceeded,
+    every request completes, and the largest ones are not starved."""
+    shapes = {i: (n, 3) for i, n in enumerate((10_000, 25_000, 50_000, 100_000, 150_000, 200_000))}
+    ex = FakeExecutor(shapes, n_slots=2, base=0.5e-3, per_ray=2e-9)
+    rng = np.random.default_rng(5)
+    reqs = random_requests(rng, 600, scenes=tuple(shapes), sizes=(128, 256, 512, 1024), rate=800.0)
+    biggest = max(ex.item_bytes(r) for r in reqs)
+    budget = int(1.3 * biggest)
+    srv = Server(ex, budget, max_batch_items=64)
+
+    def check(s):
+        assert s.inflight_bytes <= budget
+
+    simulate(srv, ex, reqs, check)
+    assert all(r.error is None and r.image is not None for r in reqs)
+    big = [r for r in reqs if r.rays == 1024 * 1024 and r.backward]
+    assert big and all(r.done is not None for r in big)
+    assert srv.peak_bytes > 0.5 * budget
