@@ -107,9 +107,9 @@ def _lib():
             I = ctypes.c_int
             L = ctypes.c_int64
             Dbl = ctypes.c_double
-            lib.oracle_forward.argtypes = [P, P, P, I, I, P, I, I, Dbl, I, P, L, I, P, P, P, P, P, P, P, P]
+            lib.oracle_forward.argtypes = [P, P, P, I, I, P, I, I, Dbl, I, P, L, I, P, P, P, P, P, P, P, P, I]
             lib.oracle_forward.restype = I
-            lib.oracle_backward.argtypes = [P, P, P, I, I, P, I, I, Dbl, I, P, L, P, I, P, P, P, P, P, P, P, P, I, P]
+            lib.oracle_backward.argtypes = [P, P, P, I, I, P, I, I, Dbl, I, P, L, P, I, P, P, P, P, P, P, P, P, I, P, I]
             lib.oracle_backward.restype = I
             lib.oracle_quadrature.argtypes = [P, P, I, P, I, I, Dbl, I, P, L, I, I, P, P, P]
             lib.oracle_quadrature.restype = I
@@ -165,11 +165,13 @@ def _given(given, n: int, K: int):
 
 
 def forward(means, covs, attrs, cam_vec, H: int, W: int, K: int, eta: float = 0.01,
-            pixels: Optional[Sequence[int]] = None, threads: int = 0, given=None) -> ForwardResult:
+            pixels: Optional[Sequence[int]] = None, threads: int = 0, given=None,
+            binned: bool = False) -> ForwardResult:
     """Render the given pixels (linear i*W + j; None = every pixel, row-major).
     given: optional (n_pix, K) kept sets chosen elsewhere (-1 padded); the
     selection (step 4) is then skipped and the blend runs on exactly those
-    sets (n_pass = -1, flags = 0)."""
+    sets (n_pass = -1, flags = 0).  binned: step 4 on the candidates of
+    16x16 screen tiles (same results, less work; a timing mode)."""
     m, c, a, cv = _f64(means), _f64(covs), _f64(attrs), _f64(cam_vec)
     N, C = m.shape[0], a.shape[1]
     assert c.shape == (N, 6) and a.shape[0] == N and cv.size == 15
@@ -178,7 +180,8 @@ def forward(means, covs, attrs, cam_vec, H: int, W: int, K: int, eta: float = 0.
     r = ForwardResult(n, C, K)
     rc = _lib().oracle_forward(_ptr(m), _ptr(c), _ptr(a), N, C, _ptr(cv), H, W, float(eta), K,
                                _ptr(pix), n, threads, _ptr(r.image), _ptr(r.wsum), _ptr(r.absum),
-                               _ptr(r.kept_idx), _ptr(r.kept_rec), _ptr(r.n_pass), _ptr(r.flags), _ptr(gv))
+                               _ptr(r.kept_idx), _ptr(r.kept_rec), _ptr(r.n_pass), _ptr(r.flags), _ptr(gv),
+                               int(bool(binned)))
     if rc < 0:
         raise ValueError("oracle_forward: bad arguments")
     r.n_invalid = rc
@@ -204,7 +207,7 @@ BLOCK_RHO = 2    # ablation: no gradient through the factor e^{q_k} of Eq. 8
 
 def backward(means, covs, attrs, cam_vec, H: int, W: int, K: int, grad, eta: float = 0.01,
              pixels: Optional[Sequence[int]] = None, threads: int = 0, mode: int = 0,
-             given=None) -> BackwardResult:
+             given=None, binned: bool = False) -> BackwardResult:
     """Gradients of sum_p <grad_p, C_p> over the given pixels (grad is
     (n_pix, C), or (H, W, C) when pixels is None).  mode: 0, or BLOCK_T and/or
     BLOCK_RHO, the gradient ablations of the paper's pose-estimation ablation
@@ -220,7 +223,7 @@ def backward(means, covs, attrs, cam_vec, H: int, W: int, K: int, grad, eta: flo
                                 _ptr(pix), n, _ptr(g), threads,
                                 _ptr(r.means), _ptr(r.covs), _ptr(r.attrs), _ptr(r.camera),
                                 _ptr(r.abs_means), _ptr(r.abs_covs), _ptr(r.abs_attrs), _ptr(r.abs_camera),
-                                int(mode), _ptr(gv))
+                                int(mode), _ptr(gv), int(bool(binned)))
     if rc < 0:
         raise ValueError("oracle_backward: bad arguments")
     r.n_invalid = rc

@@ -219,11 +219,12 @@ static double optical_depth(double t, const cand_t* set, int n) {
 /* Steps 3-4 for one pixel: trace every kernel, keep those with e^q > eta and
  * l > 0, sort by (l, index), keep the first K.  Returns K_eff; writes the
  * number of passing kernels and the near-tie / near-threshold flags. */
-static int select_kernels(const ker_t* ks, int N, const double D[3], double lneta, int K, cand_t* scratch,
-                          int* n_pass_out, int* flags_out) {
+static int select_kernels(const ker_t* ks, int N, const int* list, const double D[3], double lneta, int K,
+                          cand_t* scratch, int* n_pass_out, int* flags_out) {
     int n = 0, flags = 0;
     double near_l = INFINITY;   /* smallest l among kernels within 1e-5 of the threshold */
-    for (int k = 0; k < N; ++k) {
+    for (int t = 0; t < N; ++t) {
+        const int k = list ? list[t] : t;     /* every kernel, or a tile's candidates */
         if (!ks[k].valid) continue;
         double l, q, a;
         trace_kernel(&ks[k], D, &l, &q, &a);
@@ -245,6 +246,91 @@ static int select_kernels(const ker_t* ks, int N, const double D[3], double lnet
     *n_pass_out = n;
     *flags_out = flags;
     return keff;
+}
+
+/* Optional coarse stage for timing (the CPU baseline's binned mode): the
+ * paper's coarse-to-fine rendering (Sec. 3.3; App. A.3) skips kernels that
+ * cannot reach a pixel.  Here each kernel's candidates are the 16x16 screen
+ * tiles met by the projection of a sphere around its centre that contains
+ * every point where (X - M)^T S (X - M) <= 2 ln(1/eta) + 1e-4: radius^2 =
+ * (2 ln(1/eta) + 1e-4) trace(Sigma), trace(Sigma) >= its largest
+ * eigenvalue.  A kernel with q >= ln(eta) - 5e-5 at a pixel has its peak on
+ * that pixel's ray inside the sphere, so no kernel that passes the
+ * threshold or could set a flag is skipped, and the results equal the
+ * brute-force ones bit for bit (the candidates keep ascending index order).
+ * A sphere that reaches z <= 1e-9 covers the whole image. */
+#define OR_BIN 16
+
+typedef struct {
+    int ntx, nty;
+    int64_t* off;     /* [ntx*nty + 1] */
+    int* idx;         /* kernel indices per tile, ascending */
+} bins_t;
+
+static void sphere_rows(double Mx, double Mz, double r, double F, double O, double* lo, double* hi) {
+    /* tangent planes x = k z of the sphere: (Mx - k Mz)^2 = r^2 (1 + k^2) */
+    const double a = Mz * Mz - r * r, d = sqrt(Mx * Mx + Mz * Mz - r * r);
+    const double k1 = (Mx * Mz - r * d) / a, k2 = (Mx * Mz + r * d) / a;
+    *lo = O + F * (k1 < k2 ? k1 : k2);
+    *hi = O + F * (k1 < k2 ? k2 : k1);
+}
+
+static void build_bins(const ker_t* ks, const double* covs, int N, const cam_t* cam, double eta, bins_t* b) {
+    const int H = cam->H, W = cam->W;
+    b->ntx = (W + OR_BIN - 1) / OR_BIN;
+    b->nty = (H + OR_BIN - 1) / OR_BIN;
+    const int nt = b->ntx * b->nty;
+    int* box = (int*)malloc(sizeof(int) * 4 * (size_t)(N > 0 ? N : 1));
+    b->off = (int64_t*)calloc((size_t)nt + 1, sizeof(int64_t));
+    const double grow = 2.0 * log(1.0 / eta) + 1e-4;
+    for (int n = 0; n < N; ++n) {
+        int* bx = box + 4 * n;
+        bx[0] = 1; bx[1] = 0; bx[2] = 1; bx[3] = 0;           /* empty */
+        if (!ks[n].valid) continue;
+        const double* c = covs + 6 * (size_t)n;
+        const double r = sqrt(grow * (c[0] + c[3] + c[5]));
+        const double* M = ks[n].M;
+        double i0 = 0, i1 = H - 1, j0 = 0, j1 = W - 1;
+        if (M[2] - r > 1e-9) {
+            double lo, hi;
+            sphere_rows(M[0], M[2], r, cam->F, cam->Oy, &lo, &hi);
+            i0 = fmax(i0, floor(lo) - 1.0);
+            i1 = fmin(i1, ceil(hi) + 1.0);
+            sphere_rows(M[1], M[2], r, cam->F, cam->Ox, &lo, &hi);
+            j0 = fmax(j0, floor(lo) - 1.0);
+            j1 = fmin(j1, ceil(hi) + 1.0);
+        }
+        if (i0 > i1 || j0 > j1) continue;
+        bx[0] = (int)i0 / OR_BIN; bx[1] = (int)i1 / OR_BIN;
+        bx[2] = (int)j0 / OR_BIN; bx[3] = (int)j1 / OR_BIN;
+        for (int ti = bx[0]; ti <= bx[1]; ++ti)
+            for (int tj = bx[2]; tj <= bx[3]; ++tj) b->off[ti * b->ntx + tj + 1] += 1;
+    }
+    for (int t = 0; t < nt; ++t) b->off[t + 1] += b->off[t];
+    b->idx = (int*)malloc(sizeof(int) * (size_t)(b->off[nt] > 0 ? b->off[nt] : 1));
+    int64_t* cur = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nt > 0 ? nt : 1));
+    for (int t = 0; t < nt; ++t) cur[t] = b->off[t];
+    for (int n = 0; n < N; ++n) {                              /* ascending n in every tile */
+        const int* bx = box + 4 * n;
+        for (int ti = bx[0]; ti <= bx[1]; ++ti)
+            for (int tj = bx[2]; tj <= bx[3]; ++tj) b->idx[cur[ti * b->ntx + tj]++] = n;
+    }
+    free(cur);
+    free(box);
+}
+
+static void free_bins(bins_t* b) {
+    free(b->off);
+    free(b->idx);
+}
+
+/* Step 4 on every kernel, or (bins) on the candidates of the pixel's tile. */
+static int select_pixel(const ker_t* ks, int N, const bins_t* bins, int i, int j, const double D[3],
+                        double lneta, int K, cand_t* scratch, int* n_pass_out, int* flags_out) {
+    if (!bins) return select_kernels(ks, N, NULL, D, lneta, K, scratch, n_pass_out, flags_out);
+    const int t = (i / OR_BIN) * bins->ntx + j / OR_BIN;
+    return select_kernels(ks, (int)(bins->off[t + 1] - bins->off[t]), bins->idx + bins->off[t], D, lneta, K,
+                          scratch, n_pass_out, flags_out);
 }
 
 /* Step 4 replaced by a given kept set (the set another implementation
@@ -323,13 +409,15 @@ static int nthreads_of(int req) {
  * is then skipped and steps 5-6 run on exactly these sets (n_pass = -1,
  * flags = 0); an index out of range, of a skipped kernel or repeated within
  * a pixel is a bad argument.
+ * binned: take step 4's candidates from 16x16 screen tiles (see build_bins;
+ * same results, less work; a timing mode of the CPU baseline).
  * Returns the number of skipped (non-SPD / non-finite) kernels, or -1 on bad
  * arguments. */
 int oracle_forward(const double* means, const double* covs, const double* attrs, int N, int C,
                    const double* cam15, int H, int W, double eta, int K,
                    const int64_t* pix, int64_t n_pix, int nthreads,
                    double* image, double* wsum, double* absum, int32_t* kept_idx, double* kept_rec,
-                   int32_t* n_pass, int32_t* flags, const int32_t* given) {
+                   int32_t* n_pass, int32_t* flags, const int32_t* given, int binned) {
     if (check_args(N, C, H, W, eta, K)) return -1;
     cam_t cam;
     load_camera(cam15, H, W, &cam);
@@ -341,6 +429,9 @@ int oracle_forward(const double* means, const double* covs, const double* attrs,
         free(ks);
         return -1;
     }
+    bins_t bins;
+    if (binned && !given) build_bins(ks, covs, N, &cam, eta, &bins);
+    const bins_t* bp = (binned && !given) ? &bins : NULL;
 
 #pragma omp parallel num_threads(nthreads_of(nthreads))
     {
@@ -355,7 +446,7 @@ int oracle_forward(const double* means, const double* covs, const double* attrs,
             pixel_ray(&cam, i, j, D);
             int np_ = -1, fl = 0;
             int keff = given ? given_kernels(ks, D, given + p * K, K, scratch)
-                             : select_kernels(ks, N, D, lneta, K, scratch, &np_, &fl);
+                             : select_pixel(ks, N, bp, i, j, D, lneta, K, scratch, &np_, &fl);
             blend_weights(scratch, keff, E, Wt);
             double ws = 0.0;
             for (int k = 0; k < keff; ++k) ws += Wt[k];
@@ -392,6 +483,7 @@ int oracle_forward(const double* means, const double* covs, const double* attrs,
         free(E);
         free(Wt);
     }
+    if (bp) free_bins(&bins);
     free(ks);
     return n_invalid;
 }
@@ -424,13 +516,15 @@ void oracle_transmittance(const double* rec, int n, const double* t, int nt, dou
  * ablations of the paper's pose-estimation ablation table).
  * given (optional): kept sets chosen elsewhere, as for oracle_forward; the
  * gradients are then those of the forward on exactly these sets.
+ * binned: step 4 on the candidates of 16x16 screen tiles, as for
+ * oracle_forward.
  * Returns the number of skipped kernels or -1. */
 int oracle_backward(const double* means, const double* covs, const double* attrs, int N, int C,
                     const double* cam15, int H, int W, double eta, int K,
                     const int64_t* pix, int64_t n_pix, const double* grad_pix, int nthreads,
                     double* g_means, double* g_covs, double* g_attrs, double* g_cam,
                     double* a_means, double* a_covs, double* a_attrs, double* a_cam, int grad_mode,
-                    const int32_t* given) {
+                    const int32_t* given, int binned) {
     if (check_args(N, C, H, W, eta, K)) return -1;
     cam_t cam;
     load_camera(cam15, H, W, &cam);
@@ -442,6 +536,9 @@ int oracle_backward(const double* means, const double* covs, const double* attrs
         free(ks);
         return -1;
     }
+    bins_t bins;
+    if (binned && !given) build_bins(ks, covs, N, &cam, eta, &bins);
+    const bins_t* bp = (binned && !given) ? &bins : NULL;
     const int nt = nthreads_of(nthreads);
     const size_t per = (size_t)N * (3 + 6 + (size_t)C) + 15;   /* one thread's accumulators */
     double* acc = (double*)calloc(per * (size_t)nt * 2, sizeof(double));
@@ -483,7 +580,7 @@ int oracle_backward(const double* means, const double* covs, const double* attrs
             pixel_ray(&cam, i, j, D);
             int np_, fl;
             int keff = given ? given_kernels(ks, D, given + p * K, K, kept)
-                             : select_kernels(ks, N, D, lneta, K, kept, &np_, &fl);
+                             : select_pixel(ks, N, bp, i, j, D, lneta, K, kept, &np_, &fl);
             if (keff == 0) continue;
             blend_weights(kept, keff, E, Wt);
             /* C = sum_k W_k c_k:  dL/dc_k = W_k G;  dL/dW_k = G . c_k */
@@ -645,6 +742,7 @@ int oracle_backward(const double* means, const double* covs, const double* attrs
             if (out_a[b]) out_a[b][e] = sa;
         }
     }
+    if (bp) free_bins(&bins);
     free(acc);
     free(ks);
     return n_invalid;
@@ -681,7 +779,7 @@ int oracle_quadrature(const double* means, const double* covs, int N, const doub
             double D[3];
             pixel_ray(&cam, i, j, D);
             int np_, fl;
-            int keff = select_kernels(ks, N, D, lneta, K, kept, &np_, &fl);
+            int keff = select_kernels(ks, N, NULL, D, lneta, K, kept, &np_, &fl);
             blend_weights(kept, keff, E, Wt);
             double t0 = INFINITY, t1 = -INFINITY, msum = 0.0;
             for (int m = 0; m < keff; ++m) {
