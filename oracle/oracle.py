@@ -101,8 +101,13 @@ def _lib():
     global _LIB
     with _LOCK:
         if _LIB is None:
-            build()
-            lib = ctypes.CDLL(_LIB_PATH)
+            # VOGE_ORACLE_LIB: a build of voge_oracle.c made elsewhere (the
+            # sanitizer run of the CPU tests), loaded as it is
+            path = os.environ.get("VOGE_ORACLE_LIB")
+            if not path:
+                build()
+                path = _LIB_PATH
+            lib = ctypes.CDLL(path)
             P = ctypes.c_void_p
             I = ctypes.c_int
             L = ctypes.c_int64

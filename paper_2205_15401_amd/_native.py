@@ -77,12 +77,15 @@ _LOCK = threading.Lock()
 _LIB = None
 
 
-def load(path: str = LIB_PATH):
-    """Load libvoge.so and declare its signatures."""
+def load(path: str = None):
+    """Load libvoge.so and declare its signatures.  VOGE_LIBRARY names another
+    build of the same sources (the sanitizer run of the host-side tests)."""
     global _LIB
     with _LOCK:
         if _LIB is not None:
             return _LIB
+        if path is None:
+            path = os.environ.get("VOGE_LIBRARY") or LIB_PATH
         if not os.path.exists(path):
             raise RuntimeError(f"{path} is not built; run `python -m paper_2205_15401_amd.build`")
         lib = ctypes.CDLL(path)
