@@ -243,6 +243,13 @@ BatchPlan plan_batch(const ItemShape* shapes, int n) {
     p.off_kl_T = take(4 * nl);
     p.off_kl_r = take(4 * nl);
     p.off_kl_i = take(4 * nl);
+    p.tile_cap = (uint32_t)std::min<size_t>(tile_capacity(nk, nt), 0xFFFFFFF0u);
+    p.tscan_blocks = (int)((nt + TSCAN_BLOCK - 1) / TSCAN_BLOCK);
+    p.off_tcnt = take(4 * nt);
+    p.off_tcur = take(4 * nt);
+    p.off_toff = take(4 * (nt + 1));
+    p.off_tsum = take(4 * ((size_t)p.tscan_blocks + 1));
+    p.off_tlist = take(4 * (size_t)p.tile_cap);
     p.fwd_bytes = off;
     // gM [3 nk] | gS [6 nk] | gA [total_attr]: one contiguous range, cleared at once
     p.off_grads = take(sizeof(float) * (9 * nk + p.total_attr));
@@ -323,6 +330,7 @@ struct BatchWs {
     double* camP;
     float4* bw;
     float* bwl;
+    uint32_t *tcnt, *tcur, *toff, *tsum, *tlist;
 };
 
 BatchWs carve_batch(void* ws, const voge::BatchPlan& p) {
@@ -355,6 +363,11 @@ BatchWs carve_batch(void* ws, const voge::BatchPlan& p) {
     w.camP = reinterpret_cast<double*>(b + p.off_camP);
     w.bw = reinterpret_cast<float4*>(b + p.off_bw);
     w.bwl = reinterpret_cast<float*>(b + p.off_bwl);
+    w.tcnt = reinterpret_cast<uint32_t*>(b + p.off_tcnt);
+    w.tcur = reinterpret_cast<uint32_t*>(b + p.off_tcur);
+    w.toff = reinterpret_cast<uint32_t*>(b + p.off_toff);
+    w.tsum = reinterpret_cast<uint32_t*>(b + p.off_tsum);
+    w.tlist = reinterpret_cast<uint32_t*>(b + p.off_tlist);
     return w;
 }
 
@@ -379,6 +392,10 @@ voge::ItemDev item_record(const voge::BatchPlan& p, int j, const voge_item_t& sr
     t.cx = src.camera.cx;
     t.cy = src.camera.cy;
     t.rad2 = -2.0 * std::log((double)src.params.eta);
+    t.tcnt = w.tcnt + ip.tile_start;
+    t.toff = w.toff + ip.tile_start;
+    t.tlist = w.tlist;
+    t.tcap = p.tile_cap;
     t.attrs = src.attrs;
     t.keff = w.keff + (size_t)ip.tile_start * voge::TILE_THREADS;
     t.kl_l = w.kl_l + lo;
@@ -441,6 +458,11 @@ voge::BatchDev batch_dev(const voge::BatchPlan& p, const BatchWs& w) {
     b.epi_item = w.epi_item;
     b.item_bits = p.item_bits;
     b.hdr = w.hdr;
+    b.tcnt = w.tcnt;
+    b.tcur = w.tcur;
+    b.toff = w.toff;
+    b.tlist = w.tlist;
+    b.tcap = p.tile_cap;
     return b;
 }
 
@@ -469,8 +491,8 @@ int launch_compute(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, 
     if (fwd_part) {
         {
             ProfScope ps = scope("prep");
-            voge::launch_prep(b, p.total_pblk, p.total_kern, p.max_n, w.keys, w.vals, w.keys2, w.vals2, w.hist,
-                              w.cull, w.rec, w.geo, s);
+            voge::launch_prep(b, p.total_pblk, p.total_kern, p.max_n, p.total_tiles, p.tscan_blocks, w.keys, w.vals,
+                              w.keys2, w.vals2, w.hist, w.tsum, w.cull, w.rec, w.geo, s);
             if (int rc = hip_check(hipGetLastError(), "prep launch")) return rc;
         }
         {

@@ -172,11 +172,103 @@ __global__ __launch_bounds__(PREP_THREADS) void k_prep_records(BatchDev B, int t
         if (i0 <= i1 && j0 <= j1) {
             cr.i0 = (int16_t)i0; cr.i1 = (int16_t)i1;
             cr.j0 = (int16_t)j0; cr.j1 = (int16_t)j1;
+            // coarse stage: one count per screen tile the box meets
+            const int ntx = (W + TILE - 1) / TILE;
+            for (int ti = cr.i0 / TILE; ti <= cr.i1 / TILE; ++ti)
+                for (int tj = cr.j0 / TILE; tj <= cr.j1 / TILE; ++tj)
+                    atomicAdd(&B.tcnt[it.tile_start + ti * ntx + tj], 1u);
         }
     }
     cull[r] = cr;
     rec[r] = tr;
     geo[r] = g;
+}
+
+// ------------------------------------------------------- coarse-stage bins
+// The tile counts of k_prep_records are scanned into list offsets (blocks of
+// TSCAN_BLOCK counts: block sums, one scan of the sums, block scans); then
+// every kernel writes its item-local rank into the list of each tile its
+// screen box meets.  The order inside a tile's list is whatever the atomics
+// give: select sorts a list by rank (= depth order) in LDS before it scans.
+// A tile whose list would end past the capacity is not binned (select then
+// scans all of its item's records), so a capacity shortfall costs time only.
+constexpr int TSCAN_THREADS = 256;
+constexpr int TSCAN_PER = TSCAN_BLOCK / TSCAN_THREADS;
+
+__global__ __launch_bounds__(TSCAN_THREADS) void k_tscan_sums(const uint32_t* __restrict__ cnt, int n,
+                                                               uint32_t* __restrict__ bsum) {
+    __shared__ uint32_t red[TSCAN_THREADS / WAVE];
+    const int tid = threadIdx.x;
+    const int i0 = blockIdx.x * TSCAN_BLOCK + tid * TSCAN_PER;
+    uint32_t v = 0;
+#pragma unroll
+    for (int j = 0; j < TSCAN_PER; ++j) v += i0 + j < n ? cnt[i0 + j] : 0u;
+    for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (tid % WAVE == 0) red[tid / WAVE] = v;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < TSCAN_THREADS / WAVE; ++w) t += red[w];
+        bsum[blockIdx.x] = t;
+    }
+}
+
+// Block b: the exclusive scan of its counts plus the scanned block sum;
+// clears the scatter cursors; the last block writes the grand total at n.
+__global__ __launch_bounds__(TSCAN_THREADS) void k_tscan_final(const uint32_t* __restrict__ cnt, int n,
+                                                                const uint32_t* __restrict__ bsum, int nblk,
+                                                                uint32_t* __restrict__ off, uint32_t* __restrict__ cur) {
+    __shared__ uint32_t buf[TSCAN_THREADS];
+    const int tid = threadIdx.x;
+    const int i0 = blockIdx.x * TSCAN_BLOCK + tid * TSCAN_PER;
+    uint32_t v[TSCAN_PER];
+    uint32_t run = 0;
+#pragma unroll
+    for (int j = 0; j < TSCAN_PER; ++j) {
+        v[j] = i0 + j < n ? cnt[i0 + j] : 0u;
+        run += v[j];
+    }
+    buf[tid] = run;
+    __syncthreads();
+    for (int o = 1; o < TSCAN_THREADS; o <<= 1) {
+        const uint32_t y = tid >= o ? buf[tid - o] : 0u;
+        __syncthreads();
+        buf[tid] += y;
+        __syncthreads();
+    }
+    uint32_t base = bsum[blockIdx.x] + buf[tid] - run;
+#pragma unroll
+    for (int j = 0; j < TSCAN_PER; ++j) {
+        if (i0 + j < n) {
+            off[i0 + j] = base;
+            cur[i0 + j] = 0u;
+        }
+        base += v[j];
+    }
+    if (blockIdx.x == nblk - 1 && tid == 0) off[n] = bsum[nblk];
+}
+
+__global__ __launch_bounds__(PREP_THREADS) void k_bin_scatter(BatchDev B, int total,
+                                                               const uint32_t* __restrict__ skeys,
+                                                               const CullRec* __restrict__ cull) {
+    const int r = blockIdx.x * PREP_THREADS + threadIdx.x;
+    if (r >= total) return;
+    const int ib = B.item_bits;
+    const int item = ib ? (int)(skeys[r] >> (32 - ib)) : 0;
+    const ItemDev& it = B.items[item];
+    const CullRec cr = cull[r];
+    if (cr.i0 > cr.i1 || cr.j0 > cr.j1) return;
+    const int ntx = (it.t.W + TILE - 1) / TILE;
+    const uint32_t rank = (uint32_t)(r - it.kern_start);
+    for (int ti = cr.i0 / TILE; ti <= cr.i1 / TILE; ++ti) {
+        for (int tj = cr.j0 / TILE; tj <= cr.j1 / TILE; ++tj) {
+            const int t = it.tile_start + ti * ntx + tj;
+            const uint32_t o = B.toff[t];
+            if (o + B.tcnt[t] > B.tcap) continue;          // tile not binned: nothing to write
+            const uint32_t pos = atomicAdd(&B.tcur[t], 1u);
+            B.tlist[o + pos] = rank;
+        }
+    }
 }
 
 // ------------------------------------------------------------------ sort
@@ -379,10 +471,28 @@ void launch_init(const InitPack& pack, int first, int count, bool from_args, Ite
                        pblk_item, epi_item, hdr, clear_status ? 1 : 0, clear_header ? 1 : 0);
 }
 
-void launch_prep(const BatchDev& b, int total_pblk, int total_kern, int max_n, uint32_t* keys, uint32_t* vals,
-                 uint32_t* keys2, uint32_t* vals2, uint32_t* hist, CullRec* cull, TraceRec* rec, GeoRec* geo,
-                 hipStream_t s) {
-    if (total_kern <= 0) return;
+// The bins of every item's tiles from the records' screen boxes (the counts
+// were taken by k_prep_records).
+static void launch_bins(const BatchDev& b, int total_kern, int total_tiles, int tscan_blocks, const uint32_t* skeys,
+                        uint32_t* tsum, const CullRec* cull, hipStream_t s) {
+    if (total_tiles <= 0) return;
+    hipLaunchKernelGGL(k_tscan_sums, dim3(tscan_blocks), dim3(TSCAN_THREADS), 0, s, b.tcnt, total_tiles, tsum);
+    // the scan of the block sums in place, their total at tsum[tscan_blocks]
+    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(SCAN_THREADS), 0, s, tsum, tsum + tscan_blocks, tscan_blocks);
+    hipLaunchKernelGGL(k_tscan_final, dim3(tscan_blocks), dim3(TSCAN_THREADS), 0, s, b.tcnt, total_tiles, tsum,
+                       tscan_blocks, b.toff, b.tcur);
+    const int blocks = (total_kern + PREP_THREADS - 1) / PREP_THREADS;
+    if (blocks > 0) hipLaunchKernelGGL(k_bin_scatter, dim3(blocks), dim3(PREP_THREADS), 0, s, b, total_kern, skeys, cull);
+}
+
+void launch_prep(const BatchDev& b, int total_pblk, int total_kern, int max_n, int total_tiles, int tscan_blocks,
+                 uint32_t* keys, uint32_t* vals, uint32_t* keys2, uint32_t* vals2, uint32_t* hist, uint32_t* tsum,
+                 CullRec* cull, TraceRec* rec, GeoRec* geo, hipStream_t s) {
+    launch_fill_u32(b.tcnt, (size_t)total_tiles, 0u, s);
+    if (total_kern <= 0) {
+        launch_bins(b, 0, total_tiles, tscan_blocks, keys, tsum, cull, s);
+        return;
+    }
     hipLaunchKernelGGL(k_prep_keys, dim3(total_pblk), dim3(PREP_THREADS), 0, s, b, keys, vals);
     const int N = total_kern;
     const int blocks = (N + PREP_THREADS - 1) / PREP_THREADS;
@@ -390,6 +500,7 @@ void launch_prep(const BatchDev& b, int total_pblk, int total_kern, int max_n, u
         // every item sorts in one workgroup's LDS
         hipLaunchKernelGGL(k_sort_items, dim3(b.n_items), dim3(ISORT_THREADS), 0, s, b, keys, vals);
         hipLaunchKernelGGL(k_prep_records, dim3(blocks), dim3(PREP_THREADS), 0, s, b, N, keys, vals, cull, rec, geo);
+        launch_bins(b, N, total_tiles, tscan_blocks, keys, tsum, cull, s);
         return;
     }
     // four stable 8-bit passes: keys/vals -> keys2/vals2 -> keys/vals -> ...
@@ -409,6 +520,7 @@ void launch_prep(const BatchDev& b, int total_pblk, int total_kern, int max_n, u
         t = vin; vin = vout; vout = t;
     }
     hipLaunchKernelGGL(k_prep_records, dim3(blocks), dim3(PREP_THREADS), 0, s, b, N, kin, vin, cull, rec, geo);
+    launch_bins(b, N, total_tiles, tscan_blocks, kin, tsum, cull, s);
 }
 
 }  // namespace voge

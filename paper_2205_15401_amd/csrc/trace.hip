@@ -235,9 +235,43 @@ __device__ __forceinline__ int wave_max_keff(int keff) {
 // registers are all taken by the keys).
 __host__ __device__ constexpr int cull_ahead(int KB) { return KB >= 64 ? 1 : 3; }
 
+// Longest tile list select sorts in LDS (a longer one is scanned unbinned).
+constexpr int BIN_MAX = 2048;
+
+// The tile's bin, sorted by rank (= depth order) into s_rank[0 .. n); returns
+// n, or -1 when the tile is not binned (its list is longer than BIN_MAX or
+// did not fit the pair list).  Every lane of the workgroup calls it.
+__device__ __forceinline__ int load_bin(const TraceArgs& A, int tile, uint32_t* s_rank) {
+    const int tid = threadIdx.x;
+    const uint32_t cnt = A.tcnt[tile], off = A.toff[tile];
+    if (cnt > (uint32_t)BIN_MAX || off + cnt > A.tcap) return -1;
+    const int n = (int)cnt;
+    int n2 = 2;
+    while (n2 < n) n2 <<= 1;
+    const auto src = gp(A.tlist) + off;
+    for (int i = tid; i < n2; i += TILE_THREADS) s_rank[i] = i < n ? src[i] : 0xFFFFFFFFu;
+    __syncthreads();
+    // bitonic sort, ascending (ranks are distinct; padding sorts last)
+    for (int size = 2; size <= n2 && n > 1; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = tid; i < (n2 >> 1); i += TILE_THREADS) {
+                const int lo = 2 * i - (i & (stride - 1)), hi = lo + stride;
+                const uint32_t a = s_rank[lo], b = s_rank[hi];
+                if ((a > b) == ((lo & size) == 0)) {
+                    s_rank[lo] = b;
+                    s_rank[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    return n;
+}
+
 template <int KB>
 __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
     constexpr int CULL_AHEAD = cull_ahead(KB);
+    __shared__ uint32_t s_rank[BIN_MAX];
     const int tid = threadIdx.x, lane = tid % WAVE;
     const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);   // uniform in the wave
     const int ntx = (A.W + TILE - 1) / TILE;
@@ -245,6 +279,11 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
     const int bi0 = (tile / ntx) * TILE + (wave >> 1) * 8;            // this wave's block
     const int bj0 = (tile % ntx) * TILE + (wave & 1) * 8;
     const ConstRecPtr crec = const_rec(A.rec);
+    // the candidate stream: the tile's bin in depth order, or (a tile that is
+    // not binned) every record of the item
+    const int n_bin = load_bin(A, tile, s_rank);
+    const bool binned = n_bin >= 0;
+    const int n_list = binned ? n_bin : A.N;
 
     uint64_t key[KB];
 #pragma unroll
@@ -254,12 +293,13 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
     int ub = 0;                                  // the wave's largest nkey (uniform)
     int kslot = 0;                               // the slot of kth
     bool done = !P.valid;
-    // One step: the records base .. base+63 whose boxes meet the block
-    // (hit); returns true once the block is done.
-    auto step = [&](const int base, const bool hit) -> bool {
-        uint64_t mm = wave_ballot(hit);          // this step's candidates, one bit per record
+    // One step: the list entries base .. base+63 (lane j holds the rank of
+    // entry base + j in ent) whose boxes meet the block (hit); returns true
+    // once the block is done.
+    auto step = [&](const int base, const bool hit, const int ent) -> bool {
+        uint64_t mm = wave_ballot(hit);          // this step's candidates, one bit per entry
         if (mm != 0) {
-            int rank = base + (int)__builtin_ctzll(mm);
+            int rank = __builtin_amdgcn_readlane(ent, (int)__builtin_ctzll(mm));
             mm &= mm - 1;
             TraceRec R = load_rec(crec + rank);
             for (;;) {
@@ -277,7 +317,7 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
                 const bool ins = !done & (q2 < A.rad2) & (l > 0.0) & (nk < kth);
                 // the next candidate's record is in flight while this one is inserted
                 const bool more = mm != 0;
-                const int rank_n = more ? base + (int)__builtin_ctzll(mm) : rank;
+                const int rank_n = more ? __builtin_amdgcn_readlane(ent, (int)__builtin_ctzll(mm)) : rank;
                 mm &= mm - 1;
                 __builtin_amdgcn_sched_barrier(0);
                 const TraceRec Rn = load_rec(crec + rank_n);
@@ -304,11 +344,12 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
             }
         }
         // the block is done when every pixel is, or holds K kernels nearer
-        // than the next record's depth bound (possible once a buffer is full)
+        // than the next entry's depth bound (possible once a buffer is full)
         const int nb = base + WAVE;
         bool fin = done;
-        if (ub >= A.K && nb < A.N) {
-            const float next_tlo = crec[nb].tlo;
+        if (ub >= A.K && nb < n_list) {
+            const int next = binned ? __builtin_amdgcn_readfirstlane((int)s_rank[nb]) : nb;
+            const float next_tlo = crec[next].tlo;
             fin = fin | ((kth != ~0ull) & ((double)next_tlo > key_upper_l(kth)));
         }
         return wave_all(fin);
@@ -320,13 +361,19 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
     // is reloaded right after its use, and every lane loads (lanes past the
     // last record reload that record, and r < N rejects them), so that
     // waiting for the oldest load leaves the younger ones in flight.
-    const int n_scan = wave_all(done) ? 0 : A.N;   // a block wholly outside the image scans nothing
-    const int last = A.N - 1;
+    // (entries past the end reload the last one, and r < n_list rejects them)
+    const int n_scan = wave_all(done) ? 0 : n_list;   // a block wholly outside the image scans nothing
+    const int last = n_list - 1;
     const auto cull = gp(A.cull);
+    auto entry = [&](int pos) -> int { return binned ? (int)s_rank[min(pos, last)] : min(pos, last); };
     CullBox ahead[CULL_AHEAD];
+    int ahead_e[CULL_AHEAD];
     if (n_scan > 0) {
 #pragma unroll
-        for (int d = 0; d < CULL_AHEAD; ++d) ahead[d] = load_box(cull + min(lane + d * WAVE, last));
+        for (int d = 0; d < CULL_AHEAD; ++d) {
+            ahead_e[d] = entry(lane + d * WAVE);
+            ahead[d] = load_box(cull + ahead_e[d]);
+        }
     }
     bool stop = n_scan == 0;
     for (int base0 = 0; !stop; base0 += CULL_AHEAD * WAVE) {
@@ -334,10 +381,12 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
         for (int d = 0; d < CULL_AHEAD; ++d) {
             const int base = base0 + d * WAVE, r = base + lane;
             const CullBox c = ahead[d];
-            ahead[d] = load_box(cull + min(r + CULL_AHEAD * WAVE, last));   // on every path
+            const int e = ahead_e[d];
+            ahead_e[d] = entry(r + CULL_AHEAD * WAVE);
+            ahead[d] = load_box(cull + ahead_e[d]);   // on every path
             if (!stop && base < n_scan) {
-                const bool hit = (r < A.N) & (c.i0 <= bi0 + 7) & (c.i1 >= bi0) & (c.j0 <= bj0 + 7) & (c.j1 >= bj0);
-                stop = step(base, hit);
+                const bool hit = (r < n_list) & (c.i0 <= bi0 + 7) & (c.i1 >= bi0) & (c.j0 <= bj0 + 7) & (c.j1 >= bj0);
+                stop = step(base, hit, e);
             } else {
                 stop = true;
             }

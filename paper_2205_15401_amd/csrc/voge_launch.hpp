@@ -36,6 +36,14 @@ struct TraceArgs {
     size_t S;                  // list stride: n_tiles * 256
     float F, cx, cy;
     double rad2;               // 2 ln(1/eta) = -2 ln(eta)
+    // coarse-stage bins: per tile of the item (item-local tile t) the number
+    // of kernels whose screen box meets it and the offset of their ranks in
+    // the batch's pair list (global); a tile is binned when its list fits
+    // the list's capacity (otherwise select scans every record of the item)
+    const uint32_t* tcnt;      // [n_tiles]
+    const uint32_t* toff;      // [n_tiles]
+    const uint32_t* tlist;     // the batch's pair list (item-local ranks, unordered per tile)
+    uint32_t tcap;             // pair list capacity
     const float* attrs;
     // kept lists, slot-major [K][S]
     int32_t* keff;             // [S]
@@ -88,6 +96,12 @@ struct BatchDev {
     const int* epi_item;       // [total epilogue blocks] -> item
     int item_bits;             // high bits of a sort key that hold the item
     WsHeader* hdr;
+    // coarse-stage bins over all items' tiles
+    uint32_t* tcnt;            // [total tiles] kernels per tile
+    uint32_t* tcur;            // [total tiles] scatter cursors
+    uint32_t* toff;            // [total tiles + 1] exclusive scan of tcnt
+    uint32_t* tlist;           // [tcap] item-local ranks, grouped by tile
+    uint32_t tcap;
 };
 
 // One launch over the tiles of a group of items that share a K-buffer depth.
@@ -148,6 +162,9 @@ struct BatchPlan {
     size_t off_keys, off_vals, off_keys2, off_vals2, off_hist, off_cull, off_rec, off_geo;
     size_t off_keff, off_kl_l, off_kl_m, off_kl_s, off_kl_T, off_kl_r, off_kl_i;
     size_t off_grads, off_tileD, off_camP, off_bw, off_bwl;
+    size_t off_tcnt, off_tcur, off_toff, off_tsum, off_tlist;
+    uint32_t tile_cap = 0;     // pair list capacity
+    int tscan_blocks = 0;      // blocks of the tile-count scan
     size_t fwd_bytes, bwd_bytes;
 };
 
@@ -171,9 +188,15 @@ void launch_init(const InitPack& pack, int first, int count, bool from_args, Ite
                  int* pblk_item, int* epi_item, WsHeader* hdr, bool clear_status, bool clear_header, hipStream_t s);
 
 void launch_fill_u32(void* p, size_t n, uint32_t v, hipStream_t s);
-void launch_prep(const BatchDev& b, int total_pblk, int total_kern, int max_n, uint32_t* keys, uint32_t* vals,
-                 uint32_t* keys2, uint32_t* vals2, uint32_t* hist, CullRec* cull, TraceRec* rec, GeoRec* geo,
-                 hipStream_t s);
+// Prep (keys, depth sort, records) and the coarse-stage bins: per tile the
+// kernels whose screen box meets it (count, scan, scatter).  tsum: the
+// scan's block sums, tscan_blocks + 1 words.
+void launch_prep(const BatchDev& b, int total_pblk, int total_kern, int max_n, int total_tiles, int tscan_blocks,
+                 uint32_t* keys, uint32_t* vals, uint32_t* keys2, uint32_t* vals2, uint32_t* hist, uint32_t* tsum,
+                 CullRec* cull, TraceRec* rec, GeoRec* geo, hipStream_t s);
+constexpr int TSCAN_BLOCK = 1024;        // tile counts per block of the bin scan
+// pair list capacity of a batch: generous for boxes of a few tiles each
+inline size_t tile_capacity(size_t total_kern, size_t total_tiles) { return 8 * total_kern + 64 * total_tiles + 1024; }
 
 hipError_t launch_select(const GroupDev& g, int kb, hipStream_t s);
 hipError_t launch_blend(const GroupDev& g, int kb, hipStream_t s);
