@@ -13,10 +13,16 @@ except for near ties):
   * gradients: against the oracle's backward on the GPU's kept sets, every
     pixel included: |g - g_ref| <= RTOL * (sum over pixels of |contribution|)
     per element, and per tensor ||g - g_ref||_inf <= max(RTOL ||g_ref||_inf,
-    the FP32 noise floor), the floor measured in the same check: the spread
-    of the oracle's backward when every FP32 input moves by one ulp
-    (check_backward_vs_oracle).  The plain ||g - g_ref||_inf / ||g_ref||_inf
-    of every check is recorded beside the floor (VOGE_PARITY_LOG).
+    FLOOR_MULT x the FP32 noise floor), the floor measured in the same check:
+    the largest spread of the oracle's backward over a few draws in which
+    every FP32 input moves by one ulp (check_backward_vs_oracle).  An FP32
+    implementation rounds several derived quantities per pair (the per-pair
+    scalars, the erf fit, partial sums), each acting like another such
+    perturbation, and a maximum over two draws is itself a low estimate of
+    the spread, so the tensor-wide bound takes FLOOR_MULT = 3 of it; the
+    per-element rule is unchanged.  The plain ||g - g_ref||_inf /
+    ||g_ref||_inf of every check is recorded beside the floor
+    (VOGE_PARITY_LOG).
 
 The measured floor (tests/golden/fp32_noise_floor.json, written by
 oracle/noise_floor.py from the oracle alone): one-ulp moves of the scene
@@ -43,6 +49,7 @@ import torch
 
 RTOL = 1e-5
 F32_FLOOR = 1e-7     # a little above FP32's unit roundoff (6e-8)
+FLOOR_MULT = 3.0     # tensor-wide gradient bound: this many measured one-ulp spreads
 NEAR_TIE = 1e-6      # relative l difference of a near tie at the K-th place
 NEAR_ETA = 1e-5      # |q - ln eta| of a near-threshold kernel
 
@@ -225,8 +232,8 @@ def check_backward_vs_oracle(grads, scene, cam, K, G, kept, eta=0.01, pixels=Non
     camera).  G: the upstream gradient at `pixels` ((n, C); pixels None: the
     whole image), kept: the GPU's kept sets (H*W, K).  The oracle's backward
     on the GPU's kept sets is the reference for every element.  Per tensor the
-    inf-norm bound is max(RTOL ||g_ref||_inf, the FP32 noise floor), the
-    floor being measured here: the spread of the same oracle backward when
+    inf-norm bound is max(RTOL ||g_ref||_inf, FLOOR_MULT x the FP32 noise
+    floor), the floor being measured here: the spread of the same oracle backward when
     every FP32 input (scene, camera, upstream gradient) moves by one ulp
     (floor_draws draws).  Returns {name: (elem ratio, inf ratio, plain rel)}."""
     O = _oracle()
@@ -253,7 +260,7 @@ def check_backward_vs_oracle(grads, scene, cam, K, G, kept, eta=0.01, pixels=Non
         rr = np.asarray(r, np.float64).reshape(-1)
         err = np.abs(gg - rr)
         elem = float((err / (RTOL * np.asarray(a).reshape(-1) + 1e-30)).max(initial=0.0))
-        inf_bound = max(RTOL * np.abs(rr).max(initial=0.0), floor[n]) + 1e-30
+        inf_bound = max(RTOL * np.abs(rr).max(initial=0.0), FLOOR_MULT * floor[n]) + 1e-30
         inf = float(err.max(initial=0.0) / inf_bound)
         plain = float(err.max(initial=0.0) / (np.abs(rr).max(initial=0.0) + 1e-300))
         floor_rel = floor[n] / (np.abs(rr).max(initial=0.0) + 1e-300)
