@@ -162,6 +162,23 @@ int voge_render_forward(voge_ctx_t* ctx, const float* means, const float* covs, 
                         const voge_camera_t* cam, const voge_params_t* params, float* image, float* wsum,
                         int32_t* kept, void* workspace, size_t workspace_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): the forward
+ * of voge_render_forward with its workspace in a fixed device array of
+ * VOGE_STATIC_WORKSPACE_BYTES that the library holds on each GPU it runs on,
+ * from voge_create until the process ends.  Arguments as for
+ * voge_render_forward, without the workspace.  Allocates nothing.
+ *   Errors: as voge_render_forward; VOGE_ENOSPACE when the render needs more
+ *   workspace than the array holds (voge_workspace_size(..., 0) tells the
+ *   need; 64 MiB holds e.g. a 512x512 image at K = 8 or 256x256 at K = 20).
+ *   Every call on one GPU uses that GPU's one array: calls that overlap on
+ *   one GPU (two streams, or two host threads) race, and the device status
+ *   word of the call is not readable (voge_status needs a workspace). */
+#define VOGE_STATIC_WORKSPACE_BYTES (64u << 20)
+int voge_render_forward_static(voge_ctx_t* ctx, const float* means, const float* covs, const float* attrs, int N,
+                               int C, const voge_camera_t* cam, const voge_params_t* params, float* image,
+                               float* wsum, int32_t* kept, void* stream);
+
 /* Backward of voge_render_forward for upstream gradient grad_image [H*W*C]
  * (the kept sets are held fixed; selection is not differentiable).
  *   grad_means [N*3], grad_covs [N*6] (w.r.t. the 6 packed numbers: each

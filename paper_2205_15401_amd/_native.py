@@ -29,13 +29,14 @@ VOGE_SAMPLE = 32
 VOGE_BLOCK_T = 64
 VOGE_BLOCK_RHO = 128
 VOGE_MAX_BATCH = 4096
+VOGE_STATIC_WORKSPACE_BYTES = 64 << 20
 
 EXPORTS = [
     "voge_create", "voge_destroy", "voge_workspace_size", "voge_render_forward",
     "voge_render_backward", "voge_status", "voge_last_error", "voge_version", "voge_debug_phi",
     "voge_profile_enable", "voge_profile_read", "voge_batch_workspace_size", "voge_render_batch",
     "voge_batch_status", "voge_tune_batch", "voge_tune_save", "voge_tune_load", "voge_sample",
-    "voge_quadrature",
+    "voge_quadrature", "voge_render_forward_static",
 ]
 
 
@@ -96,6 +97,7 @@ def load(path: str = None):
         lib.voge_workspace_size.argtypes = [I, I, CamP, ParP, I, ctypes.POINTER(SZ)]
         lib.voge_render_forward.argtypes = [P, P, P, P, I, I, CamP, ParP, P, P, P, P, SZ, P]
         lib.voge_render_backward.argtypes = [P, P, P, P, I, I, CamP, ParP, P, P, P, P, P, I, P, SZ, P]
+        lib.voge_render_forward_static.argtypes = [P, P, P, P, I, I, CamP, ParP, P, P, P, P]
         lib.voge_sample.argtypes = [P, P, P, I, I, CamP, ParP, P, P, P, I, P, SZ, P]
         lib.voge_quadrature.argtypes = [P, P, P, I, CamP, ParP, I, P, P, P, P, I, P, SZ, P]
         lib.voge_status.argtypes = [P, ctypes.POINTER(ctypes.c_int32), P]
@@ -155,6 +157,13 @@ def voge_render_forward(ctx, means, covs, attrs, N, C, cam, params, image, wsum,
     return _check(load().voge_render_forward(ctx, means, covs, attrs, int(N), int(C), ctypes.byref(cam),
                                              ctypes.byref(params), image, wsum, kept, workspace,
                                              int(workspace_bytes), stream))
+
+
+def voge_render_forward_static(ctx, means, covs, attrs, N, C, cam, params, image, wsum, kept, stream) -> int:
+    """voge_render_forward with the library's static per-device workspace
+    (no workspace argument; allocates nothing)."""
+    return _check(load().voge_render_forward_static(ctx, means, covs, attrs, int(N), int(C), ctypes.byref(cam),
+                                                    ctypes.byref(params), image, wsum, kept, stream))
 
 
 def voge_render_backward(ctx, means, covs, attrs, N, C, cam, params, grad_image, grad_means, grad_covs,

@@ -62,11 +62,24 @@ struct voge_ctx {
     std::string arch;
     std::mutex tune_mu;
     std::map<std::string, std::pair<voge::ExecConfig, double>> tuned;
+    // this device's copy of the static workspace (voge_render_forward_static)
+    void* scratch = nullptr;
 };
+
+// The workspace of voge_render_forward_static: a fixed array in device
+// memory, one copy on every GPU the library runs on, held until the process
+// ends.  On the host the array's name is only a stand-in for the symbol:
+// kernels and copies get the device address that hipGetSymbolAddress
+// returns for the current device (scratch_address), never the name.
+static __device__ __align__(256) unsigned char scratch[VOGE_STATIC_WORKSPACE_BYTES];
 
 namespace {
 
 thread_local std::string g_err;
+
+// Device -> address of its copy of `scratch`, looked up once per device.
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_addr;
 
 int fail(int code, const std::string& msg) {
     g_err = msg;
@@ -131,6 +144,22 @@ voge::CamDev to_dev(const voge_camera_t* cam) {
 
 int hip_check(hipError_t e, const char* what) {
     if (e != hipSuccess) return fail(VOGE_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+    return VOGE_OK;
+}
+
+// The address of `scratch` on `device` (which must be current): looked up
+// with hipGetSymbolAddress the first time, then kept.
+int scratch_address(int device, void** out) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_addr.find(device);
+    if (it == g_scratch_addr.end()) {
+        void* ptr = nullptr;
+        if (int rc = hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress (scratch)"))
+            return rc;
+        if (!ptr) return fail(VOGE_EHIP, "hipGetSymbolAddress (scratch) returned null");
+        it = g_scratch_addr.emplace(device, ptr).first;
+    }
+    *out = it->second;
     return VOGE_OK;
 }
 
@@ -761,6 +790,10 @@ int voge_create(voge_ctx_t** ctx, int device) {
     c->n_cu = n_cu;
     c->arch = prop.gcnArchName;
     c->arch = c->arch.substr(0, c->arch.find(':'));
+    if (int rc = scratch_address(device, &c->scratch)) {
+        delete c;
+        return rc;
+    }
     c->stage_bytes = sizeof(voge::ItemDev) * (size_t)voge::MAX_BATCH;
     c->ring.resize(RING_SLOTS);
     for (auto& st : c->ring) {
@@ -830,6 +863,29 @@ int voge_render_forward(voge_ctx_t* ctx, const float* means, const float* covs, 
     it.wsum = wsum;
     it.kept = kept;
     if (int rc = run_batch(ctx, &it, 1, VOGE_FORWARD, workspace, workspace_bytes, static_cast<hipStream_t>(stream)))
+        return rc;
+    g_err.clear();
+    return VOGE_OK;
+}
+
+int voge_render_forward_static(voge_ctx_t* ctx, const float* means, const float* covs, const float* attrs, int N,
+                               int C, const voge_camera_t* cam, const voge_params_t* params, float* image,
+                               float* wsum, int32_t* kept, void* stream) {
+    if (int rc = check_common(ctx, means, covs, attrs, N, C, cam, params)) return rc;
+    if (!image) return fail(VOGE_EINVAL, "image is required");
+    if (!ctx->scratch) return fail(VOGE_EHIP, "the context has no static workspace");
+    const voge::ItemShape sh{N, C, cam->height, cam->width, params->K};
+    const size_t need = voge::plan_batch(&sh, 1).fwd_bytes;
+    if (need > (size_t)VOGE_STATIC_WORKSPACE_BYTES)
+        return fail(VOGE_ENOSPACE, "the render needs " + std::to_string(need) +
+                                       " bytes of workspace, more than the static workspace's " +
+                                       std::to_string((size_t)VOGE_STATIC_WORKSPACE_BYTES));
+    voge_item_t it = single_item(means, covs, attrs, N, C, cam, params);
+    it.image = image;
+    it.wsum = wsum;
+    it.kept = kept;
+    if (int rc = run_batch(ctx, &it, 1, VOGE_FORWARD, ctx->scratch, (size_t)VOGE_STATIC_WORKSPACE_BYTES,
+                           static_cast<hipStream_t>(stream)))
         return rc;
     g_err.clear();
     return VOGE_OK;
