@@ -10,20 +10,28 @@ input already resident in device memory:
   graph     the same call with its launches replayed from a HIP graph
   per-call  256 voge_render_forward + voge_render_backward pairs per step
 
-and, as context, the single 512x512 image of the 10,000-kernel torus
-(16 channels) per call, and the serving loop on a request mix (resident
-scenes of 10k-200k kernels, 128^2-1024^2 images, half gradient requests,
-Poisson arrivals at a fraction of the one-at-a-time capacity).  Prints ONE
+and, as context: the forward alone of the same batch; the single 512x512
+image of the 10,000-kernel torus (16 channels) per call, forward + backward
+and forward alone; the plain forward of one 64x64 image of 512 spheres (per
+call and graph-replayed); the uneven batch of 64 ellipsoid clouds (one batch
+call against one call per scene); the sampler, the fitting loop and the
+exact-integral mode; and the serving loop on a request mix (resident scenes
+of 10k-200k kernels, 128^2-1024^2 images, half gradient requests, Poisson
+arrivals at 0.5, 0.7 and 0.9 of the one-at-a-time capacity).  Prints ONE
 JSON line on stdout:
 
   value         Mrays/s of the batched forward + backward
   latency_ms    p50 / p99 of the batched step (one request = one batch)
   roofline      the dominant kernel of the batched step: its algorithmic FLOP
-                rate (FLOPs from the oracle's op count) against the FP32
-                vector peak, its average duration measured live with HIP
-                events on the stream it runs on
+                rate (FLOPs from the oracle's op count) against the vector
+                peak of its arithmetic (FP64, or FP32 without packed
+                instructions: 78.6 TFLOP/s), its average duration measured
+                live with HIP events on the stream it runs on; every trace
+                kernel's fraction and the whole step's beside it
   cpu_baseline  the FP64 oracle, forward + backward on a fixed random sample
                 of the same workload's rays, timed on this host's cores
+                (brute force on all threads; one-thread and binned modes
+                beside it)
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--cpu-sample RAYS]
 """
@@ -92,9 +100,25 @@ def oracle_threads() -> int:
     return threads
 
 
-def cpu_baseline(jobs, n_rays: int, seed: int = 7):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(jobs, n_rays: int, seed: int = 7, single_frac: int = 16):
     """FP64 oracle, forward + backward, on a fixed random sample of the rays
-    of all jobs (the same number of rays from each)."""
+    of all jobs (the same number of rays from each), in four modes: brute
+    force (every kernel for every ray: the parity reference, and the
+    reported value) and binned (the same formulas on the kernels of the
+    ray's 16x16 tile), each on all of this host's threads and on one thread
+    (the single-thread runs take the first 1/single_frac of every job's
+    sample)."""
     import numpy as np
     from oracle import oracle as O
 
@@ -106,22 +130,34 @@ def cpu_baseline(jobs, n_rays: int, seed: int = 7):
         cam = job.camera
         pix = np.sort(rng.choice(cam.height * cam.width, min(per, cam.height * cam.width), replace=False))
         samples.append(pix)
-    t0 = time.perf_counter()
-    n = 0
-    for job, pix in zip(jobs, samples):
-        cam, sc = job.camera, job.scene
-        H, W, C = cam.height, cam.width, sc.channels
-        G = job.grad_image.reshape(-1, C)[pix]
-        O.forward(sc.means, sc.covs, sc.attrs, cam.as_vector(), H, W, job.K, job.eta, pixels=pix, threads=threads)
-        O.backward(sc.means, sc.covs, sc.attrs, cam.as_vector(), H, W, job.K, G, job.eta, pixels=pix,
-                   threads=threads)
-        n += pix.size
-    dt = time.perf_counter() - t0
+
+    def run(nthreads, binned, frac):
+        t0 = time.perf_counter()
+        n = 0
+        for job, pix in zip(jobs, samples):
+            pix = pix[:max(1, pix.size // frac)]
+            cam, sc = job.camera, job.scene
+            H, W, C = cam.height, cam.width, sc.channels
+            G = job.grad_image.reshape(-1, C)[pix]
+            O.forward(sc.means, sc.covs, sc.attrs, cam.as_vector(), H, W, job.K, job.eta, pixels=pix,
+                      threads=nthreads, binned=binned)
+            O.backward(sc.means, sc.covs, sc.attrs, cam.as_vector(), H, W, job.K, G, job.eta, pixels=pix,
+                       threads=nthreads, binned=binned)
+            n += pix.size
+        dt = time.perf_counter() - t0
+        return {"value": n / dt / 1e6, "threads": nthreads, "rays": n, "seconds": round(dt, 3)}
+
+    modes = {"brute_all_threads": run(threads, False, 1), "brute_1_thread": run(1, False, single_frac),
+             "binned_all_threads": run(threads, True, 1), "binned_1_thread": run(1, True, single_frac)}
+    for k, v in modes.items():
+        v["value"] = round(v["value"], 6)
+    main = modes["brute_all_threads"]
     cam = jobs[0].camera
-    return {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": threads, "kind": "oracle",
-            "sample": f"{per} random rays from each of {len(jobs)} {cam.height}x{cam.width} renders ({n} rays, "
+    return {"value": main["value"], "unit": "Mrays/s", "cores": threads, "kind": "oracle",
+            "sample": f"{per} random rays from each of {len(jobs)} {cam.height}x{cam.width} renders ({main['rays']} rays, "
                       f"seed {seed}), forward + backward, brute force over all {jobs[0].scene.n} kernels, FP64, "
-                      f"{dt:.2f} s"}
+                      f"{main['seconds']:.2f} s; one-thread modes on the first 1/{single_frac} of each render's rays",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(), "modes": modes}
 
 
 class Timer:
@@ -161,19 +197,46 @@ def kb_of(K: int) -> int:
     return 64
 
 
-def roofline_of(phases, opc, K, workload):
+# Vector-ALU peak the kernels can reach: FP64 vector, and FP32 vector without
+# packed instructions (the library is built with them off), both 78.6 TFLOP/s
+# on MI355X (256 CUs x 4 SIMDs x 16 lanes x 2 FLOP per FMA x 2.4 GHz); the
+# packed-FP32 figure (157.3) is reported beside it for the whole pipeline.
+PEAK_VALU_TFLOPS = 78.6
+# the arithmetic each kernel's counted FLOPs run in
+KERNEL_DTYPE = {"select": "f64", "blend": "f32", "bwd": "f32", "bwd_reduce": "f64"}
+
+
+def roofline_of(phases, opc, K, workload, step_ms=None):
+    """Every trace kernel's algorithmic FLOP rate against the vector peak of
+    the arithmetic it issues (78.6 TFLOP/s for FP64 and unpacked FP32), the
+    dominant one as the headline, and the whole step's rate."""
     flops = {"select": opc["flop_select"], "blend": opc["flop_blend"], "bwd": opc["flop_bwd_pixel"],
              "bwd_reduce": opc["flop_bwd_chain"]}
     kb = kb_of(K)
     kname = {"select": f"k_select<{kb}>", "blend": f"k_blend<{kb}>", "bwd": f"k_bwd_pix<{kb}>",
              "bwd_reduce": f"k_bwd_red<{kb}>"}
     avg = {k: phases[k][0] / phases[k][1] for k in flops if k in phases and phases[k][1] > 0}
+    per_kernel = {}
+    for k, ms in avg.items():
+        ach = flops[k] / (ms / 1e3) / 1e12
+        per_kernel[kname[k]] = {"avg_us": round(ms * 1e3, 2), "algorithmic_flop_per_launch": flops[k],
+                                "achieved_tflops": round(ach, 4), "dtype": KERNEL_DTYPE[k],
+                                "frac": round(ach / PEAK_VALU_TFLOPS, 6)}
     dom = max(avg, key=avg.get)
     achieved = flops[dom] / (avg[dom] / 1e3) / 1e12
     traffic = load_traffic(kname[dom].split("<")[0], workload, source_digest())
-    return {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_TFLOPS, 6), "traffic": traffic, "kernel": kname[dom],
-            "avg_us": round(avg[dom] * 1e3, 2), "algorithmic_flop_per_launch": flops[dom]}
+    out = {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+           "frac": round(achieved / PEAK_VALU_TFLOPS, 6), "traffic": traffic, "kernel": kname[dom],
+           "dtype": KERNEL_DTYPE[dom], "avg_us": round(avg[dom] * 1e3, 2), "algorithmic_flop_per_launch": flops[dom],
+           "peak_basis": "FP64 vector = FP32 vector without packed instructions (built off): 78.6 TFLOP/s",
+           "per_kernel": per_kernel}
+    if step_ms:
+        total = opc["flop_per_ray_fwd_bwd"] * opc["rays"]
+        ach = total / (step_ms / 1e3) / 1e12
+        out["pipeline"] = {"flop_per_ray": round(opc["flop_per_ray_fwd_bwd"], 2), "achieved_tflops": round(ach, 4),
+                           "frac_of_78_6": round(ach / PEAK_VALU_TFLOPS, 6),
+                           "frac_of_157_3": round(ach / PEAK_FP32_TFLOPS, 6)}
+    return out
 
 
 def pct(x, q):
@@ -207,11 +270,17 @@ def bench_poses(args, torch, dev):
     total_g, per_g = timer.run(lambda: batch.run(forward=True, backward=True, graph=True, stream=s), args.steps,
                                args.warmup)
     total_e, per_e = timer.run(lambda: batch.run(forward=True, backward=True, stream=s), args.steps, args.warmup)
+    log("[bench] graph step ms: " + " ".join(f"{x:.3f}" for x in per_g))
+    log("[bench] eager step ms: " + " ".join(f"{x:.3f}" for x in per_e))
+    # forward only (the same 256 renders, no backward)
+    total_f, per_f = timer.run(lambda: batch.run(forward=True, stream=s), args.steps, args.warmup)
+    log(f"[bench] batched forward only {total_f / args.steps:.3f} ms/step "
+        f"({rays / (total_f / args.steps) / 1e3:.1f} Mrays/s)")
     # autotuned execution choices (timed on this batch by the library)
     tune = batch.tune(forward=True, backward=True, trials=3, stream=s)
     total_t, per_t = timer.run(lambda: batch.run(forward=True, backward=True, tuned=True, stream=s), args.steps,
                                args.warmup)
-    log(f"[bench] autotuner: graph={tune.graph} order={tune.order} ({tune.best_ms:.3f} ms vs default "
+    log(f"[bench] autotuner: graph={tune.graph} order={tune.order} bins={tune.bins} ({tune.best_ms:.3f} ms vs default "
         f"{tune.default_ms:.3f} ms); tuned {total_t / args.steps:.3f} ms/step")
     st = batch.status()
     if any(st):
@@ -268,7 +337,8 @@ def bench_poses(args, torch, dev):
         "eager_per": per_e, "per_call_value": rays / ms_p / 1e3 if ms_p else None, "per_call_ms": ms_p,
         "per_render": per_render,
         "tuned_value": rays / (total_t / args.steps) / 1e3, "tuned_ms": total_t / args.steps, "tuned_per": per_t,
-        "tune": {"graph": tune.graph, "order": tune.order, "best_ms": round(tune.best_ms, 4),
+        "fwd_value": rays / (total_f / args.steps) / 1e3, "fwd_ms": total_f / args.steps, "fwd_per": per_f,
+        "tune": {"graph": tune.graph, "order": tune.order, "bins": tune.bins, "best_ms": round(tune.best_ms, 4),
                  "default_ms": round(tune.default_ms, 4)},
         "phases": phases, "rays": rays, "N": N, "C": C, "H": H, "W": W, "K": K, "eta": eta, "n": n, "jobs": jobs,
     }
@@ -352,7 +422,8 @@ def bench_fit(args, torch, dev):
 
 
 def sampler_roofline(phases, opc, K, workload):
-    """The sampler step's dominant kernel against the FP32 vector peak."""
+    """The sampler step's dominant kernel against the vector peak of its
+    arithmetic (FP64 select; FP32 blend without packed instructions)."""
     flops = {"select": opc["flop_select"], "blend_sample": opc["flop_blend_weights"] + opc["flop_sample_reduce"]}
     kb = kb_of(K)
     kname = {"select": f"k_select<{kb}>", "blend_sample": f"k_blend_sample<{kb}>"}
@@ -360,8 +431,8 @@ def sampler_roofline(phases, opc, K, workload):
     dom = max(avg, key=avg.get)
     achieved = flops[dom] / (avg[dom] / 1e3) / 1e12
     traffic = load_traffic(kname[dom].split("<")[0], workload, source_digest())
-    return {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_TFLOPS, 6), "traffic": traffic, "kernel": kname[dom],
+    return {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_VALU_TFLOPS, 6), "traffic": traffic, "kernel": kname[dom],
             "avg_us": round(avg[dom] * 1e3, 2), "algorithmic_flop_per_launch": flops[dom]}
 
 
@@ -391,9 +462,15 @@ def bench_torus(args, torch, dev):
         nat.voge_render_backward(ctx, p(means), p(covs), p(attrs), N, C, cs, par, p(grad), p(gm), p(gc), p(ga),
                                  p(gk), nat.VOGE_REUSE_PREP, p(ws), wsb, s)
 
+    def step_fwd():
+        nat.voge_render_forward(ctx, p(means), p(covs), p(attrs), N, C, cs, par, p(image), None, None, p(ws), wsb, s)
+
     total, per = Timer(torch, stream).run(step, args.torus_steps, args.warmup)
     ms = total / args.torus_steps
     log(f"[bench] single image {job.name}: {ms:.4f} ms/step, {H * W / ms / 1e3:.1f} Mrays/s")
+    total_f, per_f = Timer(torch, stream).run(step_fwd, args.torus_steps, args.warmup)
+    ms_f = total_f / args.torus_steps
+    log(f"[bench] single image {job.name} forward only: {ms_f:.4f} ms/step, {H * W / ms_f / 1e3:.1f} Mrays/s")
     nat.voge_profile_enable(ctx, True)
     nat.voge_profile_read(ctx, reset=True)
     for _ in range(args.profile_steps):
@@ -405,7 +482,118 @@ def bench_torus(args, torch, dev):
         log(f"[bench]   single-image phase {name:10s} {tot / max(cnt, 1) * 1e3:10.2f} us avg over {cnt}")
     return {"workload": job.name, "value": round(H * W / ms / 1e3, 3), "unit": "Mrays/s", "ms_per_step": round(ms, 5),
             "steps": args.torus_steps, "mode": "per-call forward+backward",
-            "latency_ms": {"p50": pct(per, 50), "p99": pct(per, 99)}}
+            "latency_ms": {"p50": pct(per, 50), "p99": pct(per, 99)},
+            "forward_only": {"value": round(H * W / ms_f / 1e3, 3), "ms_per_step": round(ms_f, 5),
+                             "latency_ms": {"p50": pct(per_f, 50), "p99": pct(per_f, 99)}},
+            "phases_us": {k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in phases.items()}}
+
+
+def bench_small(args, torch, dev):
+    """The plain forward of one 64x64 image (F = 64) of 512 spheres, K = 16:
+    per call (voge_render_forward), and the same render as a batch of one
+    replayed from a HIP graph."""
+    from paper_2205_15401_amd import _native as nat
+    from paper_2205_15401_amd import render as R
+    from paper_2205_15401_amd import scenes as S
+
+    job = S.config_small()
+    sc, cam = job.scene, job.camera
+    N, C, H, W, K = sc.n, sc.channels, cam.height, cam.width, job.K
+    m, c, a = (torch.from_numpy(x).to(dev) for x in (sc.means, sc.covs, sc.attrs))
+    cs = R.camera_struct(cam)
+    par = R.params_struct(K, job.eta)
+    wsb = nat.voge_workspace_size(N, C, cs, par, False)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    image = torch.empty((H, W, C), dtype=torch.float32, device=dev)
+    ctx = R.context(dev)
+    side = torch.cuda.Stream()
+    s = side.cuda_stream
+    p = lambda t: t.data_ptr()  # noqa: E731
+    steps = args.small_steps
+
+    def step():
+        nat.voge_render_forward(ctx, p(m), p(c), p(a), N, C, cs, par, p(image), None, None, p(ws), wsb, s)
+
+    timer = Timer(torch, side)
+    total, per = timer.run(step, steps, args.warmup)
+    batch = R.Batch([(m, c, a)], [(0, cs, K, job.eta)], dev)
+    total_g, per_g = timer.run(lambda: batch.run(forward=True, graph=True, stream=s), steps, args.warmup)
+    ms, ms_g = total / steps, total_g / steps
+    log(f"[bench] {job.name} forward: per call {ms * 1e3:.1f} us ({H * W / ms / 1e3:.1f} Mrays/s), "
+        f"graph {ms_g * 1e3:.1f} us ({H * W / ms_g / 1e3:.1f} Mrays/s)")
+    return {"workload": job.name, "mode": "forward only, one image per step", "steps": steps,
+            "per_call": {"value": round(H * W / ms / 1e3, 3), "unit": "Mrays/s", "us_per_step": round(ms * 1e3, 2),
+                         "latency_us": {"p50": round(pct(per, 50) * 1e3, 2), "p99": round(pct(per, 99) * 1e3, 2)}},
+            "graph": {"value": round(H * W / ms_g / 1e3, 3), "unit": "Mrays/s", "us_per_step": round(ms_g * 1e3, 2),
+                      "latency_us": {"p50": round(pct(per_g, 50) * 1e3, 2), "p99": round(pct(per_g, 99) * 1e3, 2)}}}
+
+
+def bench_uneven(args, torch, dev):
+    """The uneven batch: 64 ellipsoid clouds of 1,000-100,000 kernels,
+    64^2-512^2 images, K in {8, 16, 32}, forward + backward; one
+    voge_render_batch call per step (eager, graph-replayed and autotuned)
+    against one forward + backward call per scene."""
+    from paper_2205_15401_amd import _native as nat
+    from paper_2205_15401_amd import render as R
+    from paper_2205_15401_amd import scenes as S
+
+    jobs = S.config_uneven()
+    dsc = [tuple(torch.from_numpy(x).to(dev) for x in (j.scene.means, j.scene.covs, j.scene.attrs)) for j in jobs]
+    cams = [R.camera_struct(j.camera) for j in jobs]
+    batch = R.Batch(dsc, [(i, cs, j.K, j.eta) for i, (cs, j) in enumerate(zip(cams, jobs))], dev, backward=True,
+                    with_camera=True)
+    for i, j in enumerate(jobs):
+        batch.set_grad_image(i, torch.from_numpy(j.grad_image))
+    rays = sum(j.camera.height * j.camera.width for j in jobs)
+    side = torch.cuda.Stream()
+    s = side.cuda_stream
+    timer = Timer(torch, side)
+    steps = args.uneven_steps
+    total_e, per_e = timer.run(lambda: batch.run(forward=True, backward=True, stream=s), steps, args.warmup)
+    total_g, per_g = timer.run(lambda: batch.run(forward=True, backward=True, graph=True, stream=s), steps,
+                               args.warmup)
+    tune = batch.tune(forward=True, backward=True, trials=3, stream=s)
+    total_t, per_t = timer.run(lambda: batch.run(forward=True, backward=True, tuned=True, stream=s), steps,
+                               args.warmup)
+    # per call: one workspace of the largest single-scene size
+    ctx = R.context(dev)
+    pars = [R.params_struct(j.K, j.eta) for j in jobs]
+    wsb = max(nat.voge_workspace_size(j.scene.n, j.scene.channels, cs, pr, True)
+              for j, cs, pr in zip(jobs, cams, pars))
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    p = lambda t: t.data_ptr()  # noqa: E731
+
+    def per_call():
+        for i, j in enumerate(jobs):
+            m, c, a = dsc[i]
+            N, C = j.scene.n, j.scene.channels
+            nat.voge_render_forward(ctx, p(m), p(c), p(a), N, C, cams[i], pars[i], p(batch.images[i]), None, None,
+                                    p(ws), wsb, s)
+            nat.voge_render_backward(ctx, p(m), p(c), p(a), N, C, cams[i], pars[i], p(batch.grad_images[i]),
+                                     p(batch.grad_means[i]), p(batch.grad_covs[i]), p(batch.grad_attrs[i]),
+                                     p(batch.grad_cameras[i]), nat.VOGE_REUSE_PREP, p(ws), wsb, s)
+
+    total_p, per_p = timer.run(per_call, steps, 1)
+    del ws
+    ctx_ms = {"batched": total_e / steps, "graph": total_g / steps, "tuned": total_t / steps,
+              "per_call": total_p / steps}
+    log("[bench] uneven batch: " + ", ".join(f"{k} {v:.3f} ms ({rays / v / 1e3:.1f} Mrays/s)"
+                                              for k, v in ctx_ms.items()) +
+        f"; autotuner graph={tune.graph} order={tune.order} bins={tune.bins}")
+    lat = lambda per: {"p50": pct(per, 50), "p99": pct(per, 99)}  # noqa: E731
+    return {"workload": "uneven64: 64 clouds of 1e3-1e5 kernels, 64^2-512^2, K 8/16/32, C=3",
+            "rays_per_step": rays, "steps": steps, "mode": "forward+backward",
+            "batched": {"value": round(rays / ctx_ms["batched"] / 1e3, 3), "ms_per_step": round(ctx_ms["batched"], 5),
+                        "latency_ms": lat(per_e)},
+            "graph": {"value": round(rays / ctx_ms["graph"] / 1e3, 3), "ms_per_step": round(ctx_ms["graph"], 5),
+                      "latency_ms": lat(per_g)},
+            "tuned": {"value": round(rays / ctx_ms["tuned"] / 1e3, 3), "ms_per_step": round(ctx_ms["tuned"], 5),
+                      "latency_ms": lat(per_t),
+                      "choice": {"graph": tune.graph, "order": tune.order, "bins": tune.bins, "best_ms": round(tune.best_ms, 4),
+                                 "default_ms": round(tune.default_ms, 4)}},
+            "per_call": {"value": round(rays / ctx_ms["per_call"] / 1e3, 3),
+                         "ms_per_step": round(ctx_ms["per_call"], 5), "latency_ms": lat(per_p)},
+            "batched_vs_per_call": round(ctx_ms["per_call"] / ctx_ms["batched"], 3)}
 
 
 PEAK_FP64_TFLOPS = 78.6    # MI355X FP64 vector peak
@@ -536,10 +724,12 @@ def main():
     ap.add_argument("--fit-iters", type=int, default=2000, help="iterations of the fitting loop (0 = skip)")
     ap.add_argument("--quad-samples", type=int, default=4001,
                     help="quadrature points per pixel of the exact-integral leg (0 = skip)")
-    ap.add_argument("--serving-requests", type=int, default=600, help="timed requests per load (0 = skip serving)")
-    ap.add_argument("--serving-warmup", type=int, default=100)
+    ap.add_argument("--small-steps", type=int, default=200, help="timed steps of the 64x64 forward (0 = skip)")
+    ap.add_argument("--uneven-steps", type=int, default=5, help="timed steps of the uneven 64-scene batch (0 = skip)")
+    ap.add_argument("--serving-requests", type=int, default=2000, help="timed requests per load (0 = skip serving)")
+    ap.add_argument("--serving-warmup", type=int, default=200)
     ap.add_argument("--serving-capacity-requests", type=int, default=200)
-    ap.add_argument("--serving-loads", type=lambda t: [float(x) for x in t.split(",")], default=[0.5, 0.9, 1.2, 1.6])
+    ap.add_argument("--serving-loads", type=lambda t: [float(x) for x in t.split(",")], default=[0.5, 0.7, 0.9])
     ap.add_argument("--serving-batch-items", type=int, default=64)
     ap.add_argument("--serving-budget-gb", type=float, default=64.0)
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -580,6 +770,8 @@ def main():
     sampler = bench_sampler(args, torch, dev, r["jobs"]) if args.sample_steps > 0 else None
     fit = bench_fit(args, torch, dev) if args.fit_iters > 0 else None
     quad = bench_quadrature(args, torch, dev) if args.quad_samples > 0 else None
+    small = bench_small(args, torch, dev) if args.small_steps > 0 else None
+    uneven = bench_uneven(args, torch, dev) if args.uneven_steps > 0 else None
     single = bench_torus(args, torch, dev) if args.torus_steps > 0 else None
     serving = bench_serving(args, torch, dev) if args.serving_requests > 0 else None
     calibration_copy()
@@ -588,7 +780,7 @@ def main():
     roofline = None
     if os.path.exists(opc_path):
         opc = json.load(open(opc_path))
-        roofline = roofline_of(r["phases"], opc, r["K"], POSES_NAME)
+        roofline = roofline_of(r["phases"], opc, r["K"], POSES_NAME, step_ms=r["eager_ms"])
         if sampler is not None:
             sampler["roofline"] = sampler_roofline(sampler["phases"], opc, r["K"], POSES_NAME)
     else:
@@ -619,6 +811,8 @@ def main():
         "latency_ms": {"p50": pct(r["eager_per"], 50), "p99": pct(r["eager_per"], 99)},
         "batched_graph": {"value": round(r["value"], 3), "ms_per_step": round(r["ms"], 5),
                           "latency_ms": {"p50": pct(r["per"], 50), "p99": pct(r["per"], 99)}},
+        "batched_forward_only": {"value": round(r["fwd_value"], 3), "ms_per_step": round(r["fwd_ms"], 5),
+                                 "latency_ms": {"p50": pct(r["fwd_per"], 50), "p99": pct(r["fwd_per"], 99)}},
         "batched_tuned": {"value": round(r["tuned_value"], 3), "ms_per_step": round(r["tuned_ms"], 5),
                           "latency_ms": {"p50": pct(r["tuned_per"], 50), "p99": pct(r["tuned_per"], 99)},
                           "choice": r["tune"]},
@@ -637,6 +831,8 @@ def main():
         "fit": fit,
         "exact_integral": quad,
         "single_image": single,
+        "small_forward": small,
+        "uneven_batch": uneven,
         "serving": serving,
         "phases_us": {k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in r["phases"].items()},
         "roofline": roofline,

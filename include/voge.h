@@ -272,19 +272,25 @@ int voge_render_batch(voge_ctx_t* ctx, const voge_item_t* items, int n_items, in
 /* Autotuner.  For the shapes of a batch (per item: image size, K, C and the
  * bit length of N, in call order; plus the work flags and the device
  * architecture) it times the execution choices -- launches issued one by one
- * or replayed from a HIP graph, and the order in which workgroups take screen
+ * or replayed from a HIP graph; the order in which workgroups take screen
  * tiles (a contiguous band of tiles per XCD, for L2 locality, or every eighth
- * tile per XCD, for balance) -- on the caller's batch, and keeps the fastest in
+ * tile per XCD, for balance); and which scenes get coarse-stage bins (per
+ * 16x16 tile the kernels whose screen box meets it, so that a tile scans its
+ * bin instead of every kernel; building them costs a pass over the kernels
+ * and a sort per tile) -- on the caller's batch, and keeps the fastest in
  * the context for calls with VOGE_TUNED.  Results are those of
  * voge_render_batch (the call renders the batch 1 + trials times per choice).
  *   flags      as for voge_render_batch, without VOGE_GRAPH and VOGE_TUNED
  *   trials     timed renders per choice (>= 1); graph choices need a non-null stream
  *   result     optional: the choice kept and the mean times (ms) of it and of
- *              the default (separate launches, banded order)
+ *              the default (separate launches, banded order, no bins)
  * Synchronises `stream`.  Errors as for voge_render_batch. */
 typedef struct voge_tune_result {
     int32_t graph;            /* 1 if the kept choice replays a HIP graph      */
     int32_t order;            /* 0 banded tiles per XCD, 1 plain tile order     */
+    int32_t bins;             /* coarse-stage bins: 0 none (the default), 1 for
+                                 scenes of 16,384 kernels or more, 2 every
+                                 scene                                          */
     double best_ms;
     double default_ms;
 } voge_tune_result_t;

@@ -43,6 +43,13 @@ int voge_profile_read(voge_ctx_t* ctx, voge_phase_time_t* out, int max_out, int*
  * pointers with n > 0) / VOGE_EHIP. */
 int voge_debug_phi(const float* x, float* y, int n, void* stream);
 
+/* The coarse-stage bin choice of calls through `ctx` that do not take a
+ * tuned choice (VOGE_TUNED): 0 no bins (the default), 1 bins for scenes of
+ * 16,384 kernels or more, 2 bins for every scene.  Results do not depend on it
+ * (a tile without a bin scans every kernel of its scene); it selects which
+ * code path renders, for tests and timing.  Returns 0 or VOGE_EINVAL. */
+int voge_debug_bins(voge_ctx_t* ctx, int bins);
+
 #ifdef __cplusplus
 }
 #endif

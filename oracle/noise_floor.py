@@ -12,8 +12,15 @@ can be held closer to the oracle than that.  Kept sets are held fixed (the
 unmoved selection is handed to the perturbed runs), so the spread is that of
 the blend (Eq. 7-8) and of its gradients, not of the discrete selection.
 
-For each workload and each group of inputs moved (all of them; the scene
-geometry; the camera; attributes and upstream gradient) this writes, per
+An FP32 implementation also rounds what it derives per (pixel, kernel) pair:
+the oracle's jitter mode moves each per-pair derivative of the backward
+(dL/dq, dL/dl, dL/da and the pair's weight in the attribute gradient) by one
+FP32 unit roundoff, up or down, which no implementation that carries them in
+FP32 avoids.
+
+For each workload and each group of quantities moved (all inputs; the scene
+geometry; the camera; attributes and upstream gradient; the per-pair
+derivatives alone; all inputs and the per-pair derivatives) this writes, per
 output, the largest spread over a few perturbation draws in the units the
 parity rules use:
   * image: max |dC| / (|C| + sum_k W_k |c_k|)   (the per-element image scale);
@@ -56,6 +63,10 @@ GROUPS = {
     "geometry": ("means", "covs"),
     "camera": ("camera",),
     "attrs_grad": ("attrs", "grad"),
+    # the per-pair derivatives of the backward rounded to FP32 (the oracle's
+    # jitter mode), alone and on top of every input
+    "pairs": ("pairs",),
+    "all_with_pairs": ("means", "covs", "attrs", "camera", "grad", "pairs"),
 }
 
 
@@ -83,7 +94,8 @@ def spread(scene, cam, K, pixels, G, draws, rng, eta=0.01, group="all"):
         hit = img_scale > 0
         if hit.any():
             res["image_rel"] = max(res["image_rel"], float((np.abs(f.image - base.image)[hit] / img_scale[hit]).max()))
-        b = O.backward(m, c, a, cvp, H, W, K, Gp, eta, pixels=pixels, given=given)
+        seed = int(rng.integers(1, 2**63)) if "pairs" in moved else 0
+        b = O.backward(m, c, a, cvp, H, W, K, Gp, eta, pixels=pixels, given=given, jitter_seed=seed)
         for n in names:
             g0, g1 = getattr(bb, n).reshape(-1), getattr(b, n).reshape(-1)
             ab = getattr(bb, "abs_" + n).reshape(-1)

@@ -114,7 +114,8 @@ def _lib():
             Dbl = ctypes.c_double
             lib.oracle_forward.argtypes = [P, P, P, I, I, P, I, I, Dbl, I, P, L, I, P, P, P, P, P, P, P, P, I]
             lib.oracle_forward.restype = I
-            lib.oracle_backward.argtypes = [P, P, P, I, I, P, I, I, Dbl, I, P, L, P, I, P, P, P, P, P, P, P, P, I, P, I]
+            lib.oracle_backward.argtypes = [P, P, P, I, I, P, I, I, Dbl, I, P, L, P, I, P, P, P, P, P, P, P, P, I, P, I,
+                                            ctypes.c_uint64]
             lib.oracle_backward.restype = I
             lib.oracle_quadrature.argtypes = [P, P, I, P, I, I, Dbl, I, P, L, I, I, P, P, P]
             lib.oracle_quadrature.restype = I
@@ -212,12 +213,16 @@ BLOCK_RHO = 2    # ablation: no gradient through the factor e^{q_k} of Eq. 8
 
 def backward(means, covs, attrs, cam_vec, H: int, W: int, K: int, grad, eta: float = 0.01,
              pixels: Optional[Sequence[int]] = None, threads: int = 0, mode: int = 0,
-             given=None, binned: bool = False) -> BackwardResult:
+             given=None, binned: bool = False, jitter_seed: int = 0) -> BackwardResult:
     """Gradients of sum_p <grad_p, C_p> over the given pixels (grad is
     (n_pix, C), or (H, W, C) when pixels is None).  mode: 0, or BLOCK_T and/or
     BLOCK_RHO, the gradient ablations of the paper's pose-estimation ablation
     table ("w/o grad T(r)" and "w/o grad rho(r)").  given: optional (n_pix, K)
-    kept sets, as for forward()."""
+    kept sets, as for forward().  jitter_seed: nonzero moves every per-pair
+    derivative (dL/dq, dL/dl, dL/da and the pair's weight in the attribute
+    gradient) by one FP32 unit roundoff up or down (signs drawn from the seed):
+    the noise-floor diagnostic of an implementation that carries them in
+    FP32; 0 is the plain backward."""
     m, c, a, cv = _f64(means), _f64(covs), _f64(attrs), _f64(cam_vec)
     N, C = m.shape[0], a.shape[1]
     pix, n = _pix(pixels, H, W)
@@ -228,7 +233,7 @@ def backward(means, covs, attrs, cam_vec, H: int, W: int, K: int, grad, eta: flo
                                 _ptr(pix), n, _ptr(g), threads,
                                 _ptr(r.means), _ptr(r.covs), _ptr(r.attrs), _ptr(r.camera),
                                 _ptr(r.abs_means), _ptr(r.abs_covs), _ptr(r.abs_attrs), _ptr(r.abs_camera),
-                                int(mode), _ptr(gv), int(bool(binned)))
+                                int(mode), _ptr(gv), int(bool(binned)), int(jitter_seed) & ((1 << 64) - 1))
     if rc < 0:
         raise ValueError("oracle_backward: bad arguments")
     r.n_invalid = rc

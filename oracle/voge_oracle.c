@@ -52,6 +52,25 @@
 #define OR_FLAG_TIE 1      /* |l_K - l_{K+1}| <= 1e-6 l_K: the K-th place is a near tie   */
 #define OR_FLAG_ETA 2      /* some kernel with l > 0 sits within 1e-5 of the threshold q  */
 
+/* Noise-floor mode of oracle_backward (jitter != 0): every per-pair
+ * derivative -- dL/dq, dL/dl and dL/da of a (pixel, kept kernel) pair and its
+ * weight W in the attribute gradient -- is multiplied by 1 + s 2^-24 with a
+ * sign s = +-1 drawn per (seed, pixel, kernel, quantity), i.e. moved by the
+ * unit roundoff of FP32, as an implementation that carries those quantities
+ * in FP32 rounds them.  The signs come from SplitMix64 (Steele, Lea and Flood,
+ * "Fast splittable pseudorandom number generators", OOPSLA 2014), a counter
+ * hash, so a draw does not depend on threads or order.  A diagnostic of the
+ * spread no FP32 implementation can beat; the default (jitter = 0) is the
+ * plain FP64 backward. */
+static double pair_jitter(uint64_t seed, int64_t pixel, int kernel, int which) {
+    uint64_t z = seed ^ ((uint64_t)pixel * 0x100000001B3ull) ^ ((uint64_t)kernel << 3) ^ (uint64_t)which;
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (z >> 63) ? 1.0 + ldexp(1.0, -24) : 1.0 - ldexp(1.0, -24);
+}
+
 /* gradient ablations of oracle_backward (grad_mode bits) */
 #define ORACLE_BLOCK_T 1     /* no gradient through the transmittance T(l_k)               */
 #define ORACLE_BLOCK_RHO 2   /* no gradient through the factor e^{q_k} of Eq. 8            */
@@ -524,7 +543,7 @@ int oracle_backward(const double* means, const double* covs, const double* attrs
                     const int64_t* pix, int64_t n_pix, const double* grad_pix, int nthreads,
                     double* g_means, double* g_covs, double* g_attrs, double* g_cam,
                     double* a_means, double* a_covs, double* a_attrs, double* a_cam, int grad_mode,
-                    const int32_t* given, int binned) {
+                    const int32_t* given, int binned, uint64_t jitter) {
     if (check_args(N, C, H, W, eta, K)) return -1;
     cam_t cam;
     load_camera(cam15, H, W, &cam);
@@ -587,10 +606,11 @@ int oracle_backward(const double* means, const double* covs, const double* attrs
             for (int k = 0; k < keff; ++k) {
                 const double* ck = attrs + (size_t)kept[k].idx * C;
                 double g = 0.0, ag = 0.0;
+                const double wj = jitter ? Wt[k] * pair_jitter(jitter, lin, kept[k].idx, 3) : Wt[k];
                 for (int c = 0; c < C; ++c) {
                     g += G[c] * ck[c];
                     ag += fabs(G[c] * ck[c]);
-                    gA[(size_t)kept[k].idx * C + c] += Wt[k] * G[c];
+                    gA[(size_t)kept[k].idx * C + c] += wj * G[c];
                     aA[(size_t)kept[k].idx * C + c] += fabs(Wt[k] * G[c]);
                 }
                 /* W_k = exp(-E_k) e^{q_k}: direct path through e^{q_k}, and dL/dE_k.
@@ -634,6 +654,11 @@ int oracle_backward(const double* means, const double* covs, const double* attrs
                 double l = kept[k].l, a = kept[k].a;
                 double dq = dm[k] * exp(kept[k].q);
                 double adq = adm[k] * exp(kept[k].q);
+                if (jitter) {
+                    dq *= pair_jitter(jitter, lin, kept[k].idx, 0);
+                    dl[k] *= pair_jitter(jitter, lin, kept[k].idx, 1);
+                    da[k] *= pair_jitter(jitter, lin, kept[k].idx, 2);
+                }
                 double V[3], SV[3], SD[3];
                 for (int d = 0; d < 3; ++d) V[d] = kk->M[d] - l * D[d];
                 mat_vec(kk->S, V, SV);

@@ -36,7 +36,7 @@ EXPORTS = [
     "voge_render_backward", "voge_status", "voge_last_error", "voge_version", "voge_debug_phi",
     "voge_profile_enable", "voge_profile_read", "voge_batch_workspace_size", "voge_render_batch",
     "voge_batch_status", "voge_tune_batch", "voge_tune_save", "voge_tune_load", "voge_sample",
-    "voge_quadrature", "voge_render_forward_static",
+    "voge_quadrature", "voge_render_forward_static", "voge_debug_bins",
 ]
 
 
@@ -60,8 +60,8 @@ class VogeItem(ctypes.Structure):
 
 
 class VogeTuneResult(ctypes.Structure):
-    _fields_ = [("graph", ctypes.c_int32), ("order", ctypes.c_int32), ("best_ms", ctypes.c_double),
-                ("default_ms", ctypes.c_double)]
+    _fields_ = [("graph", ctypes.c_int32), ("order", ctypes.c_int32), ("bins", ctypes.c_int32),
+                ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
 
 
 class VogePhaseTime(ctypes.Structure):
@@ -105,6 +105,7 @@ def load(path: str = None):
         lib.voge_last_error.restype = ctypes.c_char_p
         lib.voge_version.argtypes = []
         lib.voge_debug_phi.argtypes = [P, P, I, P]
+        lib.voge_debug_bins.argtypes = [P, I]
         lib.voge_profile_enable.argtypes = [P, I]
         lib.voge_profile_read.argtypes = [P, ctypes.POINTER(VogePhaseTime), I, ctypes.POINTER(I), I]
         ItemP = ctypes.POINTER(VogeItem)
@@ -250,3 +251,9 @@ def voge_profile_read(ctx, reset: bool = True):
     n = ctypes.c_int()
     _check(load().voge_profile_read(ctx, arr, 16, ctypes.byref(n), int(bool(reset))))
     return {arr[i].name.decode(): (arr[i].total_ms, int(arr[i].count)) for i in range(min(n.value, 16))}
+
+
+def voge_debug_bins(ctx, bins: int) -> int:
+    """Coarse-stage bins of untuned calls through ctx: 0 none (the default),
+    1 scenes of 16,384 kernels or more, 2 every scene."""
+    return _check(load().voge_debug_bins(ctx, int(bins)))

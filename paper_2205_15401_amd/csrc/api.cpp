@@ -64,6 +64,8 @@ struct voge_ctx {
     std::map<std::string, std::pair<voge::ExecConfig, double>> tuned;
     // this device's copy of the static workspace (voge_render_forward_static)
     void* scratch = nullptr;
+    // bin choice of calls without a tuned choice (voge_debug_bins)
+    int bins = 0;
 };
 
 // The workspace of voge_render_forward_static: a fixed array in device
@@ -401,7 +403,8 @@ BatchWs carve_batch(void* ws, const voge::BatchPlan& p) {
 }
 
 // The device record of table entry j.
-voge::ItemDev item_record(const voge::BatchPlan& p, int j, const voge_item_t& src, const BatchWs& w, int flags) {
+voge::ItemDev item_record(const voge::BatchPlan& p, int j, const voge_item_t& src, const BatchWs& w, int flags,
+                          const voge::ExecConfig& cfg) {
     const voge::ItemPlan& ip = p.items[j];
     voge::ItemDev d{};
     voge::TraceArgs& t = d.t;
@@ -425,6 +428,7 @@ voge::ItemDev item_record(const voge::BatchPlan& p, int j, const voge_item_t& sr
     t.toff = w.toff + ip.tile_start;
     t.tlist = w.tlist;
     t.tcap = p.tile_cap;
+    t.binned = voge::item_binned(cfg, ip.s.N) ? 1 : 0;
     t.attrs = src.attrs;
     t.keff = w.keff + (size_t)ip.tile_start * voge::TILE_THREADS;
     t.kl_l = w.kl_l + lo;
@@ -479,8 +483,9 @@ voge::ItemDev item_record(const voge::BatchPlan& p, int j, const voge_item_t& sr
     return d;
 }
 
-voge::BatchDev batch_dev(const voge::BatchPlan& p, const BatchWs& w) {
+voge::BatchDev batch_dev(const voge::BatchPlan& p, const BatchWs& w, const voge::ExecConfig& cfg) {
     voge::BatchDev b{};
+    for (const auto& it : p.items) b.any_binned |= voge::item_binned(cfg, it.s.N) ? 1 : 0;
     b.items = w.items;
     b.n_items = (int)p.items.size();
     b.pblk_item = w.pblk_item;
@@ -495,7 +500,8 @@ voge::BatchDev batch_dev(const voge::BatchPlan& p, const BatchWs& w) {
     return b;
 }
 
-voge::GroupDev group_dev(const voge::GroupPlan& g, const BatchWs& w, const voge::ExecConfig& cfg) {
+voge::GroupDev group_dev(const voge::BatchPlan& p, const voge::GroupPlan& g, const BatchWs& w,
+                         const voge::ExecConfig& cfg) {
     voge::GroupDev d{};
     d.items = w.items;
     d.tile_item = w.tile_item;
@@ -503,6 +509,7 @@ voge::GroupDev group_dev(const voge::GroupPlan& g, const BatchWs& w, const voge:
     d.tile0 = g.tile0;
     d.n_tiles = g.n_tiles;
     d.order = cfg.order;
+    for (int j = g.first_item; j < g.first_item + g.n_items; ++j) d.bins |= voge::item_binned(cfg, p.items[j].s.N) ? 1 : 0;
     return d;
 }
 
@@ -514,7 +521,7 @@ int upload_items(voge_ctx_t* ctx, const std::vector<voge::ItemDev>& recs, const 
 // All launches of a call after the table upload.
 int launch_compute(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, int flags,
                    const voge::ExecConfig& cfg, bool profile, hipStream_t s, const voge::QuadOut* quad = nullptr) {
-    const voge::BatchDev b = batch_dev(p, w);
+    const voge::BatchDev b = batch_dev(p, w, cfg);
     auto scope = [&](const char* name) { return ProfScope(profile ? ctx : nullptr, name, s); };
     const bool fwd_part = (flags & VOGE_FORWARD) || !(flags & VOGE_REUSE_PREP);
     if (fwd_part) {
@@ -527,14 +534,14 @@ int launch_compute(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, 
         {
             ProfScope ps = scope("select");
             for (const auto& g : p.groups)
-                if (int rc = hip_check(voge::launch_select(group_dev(g, w, cfg), g.kb, s), "select launch")) return rc;
+                if (int rc = hip_check(voge::launch_select(group_dev(p, g, w, cfg), g.kb, s), "select launch")) return rc;
         }
     }
     if (quad) {
         // exact-integral mode (one item): the quadrature replaces the blend
         ProfScope ps = scope("quadrature");
         const voge::GroupPlan& g = p.groups[0];
-        return hip_check(voge::launch_quadrature(group_dev(g, w, cfg), g.kb, *quad, s), "quadrature launch");
+        return hip_check(voge::launch_quadrature(group_dev(p, g, w, cfg), g.kb, *quad, s), "quadrature launch");
     }
     if (flags & VOGE_SAMPLE) {
         {
@@ -546,7 +553,7 @@ int launch_compute(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, 
             // the blend, with the sampler's per-tile reduction fused in
             ProfScope ps = scope("blend_sample");
             for (const auto& g : p.groups)
-                if (int rc = hip_check(voge::launch_blend_sample(group_dev(g, w, cfg), g.kb, g.max_c, s),
+                if (int rc = hip_check(voge::launch_blend_sample(group_dev(p, g, w, cfg), g.kb, g.max_c, s),
                                        "blend+sample launch"))
                     return rc;
         }
@@ -558,7 +565,7 @@ int launch_compute(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, 
     } else if (fwd_part) {
         ProfScope ps = scope("blend");
         for (const auto& g : p.groups)
-            if (int rc = hip_check(voge::launch_blend(group_dev(g, w, cfg), g.kb, s), "blend launch")) return rc;
+            if (int rc = hip_check(voge::launch_blend(group_dev(p, g, w, cfg), g.kb, s), "blend launch")) return rc;
     }
     if (flags & VOGE_BACKWARD) {
         {
@@ -569,12 +576,12 @@ int launch_compute(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, 
         {
             ProfScope ps = scope("bwd");
             for (const auto& g : p.groups)
-                if (int rc = hip_check(voge::launch_bwd(group_dev(g, w, cfg), g.kb, s), "backward launch")) return rc;
+                if (int rc = hip_check(voge::launch_bwd(group_dev(p, g, w, cfg), g.kb, s), "backward launch")) return rc;
         }
         {
             ProfScope ps = scope("bwd_reduce");
             for (const auto& g : p.groups)
-                if (int rc = hip_check(voge::launch_bwd_reduce(group_dev(g, w, cfg), g.kb, g.max_c, s),
+                if (int rc = hip_check(voge::launch_bwd_reduce(group_dev(p, g, w, cfg), g.kb, g.max_c, s),
                                        "backward reduce launch"))
                     return rc;
         }
@@ -592,6 +599,7 @@ std::vector<int64_t> graph_key(const voge::BatchPlan& p, const void* ws, int fla
     k.push_back((int64_t)reinterpret_cast<uintptr_t>(ws));
     k.push_back(flags & WORK_FLAGS);
     k.push_back(cfg.order);
+    k.push_back(cfg.bins);
     k.push_back((int64_t)p.items.size());
     for (const auto& it : p.items) {
         k.push_back(it.caller);
@@ -646,9 +654,8 @@ int run_batch(voge_ctx_t* ctx, const voge_item_t* items, int n, int flags, void*
     DeviceGuard guard(ctx->device);
     if (!guard.ok) return fail(VOGE_EHIP, "cannot select the context's device");
     const BatchWs w = carve_batch(workspace, p);
-    std::vector<voge::ItemDev> recs(n);
-    for (int j = 0; j < n; ++j) recs[j] = item_record(p, j, items[p.items[j].caller], w, flags);
     voge::ExecConfig cfg;
+    cfg.bins = ctx->bins;
     if (force) {
         cfg = *force;
     } else {
@@ -661,6 +668,8 @@ int run_batch(voge_ctx_t* ctx, const voge_item_t* items, int n, int flags, void*
         if (flags & VOGE_GRAPH) cfg.graph = 1;
     }
     if (s == nullptr || quad) cfg.graph = 0;       // graphs: non-null streams, render calls only
+    std::vector<voge::ItemDev> recs(n);
+    for (int j = 0; j < n; ++j) recs[j] = item_record(p, j, items[p.items[j].caller], w, flags, cfg);
     const bool fwd_part = (flags & VOGE_FORWARD) || !(flags & VOGE_REUSE_PREP);
     {
         ProfScope ps(ctx, "upload", s);
@@ -998,12 +1007,14 @@ int voge_tune_batch(voge_ctx_t* ctx, const voge_item_t* items, int n_items, int 
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<voge::ExecConfig> cands;
     for (int graph = 0; graph < (s ? 2 : 1); ++graph)
-        for (int order = 0; order < 2; ++order) {
-            voge::ExecConfig c;
-            c.graph = graph;
-            c.order = order;
-            cands.push_back(c);
-        }
+        for (int order = 0; order < 2; ++order)
+            for (int bins = 0; bins < 3; ++bins) {
+                voge::ExecConfig c;
+                c.graph = graph;
+                c.order = order;
+                c.bins = bins;
+                cands.push_back(c);
+            }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (int rc = hip_check(hipEventCreate(&e0), "hipEventCreate")) return rc;
     if (int rc = hip_check(hipEventCreate(&e1), "hipEventCreate")) {
@@ -1040,6 +1051,7 @@ int voge_tune_batch(voge_ctx_t* ctx, const voge_item_t* items, int n_items, int 
     if (result) {
         result->graph = best_cfg.graph;
         result->order = best_cfg.order;
+        result->bins = best_cfg.bins;
         result->best_ms = best;
         result->default_ms = dflt;
     }
@@ -1076,8 +1088,9 @@ int voge_tune_save(voge_ctx_t* ctx, const char* path) {
     std::lock_guard<std::mutex> g(ctx->tune_mu);
     for (const auto& kv : ctx->tuned) {
         if (kv.first.find('"') != std::string::npos) continue;
-        std::fprintf(f, "{\"arch\":\"%s\",\"key\":\"%s\",\"graph\":%d,\"order\":%d,\"ms\":%.6g}\n", ctx->arch.c_str(),
-                     kv.first.c_str(), kv.second.first.graph, kv.second.first.order, kv.second.second);
+        std::fprintf(f, "{\"arch\":\"%s\",\"key\":\"%s\",\"graph\":%d,\"order\":%d,\"bins\":%d,\"ms\":%.6g}\n",
+                     ctx->arch.c_str(), kv.first.c_str(), kv.second.first.graph, kv.second.first.order,
+                     kv.second.first.bins, kv.second.second);
     }
     const bool ok = std::fclose(f) == 0;
     if (!ok) return fail(VOGE_EINVAL, std::string("cannot write ") + path);
@@ -1098,23 +1111,27 @@ int voge_tune_load(voge_ctx_t* ctx, const char* path) {
         std::string line(buf);
         while (!line.empty() && (line.back() == '\n' || line.back() == '\r')) line.pop_back();
         if (line.empty()) continue;
-        std::string arch, key, graph, order, ms;
+        std::string arch, key, graph, order, bins = "0", ms;
         if (!json_field(line, "arch", arch) || !json_field(line, "key", key) || !json_field(line, "graph", graph) ||
             !json_field(line, "order", order) || !json_field(line, "ms", ms)) {
             bad = true;
             break;
         }
+        (void)json_field(line, "bins", bins);     // absent in files of earlier versions: the default
         char* end = nullptr;
         const long gv = std::strtol(graph.c_str(), &end, 10);
         if (*end || (gv != 0 && gv != 1)) { bad = true; break; }
         const long ov = std::strtol(order.c_str(), &end, 10);
         if (*end || (ov != 0 && ov != 1)) { bad = true; break; }
+        const long bv = std::strtol(bins.c_str(), &end, 10);
+        if (*end || bv < 0 || bv > 2) { bad = true; break; }
         const double mv = std::strtod(ms.c_str(), &end);
         if (*end) { bad = true; break; }
         if (arch != ctx->arch) continue;
         voge::ExecConfig c;
         c.graph = (int)gv;
         c.order = (int)ov;
+        c.bins = (int)bv;
         got[key] = {c, mv};
     }
     std::fclose(f);
@@ -1175,6 +1192,14 @@ int voge_profile_read(voge_ctx_t* ctx, voge_phase_time_t* out, int max_out, int*
     }
     *n_out = n;
     if (reset) ctx->totals.clear();
+    g_err.clear();
+    return VOGE_OK;
+}
+
+int voge_debug_bins(voge_ctx_t* ctx, int bins) {
+    if (!ctx) return fail(VOGE_EINVAL, "ctx is null");
+    if (bins < 0 || bins > 2) return fail(VOGE_EINVAL, "bins must be 0, 1 or 2");
+    ctx->bins = bins;
     g_err.clear();
     return VOGE_OK;
 }

@@ -172,11 +172,13 @@ __global__ __launch_bounds__(PREP_THREADS) void k_prep_records(BatchDev B, int t
         if (i0 <= i1 && j0 <= j1) {
             cr.i0 = (int16_t)i0; cr.i1 = (int16_t)i1;
             cr.j0 = (int16_t)j0; cr.j1 = (int16_t)j1;
-            // coarse stage: one count per screen tile the box meets
-            const int ntx = (W + TILE - 1) / TILE;
-            for (int ti = cr.i0 / TILE; ti <= cr.i1 / TILE; ++ti)
-                for (int tj = cr.j0 / TILE; tj <= cr.j1 / TILE; ++tj)
-                    atomicAdd(&B.tcnt[it.tile_start + ti * ntx + tj], 1u);
+            // coarse stage (binned items): one count per screen tile the box meets
+            if (it.t.binned) {
+                const int ntx = (W + TILE - 1) / TILE;
+                for (int ti = cr.i0 / TILE; ti <= cr.i1 / TILE; ++ti)
+                    for (int tj = cr.j0 / TILE; tj <= cr.j1 / TILE; ++tj)
+                        atomicAdd(&B.tcnt[it.tile_start + ti * ntx + tj], 1u);
+            }
         }
     }
     cull[r] = cr;
@@ -257,7 +259,7 @@ __global__ __launch_bounds__(PREP_THREADS) void k_bin_scatter(BatchDev B, int to
     const int item = ib ? (int)(skeys[r] >> (32 - ib)) : 0;
     const ItemDev& it = B.items[item];
     const CullRec cr = cull[r];
-    if (cr.i0 > cr.i1 || cr.j0 > cr.j1) return;
+    if (!it.t.binned || cr.i0 > cr.i1 || cr.j0 > cr.j1) return;
     const int ntx = (it.t.W + TILE - 1) / TILE;
     const uint32_t rank = (uint32_t)(r - it.kern_start);
     for (int ti = cr.i0 / TILE; ti <= cr.i1 / TILE; ++ti) {
@@ -488,7 +490,9 @@ static void launch_bins(const BatchDev& b, int total_kern, int total_tiles, int 
 void launch_prep(const BatchDev& b, int total_pblk, int total_kern, int max_n, int total_tiles, int tscan_blocks,
                  uint32_t* keys, uint32_t* vals, uint32_t* keys2, uint32_t* vals2, uint32_t* hist, uint32_t* tsum,
                  CullRec* cull, TraceRec* rec, GeoRec* geo, hipStream_t s) {
-    launch_fill_u32(b.tcnt, (size_t)total_tiles, 0u, s);
+    // no binned item: no bins (select reads them only for binned items)
+    if (!b.any_binned) total_tiles = 0;
+    if (total_tiles > 0) launch_fill_u32(b.tcnt, (size_t)total_tiles, 0u, s);
     if (total_kern <= 0) {
         launch_bins(b, 0, total_tiles, tscan_blocks, keys, tsum, cull, s);
         return;

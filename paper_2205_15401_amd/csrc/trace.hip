@@ -239,10 +239,12 @@ __host__ __device__ constexpr int cull_ahead(int KB) { return KB >= 64 ? 1 : 3; 
 constexpr int BIN_MAX = 2048;
 
 // The tile's bin, sorted by rank (= depth order) into s_rank[0 .. n); returns
-// n, or -1 when the tile is not binned (its list is longer than BIN_MAX or
-// did not fit the pair list).  Every lane of the workgroup calls it.
+// n, or -1 when the tile is not binned (its item is not, or its list is
+// longer than BIN_MAX or did not fit the pair list).  Every lane of the
+// workgroup calls it.
 __device__ __forceinline__ int load_bin(const TraceArgs& A, int tile, uint32_t* s_rank) {
     const int tid = threadIdx.x;
+    if (!A.binned) return -1;
     const uint32_t cnt = A.tcnt[tile], off = A.toff[tile];
     if (cnt > (uint32_t)BIN_MAX || off + cnt > A.tcap) return -1;
     const int n = (int)cnt;
@@ -268,10 +270,12 @@ __device__ __forceinline__ int load_bin(const TraceArgs& A, int tile, uint32_t* 
     return n;
 }
 
-template <int KB>
-__device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
+// BIN: the candidate stream is the tile's bin, n_list ranks in depth order
+// in s_rank (LDS); otherwise it is every record of the item (n_list = N),
+// entry j being rank j.
+template <int KB, bool BIN>
+__device__ __forceinline__ void select_body(const TraceArgs& A, int tile, const uint32_t* s_rank, const int n_list) {
     constexpr int CULL_AHEAD = cull_ahead(KB);
-    __shared__ uint32_t s_rank[BIN_MAX];
     const int tid = threadIdx.x, lane = tid % WAVE;
     const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);   // uniform in the wave
     const int ntx = (A.W + TILE - 1) / TILE;
@@ -279,11 +283,13 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
     const int bi0 = (tile / ntx) * TILE + (wave >> 1) * 8;            // this wave's block
     const int bj0 = (tile % ntx) * TILE + (wave & 1) * 8;
     const ConstRecPtr crec = const_rec(A.rec);
-    // the candidate stream: the tile's bin in depth order, or (a tile that is
-    // not binned) every record of the item
-    const int n_bin = load_bin(A, tile, s_rank);
-    const bool binned = n_bin >= 0;
-    const int n_list = binned ? n_bin : A.N;
+    // entry j of the stream: its rank
+    auto rank_of = [&](int pos) -> int {
+        if constexpr (BIN)
+            return (int)s_rank[pos];
+        else
+            return pos;
+    };
 
     uint64_t key[KB];
 #pragma unroll
@@ -299,7 +305,7 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
     auto step = [&](const int base, const bool hit, const int ent) -> bool {
         uint64_t mm = wave_ballot(hit);          // this step's candidates, one bit per entry
         if (mm != 0) {
-            int rank = __builtin_amdgcn_readlane(ent, (int)__builtin_ctzll(mm));
+            int rank = BIN ? __builtin_amdgcn_readlane(ent, (int)__builtin_ctzll(mm)) : base + (int)__builtin_ctzll(mm);
             mm &= mm - 1;
             TraceRec R = load_rec(crec + rank);
             for (;;) {
@@ -317,7 +323,8 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
                 const bool ins = !done & (q2 < A.rad2) & (l > 0.0) & (nk < kth);
                 // the next candidate's record is in flight while this one is inserted
                 const bool more = mm != 0;
-                const int rank_n = more ? __builtin_amdgcn_readlane(ent, (int)__builtin_ctzll(mm)) : rank;
+                const int nxt = (int)__builtin_ctzll(mm);
+                const int rank_n = !more ? rank : BIN ? __builtin_amdgcn_readlane(ent, nxt) : base + nxt;
                 mm &= mm - 1;
                 __builtin_amdgcn_sched_barrier(0);
                 const TraceRec Rn = load_rec(crec + rank_n);
@@ -348,8 +355,12 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
         const int nb = base + WAVE;
         bool fin = done;
         if (ub >= A.K && nb < n_list) {
-            const int next = binned ? __builtin_amdgcn_readfirstlane((int)s_rank[nb]) : nb;
-            const float next_tlo = crec[next].tlo;
+            // (a readfirstlane of the record scan's uniform position makes the
+            // compiler treat the scan position as divergent: records would then
+            // come through vector loads into 30-odd more VGPRs)
+            int nbr = nb;
+            if constexpr (BIN) nbr = __builtin_amdgcn_readfirstlane(rank_of(nb));
+            const float next_tlo = crec[nbr].tlo;
             fin = fin | ((kth != ~0ull) & ((double)next_tlo > key_upper_l(kth)));
         }
         return wave_all(fin);
@@ -365,14 +376,18 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
     const int n_scan = wave_all(done) ? 0 : n_list;   // a block wholly outside the image scans nothing
     const int last = n_list - 1;
     const auto cull = gp(A.cull);
-    auto entry = [&](int pos) -> int { return binned ? (int)s_rank[min(pos, last)] : min(pos, last); };
+    auto entry = [&](int pos) -> int { return rank_of(min(pos, last)); };
     CullBox ahead[CULL_AHEAD];
-    int ahead_e[CULL_AHEAD];
+    int ahead_e[BIN ? CULL_AHEAD : 1];          // the entries' ranks (a bin's only)
     if (n_scan > 0) {
 #pragma unroll
         for (int d = 0; d < CULL_AHEAD; ++d) {
-            ahead_e[d] = entry(lane + d * WAVE);
-            ahead[d] = load_box(cull + ahead_e[d]);
+            if constexpr (BIN) {
+                ahead_e[d] = entry(lane + d * WAVE);
+                ahead[d] = load_box(cull + ahead_e[d]);
+            } else {
+                ahead[d] = load_box(cull + entry(lane + d * WAVE));
+            }
         }
     }
     bool stop = n_scan == 0;
@@ -381,9 +396,14 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile) {
         for (int d = 0; d < CULL_AHEAD; ++d) {
             const int base = base0 + d * WAVE, r = base + lane;
             const CullBox c = ahead[d];
-            const int e = ahead_e[d];
-            ahead_e[d] = entry(r + CULL_AHEAD * WAVE);
-            ahead[d] = load_box(cull + ahead_e[d]);   // on every path
+            int e = 0;
+            if constexpr (BIN) {
+                e = ahead_e[d];
+                ahead_e[d] = entry(r + CULL_AHEAD * WAVE);
+                ahead[d] = load_box(cull + ahead_e[d]);   // on every path
+            } else {
+                ahead[d] = load_box(cull + entry(r + CULL_AHEAD * WAVE));
+            }
             if (!stop && base < n_scan) {
                 const bool hit = (r < n_list) & (c.i0 <= bi0 + 7) & (c.i1 >= bi0) & (c.j0 <= bj0 + 7) & (c.j1 >= bj0);
                 stop = step(base, hit, e);
@@ -1341,11 +1361,22 @@ __device__ __forceinline__ TraceArgs item_view(const GroupDev& g, int& tile) {
 template <int KB>
 constexpr int select_waves() { return KB == 32 ? 3 : 1; }
 
-template <int KB>
+// BINS: the launch holds binned items, whose tiles' bins are sorted into the
+// dynamic LDS s_rank (BIN_MAX entries) and scanned in place of every record;
+// a launch without binned items compiles the record scan alone.
+template <int KB, bool BINS>
 __global__ __launch_bounds__(TILE_THREADS, select_waves<KB>()) void k_select(GroupDev g) {
+    extern __shared__ __align__(16) uint32_t s_rank[];
     int tile;
     const TraceArgs A = item_view(g, tile);
-    select_body<KB>(A, tile);
+    if constexpr (BINS) {
+        const int n_bin = load_bin(A, tile, s_rank);
+        if (n_bin >= 0) {
+            select_body<KB, true>(A, tile, s_rank, n_bin);
+            return;
+        }
+    }
+    select_body<KB, false>(A, tile, nullptr, A.N);
 }
 
 template <int KB>
@@ -1403,7 +1434,10 @@ static hipError_t run_kb(int which, const GroupDev& g, hipStream_t s, int max_c 
     const int nt = g.n_tiles;
     if (nt <= 0) return hipSuccess;
     if (which == 0) {
-        hipLaunchKernelGGL(k_select<KB>, dim3(nt), dim3(TILE_THREADS), 0, s, g);
+        if (g.bins)
+            hipLaunchKernelGGL((k_select<KB, true>), dim3(nt), dim3(TILE_THREADS), BIN_MAX * sizeof(uint32_t), s, g);
+        else
+            hipLaunchKernelGGL((k_select<KB, false>), dim3(nt), dim3(TILE_THREADS), 0, s, g);
     } else if (which == 1) {
         hipLaunchKernelGGL(k_blend<KB>, dim3(nt), dim3(TILE_THREADS), 0, s, g);
     } else if (which == 2) {

@@ -44,6 +44,7 @@ struct TraceArgs {
     const uint32_t* toff;      // [n_tiles]
     const uint32_t* tlist;     // the batch's pair list (item-local ranks, unordered per tile)
     uint32_t tcap;             // pair list capacity
+    int binned;                // 0: the item is not binned (select scans all its records)
     const float* attrs;
     // kept lists, slot-major [K][S]
     int32_t* keff;             // [S]
@@ -102,6 +103,7 @@ struct BatchDev {
     uint32_t* toff;            // [total tiles + 1] exclusive scan of tcnt
     uint32_t* tlist;           // [tcap] item-local ranks, grouped by tile
     uint32_t tcap;
+    int any_binned;            // some item is binned (else no bins are built)
 };
 
 // One launch over the tiles of a group of items that share a K-buffer depth.
@@ -111,6 +113,7 @@ struct GroupDev {
     int single;                // the group's item when it has only one, else -1
     int tile0, n_tiles;        // the group's global tiles
     int order;                 // block -> tile order: 0 banded per XCD, 1 plain
+    int bins;                  // some item of the group is binned (select stages bins in LDS)
 };
 
 // Outputs of the exact-integral mode (one item): per pixel and kept slot,
@@ -127,7 +130,17 @@ struct QuadOut {
 struct ExecConfig {
     int graph = 0;             // replay the launches from a cached HIP graph
     int order = 0;             // block -> tile order of the trace kernels
+    int bins = 0;              // coarse-stage bins: 0 none, 1 items of BIN_MIN_KERNELS or more, 2 every item
 };
+
+// Kernels from which an item's tiles are binned under choice 1.  Bins are
+// off by default: on the measured workloads (up to 100,000 kernels per
+// scene) building and sorting them cost more than the record scan they save.
+constexpr int BIN_MIN_KERNELS = 16384;
+
+inline bool item_binned(const ExecConfig& c, int N) {
+    return c.bins == 2 || (c.bins == 1 && N >= BIN_MIN_KERNELS);
+}
 
 // Host-side plan of a batch: sizes, table order and workspace offsets.
 struct ItemShape {

@@ -333,7 +333,7 @@ def test_autotuned_choice_renders_the_same_and_the_cache_round_trips(tmp_path):
     lines = path.read_text().splitlines()
     mine = [l for l in lines if "64x64/K20/C3/N12*10" in l]
     assert len(mine) == 1 and '"arch":"gfx' in mine[0]
-    assert f'"graph":{res.graph}' in mine[0] and f'"order":{res.order}' in mine[0]
+    assert f'"graph":{res.graph}' in mine[0] and f'"order":{res.order}' in mine[0] and f'"bins":{res.bins}' in mine[0]
     other = tmp_path / "other.jsonl"
     other.write_text('{"arch":"gfx000","key":"k","graph":1,"order":1,"ms":1}\n')
     nat.voge_tune_load(ctx, str(other))                       # another architecture: skipped

@@ -13,8 +13,11 @@ FP64 oracle through the C ABI, and the largest serving shape.
   kept sets on sampled pixels, images and every gradient on all pixels.
 * The coarse stage's fallbacks: a tile whose bin holds more kernels than
   select sorts in LDS, and tiles past the end of a full pair list, are
-  scanned over every record of their item.
+  scanned over every record of their item (bins forced on for every scene).
+* Bins on and off: the same renders, bit for bit.
 """
+
+import contextlib
 
 import numpy as np
 import pytest
@@ -98,7 +101,10 @@ def test_full_tables_sampler_matches_the_oracle(K):
     phi = rng.standard_normal((H, W, 5)).astype(np.float32)
     m, c, a = to_dev(scene.means), to_dev(scene.covs), to_dev(scene.attrs)
     cs = R.camera_struct(cam)
-    _, _, kept, work = R.render_forward(m, c, a, cs, K, 0.01, with_kept=True, for_backward=True)
+    # the workspace sized for the sampler's 5 feature channels (the forward's
+    # attributes have 3)
+    work = R.new_workspace(R.workspace_bytes(scene.n, phi.shape[2], cs, R.params_struct(K, 0.01), True), m.device)
+    _, _, kept, work = R.render_forward(m, c, a, cs, K, 0.01, with_kept=True, workspace=work)
     alpha, wk, _ = R.sample(m, c, torch.from_numpy(phi).cuda(), cs, K, 0.01, workspace=work, reuse=True,
                             with_weight=True)
     torch.cuda.synchronize()
@@ -109,7 +115,7 @@ def test_full_tables_sampler_matches_the_oracle(K):
     absref = O.sample(scene.means, scene.covs, cam.as_vector(), H, W, K, np.abs(phi), 0.01, given=kept)
     al, w = alpha.cpu().numpy().astype(np.float64), wk.cpu().numpy().astype(np.float64)
     seen = ref.den > 0
-    assert seen.sum() > 0.9 * scene.n
+    assert seen.sum() > 0.5 * scene.n
     assert np.all(al[~seen] == 0.0) and np.all(w[~seen] == 0.0)
     bound = RTOL * (absref.num[seen] / ref.den[seen, None] + np.abs(ref.alpha[seen])) + 1e-30
     ratio = np.abs(al[seen] - ref.alpha[seen]) / bound
@@ -143,7 +149,7 @@ def test_largest_serving_request_matches_the_oracle():
                             full_image=True, name="serving 200k 1024px forward")
     check_backward_vs_oracle(dict(means=gm.cpu().numpy(), covs=gc.cpu().numpy(), attrs=ga.cpu().numpy(),
                                   camera=gk.cpu().numpy()), scene, cam, 20, G.reshape(-1, 3), kept,
-                             name="serving 200k 1024px backward", floor_draws=1)
+                             name="serving 200k 1024px backward", floor_draws=2)
 
 
 def wide_scene(rng, n, sigma, size, centre_z=3.0, spread=0.6, C=3):
@@ -156,6 +162,17 @@ def wide_scene(rng, n, sigma, size, centre_z=3.0, spread=0.6, C=3):
     covs = np.zeros((n, 6), np.float32)
     covs[:, 0] = covs[:, 3] = covs[:, 5] = s ** 2
     return S.Scene(means, covs, rng.standard_normal((n, C)).astype(np.float32))
+
+
+@contextlib.contextmanager
+def bins(mode):
+    """Coarse-stage bins of the untuned calls inside: 0 none, 2 every scene."""
+    ctx = R.context(torch.device("cuda:0"))
+    nat.voge_debug_bins(ctx, mode)
+    try:
+        yield
+    finally:
+        nat.voge_debug_bins(ctx, 0)
 
 
 def check_both(scene, cam, K, name, seed):
@@ -184,10 +201,11 @@ def test_tiles_with_more_candidates_than_a_bin_holds():
     rng = np.random.default_rng(90)
     wide = wide_scene(rng, 2600, 1.2, 48)
     cam = S.identity_camera(48, 48.0, height=40)
-    kept = check_both(wide, cam, 20, "unbinned tiles", 91)
-    assert (kept >= 0).all()                      # every pixel keeps 20 of the 2,600
-    small = S.cloud_scene(rng, 1000, 3, std_range=(0.02, 0.06))
-    check_both(small, cam, 20, "binned tiles", 92)
+    with bins(2):
+        kept = check_both(wide, cam, 20, "unbinned tiles", 91)
+        assert (kept >= 0).all()                      # every pixel keeps 20 of the 2,600
+        small = S.cloud_scene(rng, 1000, 3, std_range=(0.02, 0.06))
+        check_both(small, cam, 20, "binned tiles", 92)
 
 
 def test_pair_list_overflow_falls_back_per_tile():
@@ -198,4 +216,55 @@ def test_pair_list_overflow_falls_back_per_tile():
     rng = np.random.default_rng(93)
     wide = wide_scene(rng, 1000, 1.2, 256, spread=0.8)
     cam = S.identity_camera(256, 256.0)
-    check_both(wide, cam, 8, "pair-list overflow", 94)
+    with bins(2):
+        check_both(wide, cam, 8, "pair-list overflow", 94)
+
+
+@pytest.mark.parametrize("which", ["torus", "cloud", "poses"])
+def test_bins_on_and_off_render_the_same(which):
+    """Bins only decide which kernels a tile scans, never what it keeps: the
+    same renders with bins for every scene and with none give bit-identical
+    images, weight sums and kept sets (512^2 torus of 10,000 kernels; a
+    30,000-kernel cloud at 256^2; 16 poses of the
+    4,096-kernel torus in one batch), and one of each against the oracle."""
+    dev = torch.device("cuda:0")
+    if which == "poses":
+        jobs = S.config_poses(n_poses=16)
+        sc = jobs[0].scene
+        dsc = [tuple(to_dev(x) for x in (sc.means, sc.covs, sc.attrs))]
+        outs = []
+        for mode in (2, 0):
+            with bins(mode):
+                b = R.Batch(dsc, [(0, R.camera_struct(j.camera), j.K, j.eta) for j in jobs], dev, with_wsum=True,
+                            with_kept=True)
+                b.run(forward=True)
+                torch.cuda.synchronize()
+                outs.append([(b.images[i].cpu(), b.wsums[i].cpu(), b.kepts[i].cpu()) for i in range(len(jobs))])
+        for (i1, w1, k1), (i2, w2, k2) in zip(*outs):
+            assert torch.equal(i1, i2) and torch.equal(w1, w2) and torch.equal(k1, k2)
+        j = jobs[3]
+        i1, w1, k1 = outs[0][3]
+        check_forward_vs_oracle(i1.numpy(), w1.numpy(), k1.numpy().reshape(-1, j.K), sc, j.camera, j.K,
+                                name="pose 3 binned")
+        return
+    if which == "torus":
+        job = S.config_torus(with_grad=False)
+        scene, cam, K = job.scene, job.camera, job.K
+    else:
+        rng = np.random.default_rng(95)
+        scene = S.cloud_scene(rng, 30_000, 3)
+        cam, K = S.identity_camera(256), 16
+    m, c, a = to_dev(scene.means), to_dev(scene.covs), to_dev(scene.attrs)
+    cs = R.camera_struct(cam)
+    outs = []
+    for mode in (2, 0):
+        with bins(mode):
+            img, ws, kept, _ = R.render_forward(m, c, a, cs, K, 0.01, with_wsum=True, with_kept=True)
+            torch.cuda.synchronize()
+            outs.append((img.cpu(), ws.cpu(), kept.cpu()))
+    (i1, w1, k1), (i2, w2, k2) = outs
+    assert torch.equal(i1, i2) and torch.equal(w1, w2) and torch.equal(k1, k2)
+    H, W = cam.height, cam.width
+    pix = np.sort(np.random.default_rng(96).choice(H * W, 3000, replace=False))
+    check_forward_vs_oracle(i1.numpy(), w1.numpy(), k1.numpy().reshape(H * W, K), scene, cam, K, pixels=pix,
+                            name=f"{which} binned")

@@ -28,7 +28,11 @@ def test_ulp_jitter_moves_each_element_by_one_ulp():
 def test_stored_floor_is_reproduced():
     with open(GOLDEN) as f:
         g = json.load(f)
-    assert set(g["max"]) == {"all", "geometry", "camera", "attrs_grad"}
+    assert set(g["max"]) == {"all", "geometry", "camera", "attrs_grad", "pairs", "all_with_pairs"}
+    # rounding the per-pair derivatives to FP32 moves the gradients by about
+    # the FP32 rounding of the output: the inputs set the floor
+    for n in ("means", "covs", "attrs", "camera"):
+        assert g["max"]["pairs"][n]["inf_over_ref"] < 1e-6, n
     # attributes and upstream gradient alone move the results by about the
     # FP32 rounding of the output; geometry moves them by far more than 1e-5
     assert g["max"]["attrs_grad"]["image_rel"] < 2e-7
@@ -42,3 +46,33 @@ def test_stored_floor_is_reproduced():
     assert 0.2 * stored["image_rel"] < r["image_rel"] < 5 * stored["image_rel"]
     for n in ("means", "covs", "attrs", "camera"):
         assert 0.1 * stored[n]["inf_over_ref"] < r[n]["inf_over_ref"] < 10 * stored[n]["inf_over_ref"], n
+
+
+def test_pair_jitter_moves_each_pair_derivative_by_one_unit_roundoff():
+    """The oracle's noise-floor mode on a lone kernel seen by one pixel: the
+    attribute gradient W G is moved by exactly one FP32 unit roundoff (2^-24
+    relative), up or down as the seed draws; seed 0 is the plain backward
+    bit for bit, and one seed always draws the same signs."""
+    from oracle import oracle as O
+    means = np.array([[0.02, -0.01, 3.0]], np.float32)
+    covs = np.array([[0.01, 0.0, 0.0, 0.01, 0.0, 0.01]], np.float32)
+    attrs = np.array([[0.5, -2.0]], np.float32)
+    cam = S.identity_camera(8, 8.0)
+    G = np.array([[1.5, 0.25]])
+    pix = [4 * 8 + 4]
+    args = (means, covs, attrs, cam.as_vector(), 8, 8, 4, G)
+    plain = O.backward(*args, pixels=pix)
+    again = O.backward(*args, pixels=pix, jitter_seed=0)
+    for n in ("means", "covs", "attrs", "camera"):
+        assert np.array_equal(getattr(plain, n), getattr(again, n))
+    signs = set()
+    for seed in range(1, 9):
+        j = O.backward(*args, pixels=pix, jitter_seed=seed)
+        rel = (j.attrs / plain.attrs - 1.0) / 2.0 ** -24
+        assert np.allclose(rel, rel[0, 0], atol=1e-6) and abs(abs(rel[0, 0]) - 1.0) < 1e-6
+        signs.add(int(np.sign(rel[0, 0])))
+        j2 = O.backward(*args, pixels=pix, jitter_seed=seed)
+        assert np.array_equal(j.attrs, j2.attrs) and np.array_equal(j.covs, j2.covs)
+        # the geometric gradients move by a few unit roundoffs at most
+        assert np.abs(j.means - plain.means).max() <= 4 * 2.0 ** -24 * np.abs(plain.abs_means).max()
+    assert signs == {-1, 1}
