@@ -576,13 +576,7 @@ int launch_compute(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, 
         {
             ProfScope ps = scope("bwd");
             for (const auto& g : p.groups)
-                if (int rc = hip_check(voge::launch_bwd(group_dev(p, g, w, cfg), g.kb, s), "backward launch")) return rc;
-        }
-        {
-            ProfScope ps = scope("bwd_reduce");
-            for (const auto& g : p.groups)
-                if (int rc = hip_check(voge::launch_bwd_reduce(group_dev(p, g, w, cfg), g.kb, g.max_c, s),
-                                       "backward reduce launch"))
+                if (int rc = hip_check(voge::launch_bwd(group_dev(p, g, w, cfg), g.kb, g.max_c, s), "backward launch"))
                     return rc;
         }
         {

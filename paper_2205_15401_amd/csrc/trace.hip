@@ -1,6 +1,5 @@
 // trace.hip -- per-pixel ray tracing and K-nearest selection (k_select),
-// erf-sum transmittance and blending (k_blend), and the backward (k_bwd_pix,
-// k_bwd_red).
+// erf-sum transmittance and blending (k_blend), and the backward (k_bwd).
 //
 // Every kernel maps one workgroup of 256 lanes to one 16x16 screen tile of
 // some item of the batch; each wave owns an 8x8 block and each lane one
@@ -23,8 +22,8 @@
 //     depth floor; the wave stops when all its pixels are done.
 //   k_blend -- E_k = sum_m e^{q_m} Phi((l_k - l_m) sqrt(a_m)) (Eq. 7 at
 //     t = l_k; App. A.2), T_k = exp(-E_k), W_k = T_k e^{q_k}, C = sum W_k c_k (Eq. 8).
-//   k_bwd_pix, k_bwd_red -- gradients of C with the kept sets fixed (formulas
-//     above bwd_pix_body).
+//   k_bwd -- gradients of C with the kept sets fixed (formulas above
+//     bwd_pix_body): a pixel phase, then a tile reduction.
 //
 // D' is F times the paper's D: l * D', q, the erf arguments and every weight
 // are unchanged by that scale; only l itself scales.
@@ -764,7 +763,7 @@ __host__ __device__ constexpr int red_ch(int KB) { return KB >= 64 ? 4 : 8; }
 constexpr int GRAD_STAGE_CH = 4;
 __host__ __device__ constexpr bool red_stage_grad(int KB, int max_c) { return KB < 64 && max_c <= GRAD_STAGE_CH; }
 
-// LDS of k_bwd_red: the hash table (keys, pair counts, offsets and the
+// LDS of the tile reduction: the hash table (keys, pair counts, offsets and the
 // compact list of used entries, hcap ints each), later reused for the
 // reduction's partial sums (head and tail runs of every lane, nv values
 // each: the 9 geometric ones and one pass's channels); then the tile's pairs
@@ -1394,18 +1393,22 @@ __global__ __launch_bounds__(TILE_THREADS) void k_blend_sample(GroupDev g) {
     blend_body<KB, true>(A, tile, smem);
 }
 
+// The backward of a tile: the pixel phase leaves its per-pair scalars in the
+// slot-major scratch lists, and after a workgroup barrier (which makes the
+// workgroup's global writes visible to all its lanes) the tile reduction
+// reads them back while they are still in the XCD's L2.  Waves per SIMD the
+// register allocation must fit: three up to a K-buffer of 20 (a cap of 168
+// VGPRs), two at 32; at 64 a tighter cap would spill.
 template <int KB>
-__global__ __launch_bounds__(TILE_THREADS) void k_bwd_pix(GroupDev g) {
-    int tile;
-    const TraceArgs A = item_view(g, tile);
-    bwd_pix_body<KB>(A, tile);
-}
+constexpr int bwd_waves() { return KB <= 20 ? 3 : KB <= 32 ? 2 : 1; }
 
 template <int KB>
-__global__ __launch_bounds__(TILE_THREADS) void k_bwd_red(GroupDev g, int hcap, int stage_grad) {
+__global__ __launch_bounds__(TILE_THREADS, bwd_waves<KB>()) void k_bwd(GroupDev g, int hcap, int stage_grad) {
     extern __shared__ __align__(16) unsigned char smem[];
     int tile;
     const TraceArgs A = item_view(g, tile);
+    bwd_pix_body<KB>(A, tile);
+    __syncthreads();
     bwd_red_body<KB>(A, hcap, stage_grad != 0, tile, smem);
 }
 
@@ -1441,10 +1444,8 @@ static hipError_t run_kb(int which, const GroupDev& g, hipStream_t s, int max_c 
     } else if (which == 1) {
         hipLaunchKernelGGL(k_blend<KB>, dim3(nt), dim3(TILE_THREADS), 0, s, g);
     } else if (which == 2) {
-        hipLaunchKernelGGL(k_bwd_pix<KB>, dim3(nt), dim3(TILE_THREADS), 0, s, g);
-    } else if (which == 3) {
         const int hcap = table_capacity(0);
-        hipLaunchKernelGGL(k_bwd_red<KB>, dim3(nt), dim3(TILE_THREADS), bwd_lds_bytes(hcap, KB, max_c), s, g, hcap,
+        hipLaunchKernelGGL(k_bwd<KB>, dim3(nt), dim3(TILE_THREADS), bwd_lds_bytes(hcap, KB, max_c), s, g, hcap,
                            red_stage_grad(KB, max_c) ? 1 : 0);
     } else {
         hipLaunchKernelGGL(k_blend_sample<KB>, dim3(nt), dim3(TILE_THREADS), sample_lds_bytes(max_c), s, g);
@@ -1464,10 +1465,7 @@ static hipError_t dispatch(int which, const GroupDev& g, int kb, hipStream_t s, 
 
 hipError_t launch_select(const GroupDev& g, int kb, hipStream_t s) { return dispatch(0, g, kb, s); }
 hipError_t launch_blend(const GroupDev& g, int kb, hipStream_t s) { return dispatch(1, g, kb, s); }
-hipError_t launch_bwd(const GroupDev& g, int kb, hipStream_t s) { return dispatch(2, g, kb, s); }
-hipError_t launch_bwd_reduce(const GroupDev& g, int kb, int max_c, hipStream_t s) {
-    return dispatch(3, g, kb, s, max_c);
-}
+hipError_t launch_bwd(const GroupDev& g, int kb, int max_c, hipStream_t s) { return dispatch(2, g, kb, s, max_c); }
 hipError_t launch_blend_sample(const GroupDev& g, int kb, int max_c, hipStream_t s) {
     return dispatch(4, g, kb, s, max_c);
 }
