@@ -14,7 +14,9 @@ and, as context: the forward alone of the same batch; the single 512x512
 image of the 10,000-kernel torus (16 channels) per call, forward + backward
 and forward alone; the plain forward of one 64x64 image of 512 spheres (per
 call and graph-replayed); the uneven batch of 64 ellipsoid clouds (one batch
-call against one call per scene); the sampler, the fitting loop and the
+call against one call per scene); select's time against the kernel count
+(tori of 10k-200k kernels at 512^2, with and without coarse-stage bins);
+the sampler, the fitting loop and the
 exact-integral mode; and the serving loop on a request mix (resident scenes
 of 10k-200k kernels, 128^2-1024^2 images, half gradient requests, Poisson
 arrivals at 0.5, 0.7 and 0.9 of the one-at-a-time capacity).  Prints ONE
@@ -534,6 +536,46 @@ def bench_small(args, torch, dev):
                       "latency_us": {"p50": round(pct(per_g, 50) * 1e3, 2), "p99": round(pct(per_g, 99) * 1e3, 2)}}}
 
 
+def bench_select_curve(args, torch, dev):
+    """Select's time against the kernel count: tori of 10,000-200,000
+    flattened kernels (the 512x512 torus generator, 3 channels) rendered
+    forward at 512x512, K = 20, with no coarse-stage bins (every 8x8 block
+    scans every kernel's screen box) and with bins for every scene (a tile
+    scans its bin); the select and prep phases timed with HIP events."""
+    import numpy as np
+    from paper_2205_15401_amd import _native as nat
+    from paper_2205_15401_amd import render as R
+    from paper_2205_15401_amd import scenes as S
+
+    ctx = R.context(dev)
+    cam = R.camera_struct(S.identity_camera(512))
+    out = []
+    for n in args.curve_sizes:
+        sc = S.torus_scene(np.random.default_rng(11), n, 3)
+        m, c, a = (torch.from_numpy(x).to(dev) for x in (sc.means, sc.covs, sc.attrs))
+        wsb = nat.voge_workspace_size(n, 3, cam, R.params_struct(20, 0.01), False)
+        work = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        row = {"kernels": n}
+        for mode, name in ((0, "no_bins"), (2, "bins")):
+            nat.voge_debug_bins(ctx, mode)
+            for _ in range(2):
+                R.render_forward(m, c, a, cam, 20, 0.01, workspace=work)
+            torch.cuda.synchronize()
+            nat.voge_profile_enable(ctx, True)
+            nat.voge_profile_read(ctx, reset=True)
+            for _ in range(args.curve_steps):
+                R.render_forward(m, c, a, cam, 20, 0.01, workspace=work)
+            torch.cuda.synchronize()
+            ph = nat.voge_profile_read(ctx, reset=True)
+            nat.voge_profile_enable(ctx, False)
+            row[name] = {k: round(ph[k][0] / max(ph[k][1], 1) * 1e3, 2) for k in ("select", "prep", "blend") if k in ph}
+        nat.voge_debug_bins(ctx, 0)
+        log(f"[bench] select vs N: {n} kernels: no bins {row['no_bins']}, bins {row['bins']} (us)")
+        out.append(row)
+        del work
+    return {"workload": "torus of N flattened kernels, 512x512, K=20, C=3, forward", "phases_us": out}
+
+
 def bench_uneven(args, torch, dev):
     """The uneven batch: 64 ellipsoid clouds of 1,000-100,000 kernels,
     64^2-512^2 images, K in {8, 16, 32}, forward + backward; one
@@ -732,6 +774,9 @@ def main():
                     help="quadrature points per pixel of the exact-integral leg (0 = skip)")
     ap.add_argument("--small-steps", type=int, default=200, help="timed steps of the 64x64 forward (0 = skip)")
     ap.add_argument("--uneven-steps", type=int, default=5, help="timed steps of the uneven 64-scene batch (0 = skip)")
+    ap.add_argument("--curve-steps", type=int, default=5, help="timed forwards per size of the select-vs-N curve (0 = skip)")
+    ap.add_argument("--curve-sizes", type=lambda t: [int(x) for x in t.split(",")],
+                    default=[10_000, 25_000, 50_000, 100_000, 200_000])
     ap.add_argument("--serving-requests", type=int, default=2000, help="timed requests per load (0 = skip serving)")
     ap.add_argument("--serving-warmup", type=int, default=200)
     ap.add_argument("--serving-capacity-requests", type=int, default=200)
@@ -778,6 +823,7 @@ def main():
     quad = bench_quadrature(args, torch, dev) if args.quad_samples > 0 else None
     small = bench_small(args, torch, dev) if args.small_steps > 0 else None
     uneven = bench_uneven(args, torch, dev) if args.uneven_steps > 0 else None
+    curve = bench_select_curve(args, torch, dev) if args.curve_steps > 0 else None
     single = bench_torus(args, torch, dev) if args.torus_steps > 0 else None
     serving = bench_serving(args, torch, dev) if args.serving_requests > 0 else None
     calibration_copy()
@@ -839,6 +885,7 @@ def main():
         "single_image": single,
         "small_forward": small,
         "uneven_batch": uneven,
+        "select_vs_kernels": curve,
         "serving": serving,
         "phases_us": {k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in r["phases"].items()},
         "roofline": roofline,

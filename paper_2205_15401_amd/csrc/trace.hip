@@ -166,14 +166,17 @@ __device__ __forceinline__ double key_upper_l(uint64_t key) {
 
 // Write key nk into slot t (t = -1: this lane inserts nothing): a lane
 // holding n < K keys appends at t = n, a full lane overwrites the slot of its
-// largest key.  One in-place pass over slots 0 .. lim (lim wave-uniform: the
-// largest fill count, or K-1 when a full lane inserts), one compare and two
-// selects per slot.
+// largest key.  One in-place pass over the groups of four slots up to lim
+// (lim wave-uniform: the largest fill count, or K-1 when a full lane
+// inserts) that some lane writes, one compare and two selects per slot.
 template <int KB>
 __device__ __forceinline__ void kbuf_put(uint64_t (&key)[KB], uint64_t nk, int t, int lim) {
+    const int tg = t >> 2;                       // the lane's group of four slots (-1: none)
 #pragma unroll
     for (int s0 = 0; s0 < KB; s0 += 4) {
-        if (s0 <= lim) {
+        // only groups that some lane writes (a vote per group: the writes of
+        // one candidate land in one or two groups, appends near the fill counts)
+        if (s0 <= lim && wave_any(tg == (s0 >> 2))) {
 #pragma unroll
             for (int s = s0; s < s0 + 4 && s < KB; ++s) key[s] = s == t ? nk : key[s];
         }
