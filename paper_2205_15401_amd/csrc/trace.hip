@@ -34,25 +34,29 @@ namespace voge {
 
 constexpr float INV_SQRT_PI = 0.564189583547756287f;
 
-// Phi(x) = (1 + erf x)/2 = erfc(-x)/2.  erfc(z), z >= 0, by the Chebyshev fit
-// "erfcc" of Press et al., Numerical Recipes (2nd ed., Sec. 6.2):
-//   t = 1/(1 + z/2),  erfc(z) = t exp(-z^2 + P(t)),  fractional error < 1.2e-7.
-// Branch-free; one reciprocal and one exponential.
-__device__ __forceinline__ float phi_cdf(float x) {
+// Phi(x) = (1 + erf x)/2 = erfc(-x)/2, with erfc(z), z = |x|, as
+//   erfc(z) = t Q(t) e^{-z^2},   t = 1/(1 + z/2),
+// Q a degree-8 polynomial fitted to e^{z^2} erfc(z) / t (relative error
+// 4.5e-8; the fit and its method: phi_fit.py; the coefficients below are
+// Q's halved).  In FP32, |Phi - (1 + erf x)/2| < 2e-7.  Branch-free: one
+// reciprocal and the exponential e^{-x^2}, which the backward shares with
+// the density Phi'(x) = e^{-x^2}/sqrt(pi).
+__device__ __forceinline__ float phi_from(float x, float e) {
     const float z = fabsf(x);
     const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, z, 1.0f));
-    float p = fmaf(t, 0.17087277f, -0.82215223f);
-    p = fmaf(t, p, 1.48851587f);
-    p = fmaf(t, p, -1.13520398f);
-    p = fmaf(t, p, 0.27886807f);
-    p = fmaf(t, p, -0.18628806f);
-    p = fmaf(t, p, 0.09678418f);
-    p = fmaf(t, p, 0.37409196f);
-    p = fmaf(t, p, 1.00002368f);
-    p = fmaf(t, p, -1.26551223f);
-    const float h = 0.5f * t * __expf(fmaf(-z, z, p));   // erfc(z) / 2
+    float q = fmaf(t, -0.0297155753f, 0.143165097f);
+    q = fmaf(t, q, -0.245402336f);
+    q = fmaf(t, q, 0.141075402f);
+    q = fmaf(t, q, -0.0147031052f);
+    q = fmaf(t, q, 0.101923697f);
+    q = fmaf(t, q, 0.121407524f);
+    q = fmaf(t, q, 0.141207144f);
+    q = fmaf(t, q, 0.141042113f);
+    const float h = t * q * e;                     // erfc(z) / 2
     return x >= 0.f ? 1.0f - h : h;
 }
+
+__device__ __forceinline__ float phi_cdf(float x) { return phi_from(x, __expf(-x * x)); }
 
 struct PixelCtx {
     int pi, pj;
@@ -766,8 +770,8 @@ __host__ __device__ constexpr int red_ch(int KB) { return KB >= 64 ? 4 : 8; }
 constexpr int GRAD_STAGE_CH = 4;
 __host__ __device__ constexpr bool red_stage_grad(int KB, int max_c) { return KB < 64 && max_c <= GRAD_STAGE_CH; }
 
-// LDS of the tile reduction: the hash table (keys, pair counts, offsets and the
-// compact list of used entries, hcap ints each), later reused for the
+// LDS of the tile reduction: the hash table (keys, pair counts and offsets,
+// hcap ints each), later reused for the
 // reduction's partial sums (head and tail runs of every lane, nv values
 // each: the 9 geometric ones and one pass's channels); then the tile's pairs
 // in kernel order as 16-bit indices (256 * KB of them); then, when staged,
@@ -775,7 +779,7 @@ __host__ __device__ constexpr bool red_stage_grad(int KB, int max_c) { return KB
 __host__ __device__ inline int bwd_partial_values(int C, int KB) { return 9 + (C < red_ch(KB) ? C : red_ch(KB)); }
 
 __host__ __device__ inline size_t bwd_table_bytes(int hcap, int nv) {
-    const size_t table = (size_t)hcap * 4 * sizeof(int);
+    const size_t table = (size_t)hcap * 3 * sizeof(int);
     const size_t partials = (size_t)TILE_THREADS * (2 * nv * sizeof(float) + 2 * sizeof(int));
     return ((table > partials ? table : partials) + 15) & ~(size_t)15;
 }
@@ -941,8 +945,9 @@ __device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile) {
                 for (int k = k0; k < k0 + 4 && k < KB; ++k) {
                     const float d = (float)(lk[k] - lm);
                     const float x = d * sm;
-                    const float Phi = phi_cdf(x);
-                    const float dPhi = __expf(-x * x) * INV_SQRT_PI;
+                    const float ex = __expf(-x * x);
+                    const float Phi = phi_from(x, ex);
+                    const float dPhi = ex * INV_SQRT_PI;
                     acc_dm = fmaf(dE[k], Phi, acc_dm);
                     const float dx = dE[k] * mm * dPhi;
                     const float t = dx * sm;
@@ -968,8 +973,7 @@ __device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile) {
 template <int KB>
 __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, bool stage, int tile, unsigned char* smem) {
     __shared__ double s_red[TILE_THREADS / WAVE][3];
-    __shared__ int s_scan[TILE_THREADS];
-    __shared__ int s_scan2[TILE_THREADS];
+    __shared__ int s_wtot[TILE_THREADS / WAVE];
     const int tid = threadIdx.x;
     const int ntx = (A.W + TILE - 1) / TILE;
     const PixelCtx P = pixel_of(tile, ntx, A.H, A.W, A.cx, A.cy);
@@ -978,8 +982,6 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, bool 
     int* s_hkey = reinterpret_cast<int*>(smem);
     int* s_cnt = s_hkey + hcap;
     int* s_off = s_cnt + hcap;
-    int* s_used = s_off + hcap;
-    __shared__ int s_nused;
     for (int i = tid; i < hcap; i += TILE_THREADS) {
         s_hkey[i] = -1;
         s_cnt[i] = 0;
@@ -1019,38 +1021,33 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, bool 
     for (int k = 0; k < KB; ++k)
         if (sp[k] >= 0) sp[k] = (sp[k] << 16) | atomicAdd(&s_cnt[sp[k]], 1);
     __syncthreads();
-    // exclusive scans: s_cnt -> s_off, and the used entries -> s_used
+    // exclusive scan s_cnt -> s_off: each lane sums its run of entries, the
+    // wave scans the sums with shuffles, and one barrier exchanges the wave
+    // totals
     {
         const int per = (hcap + TILE_THREADS - 1) / TILE_THREADS;
-        int run = 0, nu = 0;
+        const int lane = tid % WAVE, wave = tid / WAVE;
+        int run = 0;
         for (int j = 0; j < per; ++j) {
             const int i = tid * per + j;
-            if (i < hcap) {
-                run += s_cnt[i];
-                nu += s_cnt[i] > 0;
-            }
+            if (i < hcap) run += s_cnt[i];
         }
-        s_scan[tid] = run;
-        s_scan2[tid] = nu;
+        int inc = run;
+        for (int off = 1; off < WAVE; off <<= 1) {
+            const int y = __shfl_up(inc, off);
+            if (lane >= off) inc += y;
+        }
+        if (lane == WAVE - 1) s_wtot[wave] = inc;
         __syncthreads();
-        for (int off = 1; off < TILE_THREADS; off <<= 1) {
-            const int y = tid >= off ? s_scan[tid - off] : 0;
-            const int y2 = tid >= off ? s_scan2[tid - off] : 0;
-            __syncthreads();
-            s_scan[tid] += y;
-            s_scan2[tid] += y2;
-            __syncthreads();
-        }
-        int base = s_scan[tid] - run, ub = s_scan2[tid] - nu;
+        for (int w = 0; w < wave; ++w) inc += s_wtot[w];
+        int base = inc - run;
         for (int j = 0; j < per; ++j) {
             const int i = tid * per + j;
             if (i < hcap) {
                 s_off[i] = base;
                 base += s_cnt[i];
-                if (s_cnt[i] > 0) s_used[ub++] = i;
             }
         }
-        if (tid == TILE_THREADS - 1) s_nused = s_scan2[tid];
     }
     __syncthreads();
     double gD[3] = {0.0, 0.0, 0.0};
