@@ -38,12 +38,21 @@ constexpr float INV_SQRT_PI = 0.564189583547756287f;
 //   erfc(z) = t Q(t) e^{-z^2},   t = 1/(1 + z/2),
 // Q a degree-8 polynomial fitted to e^{z^2} erfc(z) / t (relative error
 // 4.5e-8; the fit and its method: phi_fit.py; the coefficients below are
-// Q's halved).  In FP32, |Phi - (1 + erf x)/2| < 2e-7.  Branch-free: one
-// reciprocal and the exponential e^{-x^2}, which the backward shares with
-// the density Phi'(x) = e^{-x^2}/sqrt(pi).
-__device__ __forceinline__ float phi_from(float x, float e) {
-    const float z = fabsf(x);
-    const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, z, 1.0f));
+// Q's halved).  The argument comes scaled, xs = x sqrt(log2 e), so that
+// e^{-x^2} = 2^{-xs^2} is one multiply and one hardware exp2; then
+// t = 1/(1 + z/2) = 1/(1 + |xs| / (2 sqrt(log2 e))).  In FP32,
+// |Phi - (1 + erf x)/2| < 2e-7.  Branch-free: one reciprocal and the
+// exponential, which the backward shares with the density
+// Phi'(x) = e^{-x^2}/sqrt(pi).
+constexpr float SQRT_LOG2E = 1.20112240878645f;       // sqrt(log2 e)
+constexpr float HALF_OVER_SQRT_LOG2E = 0.416277306f;  // 1 / (2 sqrt(log2 e))
+
+// e^{-x^2} from the scaled argument xs = x sqrt(log2 e)
+__device__ __forceinline__ float gauss_scaled(float xs) { return __builtin_amdgcn_exp2f(-xs * xs); }
+
+__device__ __forceinline__ float phi_from(float xs, float e) {
+    const float z = fabsf(xs);
+    const float t = __builtin_amdgcn_rcpf(fmaf(HALF_OVER_SQRT_LOG2E, z, 1.0f));
     float q = fmaf(t, -0.0297155753f, 0.143165097f);
     q = fmaf(t, q, -0.245402336f);
     q = fmaf(t, q, 0.141075402f);
@@ -53,10 +62,13 @@ __device__ __forceinline__ float phi_from(float x, float e) {
     q = fmaf(t, q, 0.141207144f);
     q = fmaf(t, q, 0.141042113f);
     const float h = t * q * e;                     // erfc(z) / 2
-    return x >= 0.f ? 1.0f - h : h;
+    return xs >= 0.f ? 1.0f - h : h;
 }
 
-__device__ __forceinline__ float phi_cdf(float x) { return phi_from(x, __expf(-x * x)); }
+__device__ __forceinline__ float phi_cdf(float x) {
+    const float xs = x * SQRT_LOG2E;
+    return phi_from(xs, gauss_scaled(xs));
+}
 
 struct PixelCtx {
     int pi, pj;
@@ -559,7 +571,7 @@ __device__ __forceinline__ void blend_body(const TraceArgs& A, int tile, unsigne
     float mn = keff > 0 ? pm[0] : 0.f, sn = keff > 0 ? ps[0] : 1.f;
     for (int m = 0; m < kmax; ++m) {
         const double lm = ln;
-        const float mm = mn, sm = sn;
+        const float mm = mn, sms = sn * SQRT_LOG2E;
         const bool nin = m + 1 < keff;
         const size_t o = (size_t)(m + 1) * S;
         ln = nin ? pl[o] : 0.0;
@@ -571,8 +583,8 @@ __device__ __forceinline__ void blend_body(const TraceArgs& A, int tile, unsigne
             if (k0 < kmax) {
 #pragma unroll
                 for (int k = k0; k < k0 + 4 && k < KB; ++k) {
-                    const float x = (float)(lk[k] - lm) * sm;
-                    E[k] = fmaf(mm, phi_cdf(x), E[k]);
+                    const float xs = (float)(lk[k] - lm) * sms;
+                    E[k] = fmaf(mm, phi_from(xs, gauss_scaled(xs)), E[k]);
                 }
             }
         }
@@ -759,6 +771,9 @@ __device__ __forceinline__ void pair_chain(const GeoRec& G, double D0, double D1
     gD[2] += dq * l * SV2 + dlk * (SV2 - l * SD2) + 2.0 * dat * SD2;
 }
 
+// Pairs of a lane's chunk whose loads the tile reduction issues together.
+constexpr int RED_BATCH = 4;
+
 // Attribute channels per reduction pass: fewer at the deepest K-buffer, so
 // that the partial sums and the pair indices fit 64 KB of LDS.
 __host__ __device__ constexpr int red_ch(int KB) { return KB >= 64 ? 4 : 8; }
@@ -786,7 +801,10 @@ __host__ __device__ inline size_t bwd_table_bytes(int hcap, int nv) {
 
 size_t bwd_lds_bytes(int hcap, int KB, int max_c) {
     const size_t grad = red_stage_grad(KB, max_c) ? (size_t)TILE_THREADS * GRAD_STAGE_CH * sizeof(float) : 0;
-    return bwd_table_bytes(hcap, bwd_partial_values(max_c, KB)) + (size_t)TILE_THREADS * KB * sizeof(uint16_t) + grad;
+    const size_t red =
+        bwd_table_bytes(hcap, bwd_partial_values(max_c, KB)) + (size_t)TILE_THREADS * KB * sizeof(uint16_t) + grad;
+    const size_t pix = (size_t)TILE_THREADS * KB * sizeof(float);   // the pixel phase's g_k T_k
+    return red > pix ? red : pix;
 }
 
 // The original index of the kernel of a rank (the accumulators are kept in
@@ -812,7 +830,7 @@ __device__ __forceinline__ void flush_values(const TraceArgs& A, size_t n, const
 
 // Backward, pixel phase: per-pair scalars (dq, dl, da, W) into the scratch list.
 template <int KB>
-__device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile) {
+__device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile, float* s_dmd) {
     const int ntx = (A.W + TILE - 1) / TILE;
     const PixelCtx P = pixel_at(tile, balanced_slot(A, tile, ntx), ntx, A.H, A.W, A.cx, A.cy);
     const size_t S = A.S;
@@ -830,14 +848,13 @@ __device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile) {
     const auto Gp = gp(A.grad_image) + p * C;
 
     double lk[KB];
-    float dE[KB], dl[KB], dmd[KB];
+    float dE[KB], dl[KB];
     int ik[KB];
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
         lk[k] = 0.0;
         dE[k] = 0.f;
         dl[k] = 0.f;
-        dmd[k] = 0.f;
         ik[k] = 0;
         if (k < keff) {
             lk[k] = pl[(size_t)k * S];
@@ -910,20 +927,24 @@ __device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile) {
     }
     // the ablations stop the path through T (dE) or the direct factor e^q (dmd)
     const bool keep_T = !(A.grad_mode & 1), keep_rho = !(A.grad_mode & 2);
+    // g_k T_k waits in LDS (slot k of the lane at s_dmd[k * 256 + lane]) for
+    // the pass over m = k
+    const int tid = threadIdx.x;
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
         if (k < keff) {
             const float T = pT[(size_t)k * S];
             const float W = T * pm[(size_t)k * S];
             dE[k] = keep_T ? -g[k] * W : 0.f;
-            dmd[k] = keep_rho ? g[k] * T : 0.f;
+            s_dmd[k * TILE_THREADS + tid] = keep_rho ? g[k] * T : 0.f;
         }
     }
     // pair loop: m streams from the list (slot m+1 is loaded while slot m is
     // computed); after the sums over k, slot m's scalars are complete except
     // the k-side part of dL/dl, which goes to its own list at the end:
-    //   dq = (g_m T_m + sum_k dE_k Phi_km) m_m,  dl = -sum_k t_km (+ dl[m] later),
-    //   da = sum_k dx_km d_km / (2 s_m),  W = T_m m_m
+    //   dq = (g_m T_m + sum_k dE_k Phi_km) m_m,  dl = -s_m sum_k dx_km (+ dl[m] later),
+    //   da = sum_k dx_km d_km / (2 s_m),  W = T_m m_m,
+    // with dx_km = dE_k m_m Phi'(x_km), x_km = d_km s_m, d_km = l_k - l_m
     double ln = keff > 0 ? pl[0] : 0.0;
     float mn = keff > 0 ? pm[0] : 0.f, sn = keff > 0 ? ps[0] : 1.f, tn = keff > 0 ? pT[0] : 0.f;
     for (int m = 0; m < kmax; ++m) {
@@ -936,31 +957,28 @@ __device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile) {
         mn = nin ? pm[o + S] : 0.f;
         sn = nin ? ps[o + S] : 1.f;
         tn = nin ? pT[o + S] : 0.f;
-        const float hs = 0.5f / sm;
-        float acc_dm = 0.f, acc_dl = 0.f, acc_da = 0.f;
+        const float sms = sm * SQRT_LOG2E, mmc = mm * INV_SQRT_PI;
+        float acc_dm = 0.f, acc_dx = 0.f, acc_dd = 0.f;
 #pragma unroll
         for (int k0 = 0; k0 < KB; k0 += 4) {
             if (k0 < kmax) {
 #pragma unroll
                 for (int k = k0; k < k0 + 4 && k < KB; ++k) {
                     const float d = (float)(lk[k] - lm);
-                    const float x = d * sm;
-                    const float ex = __expf(-x * x);
-                    const float Phi = phi_from(x, ex);
-                    const float dPhi = ex * INV_SQRT_PI;
-                    acc_dm = fmaf(dE[k], Phi, acc_dm);
-                    const float dx = dE[k] * mm * dPhi;
-                    const float t = dx * sm;
-                    dl[k] += t;
-                    acc_dl -= t;
-                    acc_da = fmaf(dx, d * hs, acc_da);
+                    const float xs = d * sms;
+                    const float ex = gauss_scaled(xs);
+                    acc_dm = fmaf(dE[k], phi_from(xs, ex), acc_dm);
+                    const float dx = dE[k] * mmc * ex;
+                    dl[k] = fmaf(dx, sm, dl[k]);
+                    acc_dx += dx;
+                    acc_dd = fmaf(dx, d, acc_dd);
                 }
             }
         }
-        float dmd_m = 0.f;                       // dmd[m], m uniform in the wave
-#pragma unroll
-        for (int k = 0; k < KB; ++k) dmd_m = k == m ? dmd[k] : dmd_m;
-        if (in) st_f4(pbw + o, make_float4((dmd_m + acc_dm) * mm, acc_dl, acc_da, tm * mm));
+        if (in) {
+            const float dmd_m = s_dmd[m * TILE_THREADS + tid];
+            st_f4(pbw + o, make_float4((dmd_m + acc_dm) * mm, -sm * acc_dx, acc_dd * (0.5f / sm), tm * mm));
+        }
     }
     // the k-side part of dL/dl of each slot
     const auto pbl = gp(A.bwl) + P.q;
@@ -970,8 +988,12 @@ __device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile) {
 }
 
 // Backward, tile phase: group the tile's pairs by kernel and reduce them.
-template <int KB>
-__device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, bool stage, int tile, unsigned char* smem) {
+// NARROW: every item of the launch has at most GRAD_STAGE_CH channels (one
+// pass of that many channels; the upstream gradient staged in LDS below the
+// deepest K-buffer).
+template <int KB, bool NARROW>
+__device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int tile, unsigned char* smem) {
+    constexpr bool stage = NARROW && red_stage_grad(KB, GRAD_STAGE_CH);
     __shared__ double s_red[TILE_THREADS / WAVE][3];
     __shared__ int s_wtot[TILE_THREADS / WAVE];
     const int tid = threadIdx.x;
@@ -990,7 +1012,7 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, bool 
     const size_t p = (size_t)P.pi * A.W + P.pj;
     const float* Gp = A.grad_image + p * C;
     const size_t q0 = (size_t)tile * TILE_THREADS;            // the tile's first list index
-    constexpr int RED_CH = red_ch(KB);          // attribute channels per reduction pass
+    constexpr int RED_CH = NARROW ? GRAD_STAGE_CH : red_ch(KB);   // attribute channels per reduction pass
     constexpr int RED_NV = 9 + RED_CH;           // values per partial sum (registers)
     const int nvs = bwd_partial_values(C, KB);   // values per partial sum in LDS
     uint16_t* s_pair = reinterpret_cast<uint16_t*>(smem + bwd_table_bytes(hcap, nvs));
@@ -1099,8 +1121,8 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, bool 
     // (the chain's three only in pass 0); its kernel's rank where a run
     // starts, or at the chunk's first pair (-1: same kernel as before)
     struct Pair {
-        float dq, dl, da, w;
-        int rank, pt;
+        float dq = 0.f, dl = 0.f, da = 0.f, w = 0.f;
+        int rank = -1, pt = 0;
     };
     auto load_pair = [&](int j, bool geom) {
         const int e = s_pair[j];
@@ -1141,70 +1163,81 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, bool 
             reinterpret_cast<float4*>(s_g)[tid] = make_float4(g[0], g[1], g[2], g[3]);
             __syncthreads();
         }
-        Pair nxt = j0 < j1 ? load_pair(j0, geom) : Pair{};
-        for (int j = j0; j <= j1; ++j) {
-            const bool end = j == j1;
-            const Pair r = nxt;
-            if (j + 1 < j1) nxt = load_pair(j + 1, geom);
-            if (end || (r.rank >= 0 && r.rank != cur)) {
-                if (cur >= 0) {
-                    if (nseg == 0) {                                   // first run: may continue
-                        s_hk[tid] = cur;
+        // the run `cur` ends: the chunk's first run (it may continue from the
+        // previous chunk) and its last (it may continue into the next) go to
+        // LDS, a run inside the chunk is complete and is flushed
+        auto close_run = [&](bool end) {
+            if (nseg == 0) {
+                s_hk[tid] = cur;
 #pragma unroll
-                        for (int q = 0; q < RED_NV; ++q)
-                            if (q >= v0 && q < nvs) s_head[tid * nvs + q] = acc[q];
-                    } else if (end) {                                  // last run: may continue
-                        s_tk[tid] = cur;
+                for (int q = 0; q < RED_NV; ++q)
+                    if (q >= v0 && q < nvs) s_head[tid * nvs + q] = acc[q];
+            } else if (end) {
+                s_tk[tid] = cur;
 #pragma unroll
-                        for (int q = 0; q < RED_NV; ++q)
-                            if (q >= v0 && q < nvs) s_tail[tid * nvs + q] = acc[q];
-                    } else {                                           // complete run
-                        flush_values(A, cur_n, acc, geom, c0, nc);
-                    }
-                    ++nseg;
-                }
-                if (end) break;
-#pragma unroll
-                for (int q = 0; q < RED_NV; ++q) acc[q] = 0.f;
-                cur = r.rank;
-                if (geom) {
-                    G = load_geo(gp(A.geo) + cur);
-                    cur_n = G.idx;
-                } else {
-                    cur_n = kernel_index(A, cur);
-                }
-            }
-            const int w = r.pt / WAVE, ln = r.pt % WAVE;
-            const int row = ti0 + (w >> 1) * 8 + (ln >> 3), col = tj0 + (w & 1) * 8 + (ln & 7);
-            if (geom) {
-                double out[9];
-                pair_chain(G, (double)row - (double)A.cy, (double)col - (double)A.cx, (double)A.F, r.dq, r.dl, r.da,
-                           out, gD);
-#pragma unroll
-                for (int q = 0; q < 9; ++q) acc[q] += (float)out[q];
-            }
-            if (stage) {
-                const float4 g4 = reinterpret_cast<const float4*>(s_g)[r.pt];
-                acc[9] = fmaf(r.w, g4.x, acc[9]);
-                acc[10] = fmaf(r.w, g4.y, acc[10]);
-                acc[11] = fmaf(r.w, g4.z, acc[11]);
-                acc[12] = fmaf(r.w, g4.w, acc[12]);
+                for (int q = 0; q < RED_NV; ++q)
+                    if (q >= v0 && q < nvs) s_tail[tid * nvs + q] = acc[q];
             } else {
-                const auto Gq = gp(A.grad_image) + ((size_t)row * A.W + col) * C + c0;
-                if (nc == RED_CH && (C & 3) == 0) {
+                flush_values(A, cur_n, acc, geom, c0, nc);
+            }
+            ++nseg;
+        };
+        // the chunk in batches of RED_BATCH pairs: a batch's loads are all in
+        // flight before its first pair is reduced
+        for (int jb = j0; jb < j1; jb += RED_BATCH) {
+            Pair bp[RED_BATCH];
 #pragma unroll
-                    for (int q = 0; q < RED_CH; q += 4) {
-                        const float4 g4 = ld_f4((gptr<const float4>)(Gq + q));
-                        acc[9 + q] = fmaf(r.w, g4.x, acc[9 + q]);
-                        acc[10 + q] = fmaf(r.w, g4.y, acc[10 + q]);
-                        acc[11 + q] = fmaf(r.w, g4.z, acc[11 + q]);
-                        acc[12 + q] = fmaf(r.w, g4.w, acc[12 + q]);
+            for (int b = 0; b < RED_BATCH; ++b) bp[b] = jb + b < j1 ? load_pair(jb + b, geom) : Pair{};
+#pragma unroll
+            for (int b = 0; b < RED_BATCH; ++b) {
+                if (jb + b < j1) {
+                    const Pair& r = bp[b];
+                    if (r.rank >= 0 && r.rank != cur) {
+                        if (cur >= 0) close_run(false);
+#pragma unroll
+                        for (int q = 0; q < RED_NV; ++q) acc[q] = 0.f;
+                        cur = r.rank;
+                        if (geom) {
+                            G = load_geo(gp(A.geo) + cur);
+                            cur_n = G.idx;
+                        } else {
+                            cur_n = kernel_index(A, cur);
+                        }
                     }
-                } else {
-                    for (int q = 0; q < nc; ++q) acc[9 + q] = fmaf(r.w, Gq[q], acc[9 + q]);
+                    const int w = r.pt / WAVE, ln = r.pt % WAVE;
+                    const int row = ti0 + (w >> 1) * 8 + (ln >> 3), col = tj0 + (w & 1) * 8 + (ln & 7);
+                    if (geom) {
+                        double out[9];
+                        pair_chain(G, (double)row - (double)A.cy, (double)col - (double)A.cx, (double)A.F, r.dq, r.dl,
+                                   r.da, out, gD);
+#pragma unroll
+                        for (int q = 0; q < 9; ++q) acc[q] += (float)out[q];
+                    }
+                    if (stage) {
+                        const float4 g4 = reinterpret_cast<const float4*>(s_g)[r.pt];
+                        acc[9] = fmaf(r.w, g4.x, acc[9]);
+                        acc[10] = fmaf(r.w, g4.y, acc[10]);
+                        acc[11] = fmaf(r.w, g4.z, acc[11]);
+                        acc[12] = fmaf(r.w, g4.w, acc[12]);
+                    } else {
+                        const auto Gq = gp(A.grad_image) + ((size_t)row * A.W + col) * C + c0;
+                        if (nc == RED_CH && (C & 3) == 0) {
+#pragma unroll
+                            for (int q = 0; q < RED_CH; q += 4) {
+                                const float4 g4 = ld_f4((gptr<const float4>)(Gq + q));
+                                acc[9 + q] = fmaf(r.w, g4.x, acc[9 + q]);
+                                acc[10 + q] = fmaf(r.w, g4.y, acc[10 + q]);
+                                acc[11 + q] = fmaf(r.w, g4.z, acc[11 + q]);
+                                acc[12 + q] = fmaf(r.w, g4.w, acc[12 + q]);
+                            }
+                        } else {
+                            for (int q = 0; q < nc; ++q) acc[9 + q] = fmaf(r.w, Gq[q], acc[9 + q]);
+                        }
+                    }
                 }
             }
         }
+        if (cur >= 0) close_run(true);
         __syncthreads();
         // the lane where a kernel's run starts adds the continuation and flushes
         for (int which = 0; which < 2; ++which) {
@@ -1402,14 +1435,14 @@ __global__ __launch_bounds__(TILE_THREADS) void k_blend_sample(GroupDev g) {
 template <int KB>
 constexpr int bwd_waves() { return KB <= 20 ? 3 : KB <= 32 ? 2 : 1; }
 
-template <int KB>
-__global__ __launch_bounds__(TILE_THREADS, bwd_waves<KB>()) void k_bwd(GroupDev g, int hcap, int stage_grad) {
+template <int KB, bool NARROW>
+__global__ __launch_bounds__(TILE_THREADS, bwd_waves<KB>()) void k_bwd(GroupDev g, int hcap) {
     extern __shared__ __align__(16) unsigned char smem[];
     int tile;
     const TraceArgs A = item_view(g, tile);
-    bwd_pix_body<KB>(A, tile);
+    bwd_pix_body<KB>(A, tile, reinterpret_cast<float*>(smem));
     __syncthreads();
-    bwd_red_body<KB>(A, hcap, stage_grad != 0, tile, smem);
+    bwd_red_body<KB, NARROW>(A, hcap, tile, smem);
 }
 
 // Diagnostics: the device Phi on an array.
@@ -1445,8 +1478,12 @@ static hipError_t run_kb(int which, const GroupDev& g, hipStream_t s, int max_c 
         hipLaunchKernelGGL(k_blend<KB>, dim3(nt), dim3(TILE_THREADS), 0, s, g);
     } else if (which == 2) {
         const int hcap = table_capacity(0);
-        hipLaunchKernelGGL(k_bwd<KB>, dim3(nt), dim3(TILE_THREADS), bwd_lds_bytes(hcap, KB, max_c), s, g, hcap,
-                           red_stage_grad(KB, max_c) ? 1 : 0);
+        if (max_c <= GRAD_STAGE_CH)
+            hipLaunchKernelGGL((k_bwd<KB, true>), dim3(nt), dim3(TILE_THREADS), bwd_lds_bytes(hcap, KB, max_c), s, g,
+                               hcap);
+        else
+            hipLaunchKernelGGL((k_bwd<KB, false>), dim3(nt), dim3(TILE_THREADS), bwd_lds_bytes(hcap, KB, max_c), s, g,
+                               hcap);
     } else {
         hipLaunchKernelGGL(k_blend_sample<KB>, dim3(nt), dim3(TILE_THREADS), sample_lds_bytes(max_c), s, g);
     }
