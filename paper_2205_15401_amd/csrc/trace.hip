@@ -795,7 +795,7 @@ __host__ __device__ inline int bwd_partial_values(int C, int KB) { return 9 + (C
 
 __host__ __device__ inline size_t bwd_table_bytes(int hcap, int nv) {
     const size_t table = (size_t)hcap * 3 * sizeof(int);
-    const size_t partials = (size_t)TILE_THREADS * (2 * nv * sizeof(float) + 2 * sizeof(int));
+    const size_t partials = (size_t)TILE_THREADS * (2 * nv * sizeof(float) + 4 * sizeof(int));
     return ((table > partials ? table : partials) + 15) & ~(size_t)15;
 }
 
@@ -816,16 +816,19 @@ __device__ __forceinline__ size_t kernel_index(const TraceArgs& A, int rank) {
 // Add one kernel's partial sums to global memory: the 9 geometric values
 // (pass 0 only) and attribute channels c0 .. c0+nc-1, at the kernel's
 // original index n.
+template <int NCH>
 __device__ __forceinline__ void flush_values(const TraceArgs& A, size_t n, const float* v, bool geom, int c0,
                                              int nc) {
-    // v: the 9 geometric values, then nc channels
+    // v: the 9 geometric values, then nc <= NCH channels
     if (geom) {
 #pragma unroll
         for (int q = 0; q < 3; ++q) global_add(&A.gM[n * 3 + q], v[q]);
 #pragma unroll
         for (int q = 0; q < 6; ++q) global_add(&A.gS[n * 6 + q], v[3 + q]);
     }
-    for (int q = 0; q < nc; ++q) global_add(&A.gA[n * A.C + c0 + q], v[9 + q]);
+#pragma unroll
+    for (int q = 0; q < NCH; ++q)
+        if (q < nc) global_add(&A.gA[n * A.C + c0 + q], v[9 + q]);
 }
 
 // Backward, pixel phase: per-pair scalars (dq, dl, da, W) into the scratch list.
@@ -991,8 +994,11 @@ __device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile, float
 // NARROW: every item of the launch has at most GRAD_STAGE_CH channels (one
 // pass of that many channels; the upstream gradient staged in LDS below the
 // deepest K-buffer).
+// The lane's pixel is pixel_of(tile); rk[k]: the rank of its slot k, -1 past
+// its kept count.
 template <int KB, bool NARROW>
-__device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int tile, unsigned char* smem) {
+__device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int tile, unsigned char* smem,
+                                             const int (&rk)[KB]) {
     constexpr bool stage = NARROW && red_stage_grad(KB, GRAD_STAGE_CH);
     __shared__ double s_red[TILE_THREADS / WAVE][3];
     __shared__ int s_wtot[TILE_THREADS / WAVE];
@@ -1024,9 +1030,7 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
     // counting sort of the tile's pairs by kernel; sp[k] = table slot << 16 | position.
     // All first probes are issued back to back; collisions (rare at this load
     // factor) then probe on.
-    int sp[KB], rk[KB];
-#pragma unroll
-    for (int k = 0; k < KB; ++k) rk[k] = k < keff ? gp(A.kl_r)[P.q + (size_t)k * S] : -1;
+    int sp[KB];
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
         sp[k] = -1;
@@ -1115,6 +1119,8 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
     float* s_tail = s_head + TILE_THREADS * nvs;
     int* s_hk = reinterpret_cast<int*>(s_tail + TILE_THREADS * nvs);
     int* s_tk = s_hk + TILE_THREADS;
+    int* s_hn = s_tk + TILE_THREADS;            // the original indices of those kernels
+    int* s_tn = s_hn + TILE_THREADS;
     const int per = (n_pairs + TILE_THREADS - 1) / TILE_THREADS;
     const int j0 = min(n_pairs, tid * per), j1 = min(n_pairs, j0 + per);
     // pair j in kernel order: its scalars gathered from the slot-major lists
@@ -1169,16 +1175,18 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
         auto close_run = [&](bool end) {
             if (nseg == 0) {
                 s_hk[tid] = cur;
+                s_hn[tid] = (int)cur_n;
 #pragma unroll
                 for (int q = 0; q < RED_NV; ++q)
                     if (q >= v0 && q < nvs) s_head[tid * nvs + q] = acc[q];
             } else if (end) {
                 s_tk[tid] = cur;
+                s_tn[tid] = (int)cur_n;
 #pragma unroll
                 for (int q = 0; q < RED_NV; ++q)
                     if (q >= v0 && q < nvs) s_tail[tid * nvs + q] = acc[q];
             } else {
-                flush_values(A, cur_n, acc, geom, c0, nc);
+                flush_values<RED_CH>(A, cur_n, acc, geom, c0, nc);
             }
             ++nseg;
         };
@@ -1258,7 +1266,7 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
                     if (q >= v0 && q < nvs) sum[q] += s_head[t2 * nvs + q];
                 if (s_tk[t2] >= 0) break;                             // the run ends inside chunk t2
             }
-            flush_values(A, kernel_index(A, k), sum, geom, c0, nc);
+            flush_values<RED_CH>(A, (size_t)(which == 0 ? s_hn[tid] : s_tn[tid]), sum, geom, c0, nc);
         }
         __syncthreads();
     }
@@ -1440,9 +1448,28 @@ __global__ __launch_bounds__(TILE_THREADS, bwd_waves<KB>()) void k_bwd(GroupDev 
     extern __shared__ __align__(16) unsigned char smem[];
     int tile;
     const TraceArgs A = item_view(g, tile);
+    {
+        // a tile without kept pairs has nothing to reduce; its sum of dL/dD' is zero
+        const int ntx = (A.W + TILE - 1) / TILE;
+        const PixelCtx P = pixel_of(tile, ntx, A.H, A.W, A.cx, A.cy);
+        const int ke = P.valid ? gp(A.keff)[P.q] : 0;
+        if (!__syncthreads_or(ke > 0)) {
+            if (threadIdx.x < 3) gp(A.tileD)[(size_t)tile * 3 + threadIdx.x] = 0.0;
+            return;
+        }
+    }
     bwd_pix_body<KB>(A, tile, reinterpret_cast<float*>(smem));
+    // the reduction's ranks are loaded while the other waves finish the pixel phase
+    int rk[KB];
+    {
+        const int ntx = (A.W + TILE - 1) / TILE;
+        const PixelCtx P = pixel_of(tile, ntx, A.H, A.W, A.cx, A.cy);
+        const int keff = P.valid ? gp(A.keff)[P.q] : 0;
+#pragma unroll
+        for (int k = 0; k < KB; ++k) rk[k] = k < keff ? gp(A.kl_r)[P.q + (size_t)k * A.S] : -1;
+    }
     __syncthreads();
-    bwd_red_body<KB, NARROW>(A, hcap, tile, smem);
+    bwd_red_body<KB, NARROW>(A, hcap, tile, smem, rk);
 }
 
 // Diagnostics: the device Phi on an array.
