@@ -132,6 +132,13 @@ __device__ __forceinline__ int balanced_slot(const TraceArgs& A, int tile, int n
     return s_perm[tid];
 }
 
+// 1 / a for a > 0: hardware reciprocal estimate and two Newton steps.
+__device__ __forceinline__ double rcp_pos(double a) {
+    double r = __builtin_amdgcn_rcp(a);
+    r = fma(fma(-a, r, 1.0), r, r);
+    return fma(fma(-a, r, 1.0), r, r);
+}
+
 // b / a for a > 0: hardware reciprocal estimate, two Newton steps and a
 // residual correction (within an ulp or two of the rounded quotient).
 __device__ __forceinline__ double div_pos(double b, double a) {
@@ -749,7 +756,7 @@ __device__ __forceinline__ void pair_chain(const GeoRec& G, double D0, double D1
     const double SD0 = s0 * D0 + s1 * D1 + s2 * D2;
     const double SD1 = s1 * D0 + s3 * D1 + s4 * D2;
     const double SD2 = s2 * D0 + s4 * D1 + s5 * D2;
-    const double ia = 1.0 / (D0 * SD0 + D1 * SD1 + D2 * SD2);
+    const double ia = rcp_pos(D0 * SD0 + D1 * SD1 + D2 * SD2);
     const double l = (G.M[0] * SD0 + G.M[1] * SD1 + G.M[2] * SD2) * ia;
     const double V0 = G.M[0] - l * D0, V1 = G.M[1] - l * D1, V2 = G.M[2] - l * D2;
     const double SV0 = s0 * V0 + s1 * V1 + s2 * V2;
@@ -791,7 +798,9 @@ __host__ __device__ constexpr bool red_stage_grad(int KB, int max_c) { return KB
 // each: the 9 geometric ones and one pass's channels); then the tile's pairs
 // in kernel order as 16-bit indices (256 * KB of them); then, when staged,
 // the tile's upstream gradient (GRAD_STAGE_CH floats per pixel slot).
-__host__ __device__ inline int bwd_partial_values(int C, int KB) { return 9 + (C < red_ch(KB) ? C : red_ch(KB)); }
+__host__ __device__ constexpr int bwd_partial_values(int KB, bool narrow) {
+    return 9 + (narrow ? GRAD_STAGE_CH : red_ch(KB));
+}
 
 __host__ __device__ inline size_t bwd_table_bytes(int hcap, int nv) {
     const size_t table = (size_t)hcap * 3 * sizeof(int);
@@ -802,7 +811,8 @@ __host__ __device__ inline size_t bwd_table_bytes(int hcap, int nv) {
 size_t bwd_lds_bytes(int hcap, int KB, int max_c) {
     const size_t grad = red_stage_grad(KB, max_c) ? (size_t)TILE_THREADS * GRAD_STAGE_CH * sizeof(float) : 0;
     const size_t red =
-        bwd_table_bytes(hcap, bwd_partial_values(max_c, KB)) + (size_t)TILE_THREADS * KB * sizeof(uint16_t) + grad;
+        bwd_table_bytes(hcap, bwd_partial_values(KB, max_c <= GRAD_STAGE_CH)) + (size_t)TILE_THREADS * KB * sizeof(uint16_t) +
+        grad;
     const size_t pix = (size_t)TILE_THREADS * KB * sizeof(float);   // the pixel phase's g_k T_k
     return red > pix ? red : pix;
 }
@@ -1020,7 +1030,7 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
     const size_t q0 = (size_t)tile * TILE_THREADS;            // the tile's first list index
     constexpr int RED_CH = NARROW ? GRAD_STAGE_CH : red_ch(KB);   // attribute channels per reduction pass
     constexpr int RED_NV = 9 + RED_CH;           // values per partial sum (registers)
-    const int nvs = bwd_partial_values(C, KB);   // values per partial sum in LDS
+    constexpr int nvs = bwd_partial_values(KB, NARROW);   // values per partial sum in LDS (= RED_NV)
     uint16_t* s_pair = reinterpret_cast<uint16_t*>(smem + bwd_table_bytes(hcap, nvs));
     // the tile's upstream gradient (stage: C <= GRAD_STAGE_CH, one pass),
     // GRAD_STAGE_CH values per pixel slot
@@ -1151,7 +1161,6 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
     for (int c0 = 0; c0 == 0 || c0 < C; c0 += RED_CH) {
         const bool geom = c0 == 0;
         const int nc = max(0, min(RED_CH, C - c0));
-        const int v0 = geom ? 0 : 9;              // first value slot in use
         float acc[RED_NV];
 #pragma unroll
         for (int q = 0; q < RED_NV; ++q) acc[q] = 0.f;
@@ -1178,13 +1187,13 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
                 s_hn[tid] = (int)cur_n;
 #pragma unroll
                 for (int q = 0; q < RED_NV; ++q)
-                    if (q >= v0 && q < nvs) s_head[tid * nvs + q] = acc[q];
+                    s_head[tid * nvs + q] = acc[q];
             } else if (end) {
                 s_tk[tid] = cur;
                 s_tn[tid] = (int)cur_n;
 #pragma unroll
                 for (int q = 0; q < RED_NV; ++q)
-                    if (q >= v0 && q < nvs) s_tail[tid * nvs + q] = acc[q];
+                    s_tail[tid * nvs + q] = acc[q];
             } else {
                 flush_values<RED_CH>(A, cur_n, acc, geom, c0, nc);
             }
@@ -1258,12 +1267,12 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
             const float* own = (which == 0 ? s_head : s_tail) + tid * nvs;
             float sum[RED_NV];
 #pragma unroll
-            for (int q = 0; q < RED_NV; ++q) sum[q] = (q >= v0 && q < nvs) ? own[q] : 0.f;
+            for (int q = 0; q < RED_NV; ++q) sum[q] = own[q];
             for (int t2 = tid + 1; t2 < TILE_THREADS && s_hk[t2] == k; ++t2) {
                 if (which == 0 && s_tk[tid] >= 0) break;              // own head run ended in this chunk
 #pragma unroll
                 for (int q = 0; q < RED_NV; ++q)
-                    if (q >= v0 && q < nvs) sum[q] += s_head[t2 * nvs + q];
+                    sum[q] += s_head[t2 * nvs + q];
                 if (s_tk[t2] >= 0) break;                             // the run ends inside chunk t2
             }
             flush_values<RED_CH>(A, (size_t)(which == 0 ? s_hn[tid] : s_tn[tid]), sum, geom, c0, nc);
