@@ -778,6 +778,54 @@ __device__ __forceinline__ void pair_chain(const GeoRec& G, double D0, double D1
     gD[2] += dq * l * SV2 + dlk * (SV2 - l * SD2) + 2.0 * dat * SD2;
 }
 
+// The same chain summed over a run of pairs of one kernel.  The centre's
+// gradient and dL/dD' are linear in S: per pair they are S (-dq V + dlk D)
+// and S (dq l V + dlk (V - l D) + 2 dat D), so the run sums the vectors
+// in uM and uD and applies S once (run_close).  The inverse covariance's
+// gradient hq V V^T + dlk sym(D V^T) + dat D D^T is P_i V_j + Q_i D_j with
+// P = hq V + dlk D / 2 and Q = dlk V / 2 + dat D, added to outS (xx xy xz
+// yy yz zz).
+__device__ __forceinline__ void pair_chain_run(const GeoRec& G, double D0, double D1, double D2, double dq,
+                                               double dlt, double dat, double uM[3], double uD[3], float outS[6]) {
+    const double s0 = G.S[0], s1 = G.S[1], s2 = G.S[2], s3 = G.S[3], s4 = G.S[4], s5 = G.S[5];
+    const double SD0 = s0 * D0 + s1 * D1 + s2 * D2;
+    const double SD1 = s1 * D0 + s3 * D1 + s4 * D2;
+    const double SD2 = s2 * D0 + s4 * D1 + s5 * D2;
+    const double ia = rcp_pos(D0 * SD0 + D1 * SD1 + D2 * SD2);
+    const double l = (G.M[0] * SD0 + G.M[1] * SD1 + G.M[2] * SD2) * ia;
+    const double V0 = G.M[0] - l * D0, V1 = G.M[1] - l * D1, V2 = G.M[2] - l * D2;
+    const double dlk = dlt * ia;
+    uM[0] += dlk * D0 - dq * V0;
+    uM[1] += dlk * D1 - dq * V1;
+    uM[2] += dlk * D2 - dq * V2;
+    const double c1 = dq * l + dlk, c2 = 2.0 * dat - dlk * l;
+    uD[0] += c1 * V0 + c2 * D0;
+    uD[1] += c1 * V1 + c2 * D1;
+    uD[2] += c1 * V2 + c2 * D2;
+    const double hq = -0.5 * dq, hl = 0.5 * dlk;
+    const double P0 = hq * V0 + hl * D0, P1 = hq * V1 + hl * D1, P2 = hq * V2 + hl * D2;
+    const double Q0 = hl * V0 + dat * D0, Q1 = hl * V1 + dat * D1, Q2 = hl * V2 + dat * D2;
+    outS[0] += (float)(P0 * V0 + Q0 * D0);
+    outS[1] += (float)(P0 * V1 + Q0 * D1);
+    outS[2] += (float)(P0 * V2 + Q0 * D2);
+    outS[3] += (float)(P1 * V1 + Q1 * D1);
+    outS[4] += (float)(P1 * V2 + Q1 * D2);
+    outS[5] += (float)(P2 * V2 + Q2 * D2);
+}
+
+// The end of a run: the centre's gradient S uM into out[0..2], and S uD
+// added to gD.
+__device__ __forceinline__ void run_close(const GeoRec& G, const double uM[3], const double uD[3], float out[3],
+                                          double gD[3]) {
+    const double s0 = G.S[0], s1 = G.S[1], s2 = G.S[2], s3 = G.S[3], s4 = G.S[4], s5 = G.S[5];
+    out[0] = (float)(s0 * uM[0] + s1 * uM[1] + s2 * uM[2]);
+    out[1] = (float)(s1 * uM[0] + s3 * uM[1] + s4 * uM[2]);
+    out[2] = (float)(s2 * uM[0] + s4 * uM[1] + s5 * uM[2]);
+    gD[0] += s0 * uD[0] + s1 * uD[1] + s2 * uD[2];
+    gD[1] += s1 * uD[0] + s3 * uD[1] + s4 * uD[2];
+    gD[2] += s2 * uD[0] + s4 * uD[1] + s5 * uD[2];
+}
+
 // Pairs of a lane's chunk whose loads the tile reduction issues together.
 constexpr int RED_BATCH = 4;
 
@@ -1167,6 +1215,7 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
         int cur = -1, nseg = 0;
         size_t cur_n = 0;
         GeoRec G;
+        double uM[3] = {0.0, 0.0, 0.0}, uD[3] = {0.0, 0.0, 0.0};   // the run's S-factored sums
         s_hk[tid] = -1;
         s_tk[tid] = -1;
         if (stage) {
@@ -1182,6 +1231,7 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
         // previous chunk) and its last (it may continue into the next) go to
         // LDS, a run inside the chunk is complete and is flushed
         auto close_run = [&](bool end) {
+            if (geom) run_close(G, uM, uD, acc, gD);
             if (nseg == 0) {
                 s_hk[tid] = cur;
                 s_hn[tid] = (int)cur_n;
@@ -1213,6 +1263,8 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
                         if (cur >= 0) close_run(false);
 #pragma unroll
                         for (int q = 0; q < RED_NV; ++q) acc[q] = 0.f;
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) uM[q] = uD[q] = 0.0;
                         cur = r.rank;
                         if (geom) {
                             G = load_geo(gp(A.geo) + cur);
@@ -1223,13 +1275,9 @@ __device__ __forceinline__ void bwd_red_body(const TraceArgs& A, int hcap, int t
                     }
                     const int w = r.pt / WAVE, ln = r.pt % WAVE;
                     const int row = ti0 + (w >> 1) * 8 + (ln >> 3), col = tj0 + (w & 1) * 8 + (ln & 7);
-                    if (geom) {
-                        double out[9];
-                        pair_chain(G, (double)row - (double)A.cy, (double)col - (double)A.cx, (double)A.F, r.dq, r.dl,
-                                   r.da, out, gD);
-#pragma unroll
-                        for (int q = 0; q < 9; ++q) acc[q] += (float)out[q];
-                    }
+                    if (geom)
+                        pair_chain_run(G, (double)row - (double)A.cy, (double)col - (double)A.cx, (double)A.F, r.dq,
+                                       r.dl, r.da, uM, uD, acc + 3);
                     if (stage) {
                         const float4 g4 = reinterpret_cast<const float4*>(s_g)[r.pt];
                         acc[9] = fmaf(r.w, g4.x, acc[9]);
