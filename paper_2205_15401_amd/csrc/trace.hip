@@ -567,23 +567,41 @@ __device__ __forceinline__ void blend_body(const TraceArgs& A, int tile, unsigne
 
     double lk[KB];
     float E[KB];
+    // List loads below are made by every lane of the wave, from slots below
+    // the wave's largest kept count (which every lane's list has room for),
+    // and lanes past their own count discard the value: loads under
+    // per-lane branches would make the compiler wait for every load at once,
+    // the one issued ahead included.
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
-        lk[k] = k < keff ? pl[(size_t)k * S] : 0.0;
+        lk[k] = 0.0;
         E[k] = 0.f;
+        if (k < kmax) {
+            const double v = pl[(size_t)k * S];
+            lk[k] = k < keff ? v : 0.0;
+        }
     }
     // E_k = sum_m m_m Phi((l_k - l_m) s_m): m streams from the list, k in registers
     // slot m+1 is loaded while slot m is computed
-    double ln = keff > 0 ? pl[0] : 0.0;
-    float mn = keff > 0 ? pm[0] : 0.f, sn = keff > 0 ? ps[0] : 1.f;
+    double ln = 0.0;
+    float mn = 0.f, sn = 1.f;
+    if (kmax > 0) {
+        const double a = pl[0];
+        const float b = pm[0], c = ps[0];
+        ln = keff > 0 ? a : 0.0;
+        mn = keff > 0 ? b : 0.f;
+        sn = keff > 0 ? c : 1.f;
+    }
     for (int m = 0; m < kmax; ++m) {
         const double lm = ln;
         const float mm = mn, sms = sn * SQRT_LOG2E;
         const bool nin = m + 1 < keff;
-        const size_t o = (size_t)(m + 1) * S;
-        ln = nin ? pl[o] : 0.0;
-        mn = nin ? pm[o] : 0.f;
-        sn = nin ? ps[o] : 1.f;
+        const size_t o = (size_t)(m + 1 < kmax ? m + 1 : m) * S;
+        const double a = pl[o];
+        const float b = pm[o], c = ps[o];
+        ln = nin ? a : 0.0;
+        mn = nin ? b : 0.f;
+        sn = nin ? c : 1.f;
         // four independent pairs per uniform branch, so their chains interleave
 #pragma unroll
         for (int k0 = 0; k0 < KB; k0 += 4) {
@@ -605,13 +623,27 @@ __device__ __forceinline__ void blend_body(const TraceArgs& A, int tile, unsigne
     for (int k = 0; k < KB; ++k) {
         Wt[k] = 0.f;
         ik[k] = 0;
-        if (k < keff) {
-            const size_t o = (size_t)k * S;
-            const float T = expf(-E[k]);
-            gp(A.kl_T)[o + P.q] = T;
-            Wt[k] = T * pm[o];
-            ik[k] = gp(A.kl_i)[o + P.q];
-            ws += Wt[k];
+    }
+#pragma unroll
+    for (int k0 = 0; k0 < KB; k0 += 4) {
+        if (k0 < kmax) {
+            // e^{q_k} and the original indices of four slots, loaded together
+            float mq[4];
+            int iq[4];
+#pragma unroll
+            for (int k = k0; k < k0 + 4; ++k) {
+                const size_t o = (size_t)(k < kmax ? k : kmax - 1) * S;
+                mq[k - k0] = pm[o];
+                iq[k - k0] = gp(A.kl_i)[o + P.q];
+            }
+#pragma unroll
+            for (int k = k0; k < k0 + 4; ++k) {
+                const float T = expf(-E[k]);
+                if (k < keff) gp(A.kl_T)[(size_t)k * S + P.q] = T;
+                Wt[k] = k < keff ? T * mq[k - k0] : 0.f;
+                ik[k] = k < keff ? iq[k - k0] : 0;
+                ws += Wt[k];
+            }
         }
     }
     if (SAMPLE) sample_tile(A, P.valid, P.q, p, keff, smem);
@@ -650,18 +682,18 @@ __device__ __forceinline__ void blend_body(const TraceArgs& A, int tile, unsigne
             const auto img = gp(A.image);
             float a0 = 0.f, a1 = 0.f, a2 = 0.f;
 #pragma unroll
-            for (int k0 = 0; k0 < KB; k0 += 2) {
+            for (int k0 = 0; k0 < KB; k0 += 4) {
                 if (k0 < kmax) {
-                    float r[2][3];
+                    float r[4][3];
 #pragma unroll
-                    for (int k = k0; k < k0 + 2 && k < KB; ++k) {
+                    for (int k = k0; k < k0 + 4; ++k) {
                         const auto row = at + (size_t)ik[k] * 3;
                         r[k - k0][0] = row[0];
                         r[k - k0][1] = row[1];
                         r[k - k0][2] = row[2];
                     }
 #pragma unroll
-                    for (int k = k0; k < k0 + 2 && k < KB; ++k) {
+                    for (int k = k0; k < k0 + 4; ++k) {
                         a0 = fmaf(Wt[k], r[k - k0][0], a0);
                         a1 = fmaf(Wt[k], r[k - k0][1], a1);
                         a2 = fmaf(Wt[k], r[k - k0][2], a2);
