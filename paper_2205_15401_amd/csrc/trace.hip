@@ -1024,12 +1024,22 @@ __device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile, float
     // the pass over m = k
     const int tid = threadIdx.x;
 #pragma unroll
-    for (int k = 0; k < KB; ++k) {
-        if (k < keff) {
-            const float T = pT[(size_t)k * S];
-            const float W = T * pm[(size_t)k * S];
-            dE[k] = keep_T ? -g[k] * W : 0.f;
-            s_dmd[k * TILE_THREADS + tid] = keep_rho ? g[k] * T : 0.f;
+    for (int k0 = 0; k0 < KB; k0 += 4) {
+        if (k0 < kmax) {
+            // T_k and e^{q_k} of four slots, loaded together
+            float Tq[4], Mq[4];
+#pragma unroll
+            for (int k = k0; k < k0 + 4; ++k) {
+                const size_t o = (size_t)(k < kmax ? k : kmax - 1) * S;
+                Tq[k - k0] = pT[o];
+                Mq[k - k0] = pm[o];
+            }
+#pragma unroll
+            for (int k = k0; k < k0 + 4; ++k) {
+                const float T = Tq[k - k0];
+                dE[k] = keep_T && k < keff ? -g[k] * (T * Mq[k - k0]) : 0.f;
+                if (k < keff) s_dmd[k * TILE_THREADS + tid] = keep_rho ? g[k] * T : 0.f;
+            }
         }
     }
     // pair loop: m streams from the list (slot m+1 is loaded while slot m is
