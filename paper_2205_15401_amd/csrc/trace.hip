@@ -986,18 +986,18 @@ __device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile, float
             const auto at = gp(A.attrs);
             const float G0 = keff > 0 ? Gp[0] : 0.f, G1 = keff > 0 ? Gp[1] : 0.f, G2 = keff > 0 ? Gp[2] : 0.f;
 #pragma unroll
-            for (int k0 = 0; k0 < KB; k0 += 2) {
+            for (int k0 = 0; k0 < KB; k0 += 4) {
                 if (k0 < kmax) {
-                    float r[2][3];
+                    float r[4][3];
 #pragma unroll
-                    for (int k = k0; k < k0 + 2 && k < KB; ++k) {
+                    for (int k = k0; k < k0 + 4; ++k) {
                         const auto row = at + (size_t)ik[k] * 3;
                         r[k - k0][0] = row[0];
                         r[k - k0][1] = row[1];
                         r[k - k0][2] = row[2];
                     }
 #pragma unroll
-                    for (int k = k0; k < k0 + 2 && k < KB; ++k)
+                    for (int k = k0; k < k0 + 4; ++k)
                         g[k] = fmaf(G0, r[k - k0][0], fmaf(G1, r[k - k0][1], fmaf(G2, r[k - k0][2], g[k])));
                 }
             }
