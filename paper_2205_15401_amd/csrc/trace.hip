@@ -438,26 +438,35 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile, const 
         }
     }
 
-    // write the kept list: FP64 depth, e^q, sqrt(a), rank, original index
+    // write the kept list: FP64 depth, e^q, sqrt(a), rank, original index.
+    // Slots below the wave's largest fill count: every lane loads a record
+    // (a lane without the slot loads record 0 and discards it), so that a
+    // slot's loads are issued together and waited for once.
     const size_t S = A.S;
-    int keff = 0;
+    const auto rec = gp(A.rec);
 #pragma unroll
     for (int s = 0; s < KB; ++s) {
-        if (s < A.K && key[s] != ~0ull) {
-            const int rank = (int)(key[s] & RANK_MASK);
-            const TraceRec& R = A.rec[rank];
+        if (s < ub) {
+            const bool has = key[s] != ~0ull;
+            const int rank = has ? (int)(key[s] & RANK_MASK) : 0;
+            const auto Rp = rec + rank;
+            TraceRec R;
+            R.A0 = Rp->A0; R.A1 = Rp->A1; R.A2 = Rp->A2; R.A3 = Rp->A3; R.A4 = Rp->A4; R.A5 = Rp->A5;
+            R.B0 = Rp->B0; R.B1 = Rp->B1; R.B2 = Rp->B2; R.c = Rp->c;
+            R.idx = Rp->idx;
             double l, q2, a;
             trace_one(R, P.u, P.v, l, q2, a);
-            const size_t o = (size_t)s * S + P.q;
-            gp(A.kl_l)[o] = l;
-            gp(A.kl_m)[o] = expf(-0.5f * (float)q2);
-            gp(A.kl_s)[o] = (float)sqrt(a);
-            gp(A.kl_r)[o] = rank;
-            gp(A.kl_i)[o] = (int)R.idx;
-            ++keff;
+            if (has) {
+                const size_t o = (size_t)s * S + P.q;
+                gp(A.kl_l)[o] = l;
+                gp(A.kl_m)[o] = expf(-0.5f * (float)q2);
+                gp(A.kl_s)[o] = (float)sqrt(a);
+                gp(A.kl_r)[o] = rank;
+                gp(A.kl_i)[o] = (int)R.idx;
+            }
         }
     }
-    gp(A.keff)[P.q] = keff;
+    gp(A.keff)[P.q] = nkey;
 }
 
 // ----------------------------------------------------------------- sampler
@@ -1498,7 +1507,7 @@ __device__ __forceinline__ TraceArgs item_view(const GroupDev& g, int& tile) {
 // Waves per SIMD the select kernel must fit (a register cap for the
 // compiler): three at a K-buffer of 32 keys, which would otherwise drop to two.
 template <int KB>
-constexpr int select_waves() { return KB == 32 ? 3 : 1; }
+constexpr int select_waves() { return KB == 32 ? 3 : KB == 20 ? 6 : KB == 16 ? 7 : 1; }
 
 // BINS: the launch holds binned items, whose tiles' bins are sorted into the
 // dynamic LDS s_rank (BIN_MAX entries) and scanned in place of every record;
