@@ -212,17 +212,19 @@ def kb_of(K: int) -> int:
 # packed-FP32 figure (157.3) is reported beside it for the whole pipeline.
 PEAK_VALU_TFLOPS = 78.6
 # the arithmetic each kernel's counted FLOPs run in
-KERNEL_DTYPE = {"select": "f64", "blend": "f32", "bwd": "f32 pairs + f64 chain"}
+KERNEL_DTYPE = {"select": "f64", "blend": "f32", "bwd": "f32 pairs + f64 chain", "fwdbwd": "f32 pairs + f64 chain"}
 
 
 def roofline_of(phases, opc, K, workload, step_ms=None):
     """Every trace kernel's algorithmic FLOP rate against the vector peak of
     the arithmetic it issues (78.6 TFLOP/s for FP64 and unpacked FP32), the
     dominant one as the headline, and the whole step's rate."""
-    flops = {"select": opc["flop_select"], "blend": opc["flop_blend"],
-             "bwd": opc["flop_bwd_pixel"] + opc["flop_bwd_chain"]}
+    bwd = opc["flop_bwd_pixel"] + opc["flop_bwd_chain"]
+    flops = {"select": opc["flop_select"], "blend": opc["flop_blend"], "bwd": bwd,
+             "fwdbwd": opc["flop_blend"] + bwd}
     kb = kb_of(K)
-    kname = {"select": f"k_select<{kb}>", "blend": f"k_blend<{kb}>", "bwd": f"k_bwd<{kb}>"}
+    kname = {"select": f"k_select<{kb}>", "blend": f"k_blend<{kb}>", "bwd": f"k_bwd<{kb}>",
+             "fwdbwd": f"k_fwdbwd<{kb}>"}
     avg = {k: phases[k][0] / phases[k][1] for k in flops if k in phases and phases[k][1] > 0}
     per_kernel = {}
     for k, ms in avg.items():

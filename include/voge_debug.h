@@ -14,7 +14,7 @@ extern "C" {
 
 /* Accumulated device time of one phase of the library's calls. */
 typedef struct voge_phase_time {
-    char name[32];            /* "prep", "select", "blend", "zero", "bwd", "epilogue" */
+    char name[32];            /* "prep", "select", "blend", "zero", "bwd", "fwdbwd", "epilogue" */
     double total_ms;          /* sum of the phase's durations (HIP events)             */
     int64_t count;            /* number of timed calls                                 */
 } voge_phase_time_t;
@@ -22,9 +22,10 @@ typedef struct voge_phase_time {
 /* Turn per-phase timing on or off for calls made through `ctx`.  When on,
  * every call records a HIP event before and after each phase on the caller's
  * stream: "select" is the single kernel k_select, "blend" k_blend, "bwd"
- * k_bwd; "prep" groups the per-kernel preparation and the depth sort,
- * "epilogue" the world-space epilogue.  Host memory only.  Returns 0 or
- * VOGE_EINVAL. */
+ * k_bwd, "fwdbwd" k_fwdbwd (the blend and the backward in one kernel, for
+ * calls that ask for both); "prep" groups the per-kernel preparation and the
+ * depth sort, "epilogue" the world-space epilogue.  Host memory only.
+ * Returns 0 or VOGE_EINVAL. */
 int voge_profile_enable(voge_ctx_t* ctx, int enable);
 
 /* Wait for the recorded events, add their durations to per-phase totals and

@@ -562,6 +562,22 @@ int launch_compute(voge_ctx_t* ctx, const voge::BatchPlan& p, const BatchWs& w, 
             if (int rc = hip_check(voge::launch_sample_epilogue(b, p.total_epi, s), "sample epilogue launch"))
                 return rc;
         }
+    } else if (fwd_part && (flags & VOGE_FORWARD) && (flags & VOGE_BACKWARD)) {
+        // forward and backward in one call: the blend and the backward run
+        // in one kernel per K-buffer group
+        {
+            ProfScope ps = scope("zero");
+            const size_t nk = p.total_kern > 0 ? (size_t)p.total_kern : 1;
+            voge::launch_fill_u32(w.grads, 9 * nk + p.total_attr, 0u, s);
+        }
+        {
+            ProfScope ps = scope("fwdbwd");
+            for (const auto& g : p.groups)
+                if (int rc = hip_check(voge::launch_fwdbwd(group_dev(p, g, w, cfg), g.kb, g.max_c, s), "fwd+bwd launch"))
+                    return rc;
+        }
+        ProfScope ps = scope("epilogue");
+        return hip_check(voge::launch_epilogue(b, p.total_epi, s), "epilogue launch");
     } else if (fwd_part) {
         ProfScope ps = scope("blend");
         for (const auto& g : p.groups)

@@ -930,6 +930,70 @@ __device__ __forceinline__ void flush_values(const TraceArgs& A, size_t n, const
         if (q < nc) global_add(&A.gA[n * A.C + c0 + q], v[9 + q]);
 }
 
+// Backward, pixel phase, pair loop of one lane's pixel (list index q, kept
+// count keff, the wave's largest kept count kmax; l_k in lk, dE_k in dE, its
+// g_k T_k at s_dmd[k * 256 + lane]).  m streams from the list (slot m+1 is
+// loaded while slot m is computed); after the sums over k, slot m's scalars
+// are complete except the k-side part of dL/dl, which goes to its own list at
+// the end:
+//   dq = (g_m T_m + sum_k dE_k Phi_km) m_m,  dl = -s_m sum_k dx_km (+ dl[m] later),
+//   da = sum_k dx_km d_km / (2 s_m),  W = T_m m_m,
+// with dx_km = dE_k m_m Phi'(x_km), x_km = d_km s_m, d_km = l_k - l_m.
+template <int KB>
+__device__ __forceinline__ void bwd_pair_loop(const TraceArgs& A, size_t q, int keff, int kmax, const float* s_dmd,
+                                              const double (&lk)[KB], const float (&dE)[KB]) {
+    const size_t S = A.S;
+    const int tid = threadIdx.x;
+    const auto pl = gp(A.kl_l) + q;
+    const auto pm = gp(A.kl_m) + q;
+    const auto ps = gp(A.kl_s) + q;
+    const auto pT = gp(A.kl_T) + q;
+    const auto pbw = gp(A.bw) + q;
+    float dl[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) dl[k] = 0.f;
+    double ln = keff > 0 ? pl[0] : 0.0;
+    float mn = keff > 0 ? pm[0] : 0.f, sn = keff > 0 ? ps[0] : 1.f, tn = keff > 0 ? pT[0] : 0.f;
+    for (int m = 0; m < kmax; ++m) {
+        const bool in = m < keff;
+        const size_t o = (size_t)m * S;
+        const double lm = ln;
+        const float mm = mn, sm = sn, tm = tn;
+        const bool nin = m + 1 < keff;
+        ln = nin ? pl[o + S] : 0.0;
+        mn = nin ? pm[o + S] : 0.f;
+        sn = nin ? ps[o + S] : 1.f;
+        tn = nin ? pT[o + S] : 0.f;
+        const float sms = sm * SQRT_LOG2E, mmc = mm * INV_SQRT_PI;
+        float acc_dm = 0.f, acc_dx = 0.f, acc_dd = 0.f;
+#pragma unroll
+        for (int k0 = 0; k0 < KB; k0 += 4) {
+            if (k0 < kmax) {
+#pragma unroll
+                for (int k = k0; k < k0 + 4 && k < KB; ++k) {
+                    const float d = (float)(lk[k] - lm);
+                    const float xs = d * sms;
+                    const float ex = gauss_scaled(xs);
+                    acc_dm = fmaf(dE[k], phi_from(xs, ex), acc_dm);
+                    const float dx = dE[k] * mmc * ex;
+                    dl[k] = fmaf(dx, sm, dl[k]);
+                    acc_dx += dx;
+                    acc_dd = fmaf(dx, d, acc_dd);
+                }
+            }
+        }
+        if (in) {
+            const float dmd_m = s_dmd[m * TILE_THREADS + tid];
+            st_f4(pbw + o, make_float4((dmd_m + acc_dm) * mm, -sm * acc_dx, acc_dd * (0.5f / sm), tm * mm));
+        }
+    }
+    // the k-side part of dL/dl of each slot
+    const auto pbl = gp(A.bwl) + q;
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+        if (k < keff) pbl[(size_t)k * S] = dl[k];
+}
+
 // Backward, pixel phase: per-pair scalars (dq, dl, da, W) into the scratch list.
 template <int KB>
 __device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile, float* s_dmd) {
@@ -943,20 +1007,17 @@ __device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile, float
     const size_t p = (size_t)P.pi * A.W + P.pj;
     const auto pl = gp(A.kl_l) + P.q;
     const auto pm = gp(A.kl_m) + P.q;
-    const auto ps = gp(A.kl_s) + P.q;
     const auto pT = gp(A.kl_T) + P.q;
     const auto pi = gp(A.kl_i) + P.q;
-    const auto pbw = gp(A.bw) + P.q;
     const auto Gp = gp(A.grad_image) + p * C;
 
     double lk[KB];
-    float dE[KB], dl[KB];
+    float dE[KB];
     int ik[KB];
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
         lk[k] = 0.0;
         dE[k] = 0.f;
-        dl[k] = 0.f;
         ik[k] = 0;
         if (k < keff) {
             lk[k] = pl[(size_t)k * S];
@@ -1051,52 +1112,193 @@ __device__ __forceinline__ void bwd_pix_body(const TraceArgs& A, int tile, float
             }
         }
     }
-    // pair loop: m streams from the list (slot m+1 is loaded while slot m is
-    // computed); after the sums over k, slot m's scalars are complete except
-    // the k-side part of dL/dl, which goes to its own list at the end:
-    //   dq = (g_m T_m + sum_k dE_k Phi_km) m_m,  dl = -s_m sum_k dx_km (+ dl[m] later),
-    //   da = sum_k dx_km d_km / (2 s_m),  W = T_m m_m,
-    // with dx_km = dE_k m_m Phi'(x_km), x_km = d_km s_m, d_km = l_k - l_m
-    double ln = keff > 0 ? pl[0] : 0.0;
-    float mn = keff > 0 ? pm[0] : 0.f, sn = keff > 0 ? ps[0] : 1.f, tn = keff > 0 ? pT[0] : 0.f;
+    bwd_pair_loop<KB>(A, P.q, keff, kmax, s_dmd, lk, dE);
+}
+
+// Forward and the backward's pixel phase of a tile in one pass over its
+// pixels, for a call that asks for both with the upstream gradient given:
+// the blend (transmittance sums, weights, colour sum), then, with the kept
+// depths, transmittances and weights still in registers and the attribute
+// rows of the colour sum also giving g_k = G . c_k, the backward's dE_k and
+// pair loop.  Its outputs are those of the blend and of the pixel phase.
+template <int KB>
+__device__ __forceinline__ void fwdbwd_pix_body(const TraceArgs& A, int tile, float* s_dmd) {
+    const int ntx = (A.W + TILE - 1) / TILE;
+    const PixelCtx P = pixel_at(tile, balanced_slot(A, tile, ntx), ntx, A.H, A.W, A.cx, A.cy);
+    const size_t S = A.S;
+    const int C = A.C;
+    const int keff = P.valid ? gp(A.keff)[P.q] : 0;
+    const int kmax = wave_max_keff(keff);
+    const size_t p = (size_t)P.pi * A.W + P.pj;
+    const auto pl = gp(A.kl_l) + P.q;
+    const auto pm = gp(A.kl_m) + P.q;
+    const auto ps = gp(A.kl_s) + P.q;
+
+    // the blend's sums E_k (as in blend_body)
+    double lk[KB];
+    float E[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        lk[k] = 0.0;
+        E[k] = 0.f;
+        if (k < kmax) {
+            const double v = pl[(size_t)k * S];
+            lk[k] = k < keff ? v : 0.0;
+        }
+    }
+    double ln = 0.0;
+    float mn = 0.f, sn = 1.f;
+    if (kmax > 0) {
+        const double a = pl[0];
+        const float b = pm[0], c = ps[0];
+        ln = keff > 0 ? a : 0.0;
+        mn = keff > 0 ? b : 0.f;
+        sn = keff > 0 ? c : 1.f;
+    }
     for (int m = 0; m < kmax; ++m) {
-        const bool in = m < keff;
-        const size_t o = (size_t)m * S;
         const double lm = ln;
-        const float mm = mn, sm = sn, tm = tn;
+        const float mm = mn, sms = sn * SQRT_LOG2E;
         const bool nin = m + 1 < keff;
-        ln = nin ? pl[o + S] : 0.0;
-        mn = nin ? pm[o + S] : 0.f;
-        sn = nin ? ps[o + S] : 1.f;
-        tn = nin ? pT[o + S] : 0.f;
-        const float sms = sm * SQRT_LOG2E, mmc = mm * INV_SQRT_PI;
-        float acc_dm = 0.f, acc_dx = 0.f, acc_dd = 0.f;
+        const size_t o = (size_t)(m + 1 < kmax ? m + 1 : m) * S;
+        const double a = pl[o];
+        const float b = pm[o], c = ps[o];
+        ln = nin ? a : 0.0;
+        mn = nin ? b : 0.f;
+        sn = nin ? c : 1.f;
 #pragma unroll
         for (int k0 = 0; k0 < KB; k0 += 4) {
             if (k0 < kmax) {
 #pragma unroll
                 for (int k = k0; k < k0 + 4 && k < KB; ++k) {
-                    const float d = (float)(lk[k] - lm);
-                    const float xs = d * sms;
-                    const float ex = gauss_scaled(xs);
-                    acc_dm = fmaf(dE[k], phi_from(xs, ex), acc_dm);
-                    const float dx = dE[k] * mmc * ex;
-                    dl[k] = fmaf(dx, sm, dl[k]);
-                    acc_dx += dx;
-                    acc_dd = fmaf(dx, d, acc_dd);
+                    const float xs = (float)(lk[k] - lm) * sms;
+                    E[k] = fmaf(mm, phi_from(xs, gauss_scaled(xs)), E[k]);
                 }
             }
         }
-        if (in) {
-            const float dmd_m = s_dmd[m * TILE_THREADS + tid];
-            st_f4(pbw + o, make_float4((dmd_m + acc_dm) * mm, -sm * acc_dx, acc_dd * (0.5f / sm), tm * mm));
+    }
+    // T_k waits in LDS (where g_k T_k goes later), W_k = T_k e^{q_k} in dE
+    // until dE_k = -g_k W_k replaces it, and the original indices
+    const int tid = threadIdx.x;
+    float dE[KB];
+    int ik[KB];
+    float ws = 0.f;
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        dE[k] = 0.f;
+        ik[k] = 0;
+    }
+#pragma unroll
+    for (int k0 = 0; k0 < KB; k0 += 4) {
+        if (k0 < kmax) {
+            float mq[4];
+            int iq[4];
+#pragma unroll
+            for (int k = k0; k < k0 + 4; ++k) {
+                const size_t o = (size_t)(k < kmax ? k : kmax - 1) * S;
+                mq[k - k0] = pm[o];
+                iq[k - k0] = gp(A.kl_i)[o + P.q];
+            }
+#pragma unroll
+            for (int k = k0; k < k0 + 4; ++k) {
+                const float T = expf(-E[k]);
+                if (k < keff) {
+                    gp(A.kl_T)[(size_t)k * S + P.q] = T;
+                    s_dmd[k * TILE_THREADS + tid] = T;
+                }
+                dE[k] = k < keff ? T * mq[k - k0] : 0.f;
+                ik[k] = k < keff ? iq[k - k0] : 0;
+                ws += dE[k];
+            }
         }
     }
-    // the k-side part of dL/dl of each slot
-    const auto pbl = gp(A.bwl) + P.q;
+    // dE_k = -g_k W_k and g_k T_k (as in bwd_pix_body, with the ablations)
+    const bool keep_T = !(A.grad_mode & 1), keep_rho = !(A.grad_mode & 2);
+    auto finish = [&](int k, float gk) {
+        dE[k] = keep_T && k < keff ? -gk * dE[k] : 0.f;
+        if (k < keff) s_dmd[k * TILE_THREADS + tid] = keep_rho ? gk * s_dmd[k * TILE_THREADS + tid] : 0.f;
+    };
+    // the colour sum (weights W_k in dE; slots past keff gather row 0 with
+    // weight 0), and g_k = G . c_k; the upstream gradient is read only at
+    // pixels with kept kernels, which lie in the image
+    const bool img = A.image != nullptr && P.valid;
+    if (kmax > 0 && C == 3) {
+        // three channels: the rows of the colour sum give g_k too
+        const auto at = gp(A.attrs);
+        const auto Gp = gp(A.grad_image) + p * 3;
+        const float G0 = keff > 0 ? Gp[0] : 0.f, G1 = keff > 0 ? Gp[1] : 0.f, G2 = keff > 0 ? Gp[2] : 0.f;
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f;
 #pragma unroll
-    for (int k = 0; k < KB; ++k)
-        if (k < keff) pbl[(size_t)k * S] = dl[k];
+        for (int k0 = 0; k0 < KB; k0 += 4) {
+            if (k0 < kmax) {
+                float r[4][3];
+#pragma unroll
+                for (int k = k0; k < k0 + 4; ++k) {
+                    const auto row = at + (size_t)ik[k] * 3;
+                    r[k - k0][0] = row[0];
+                    r[k - k0][1] = row[1];
+                    r[k - k0][2] = row[2];
+                }
+#pragma unroll
+                for (int k = k0; k < k0 + 4; ++k) {
+                    a0 = fmaf(dE[k], r[k - k0][0], a0);
+                    a1 = fmaf(dE[k], r[k - k0][1], a1);
+                    a2 = fmaf(dE[k], r[k - k0][2], a2);
+                    finish(k, fmaf(G0, r[k - k0][0], fmaf(G1, r[k - k0][1], G2 * r[k - k0][2])));
+                }
+            }
+        }
+        if (img) {
+            const auto out = gp(A.image) + p * 3;
+            out[0] = a0;
+            out[1] = a1;
+            out[2] = a2;
+        }
+    } else if (kmax > 0) {
+        // other channel counts: the colour sum channel by channel, then g_k
+        float g[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) g[k] = 0.f;
+        const auto at = gp(A.attrs);
+        const auto Gp = gp(A.grad_image) + p * C;
+        for (int c = 0; c < C; ++c) {
+            const float Gc = keff > 0 ? Gp[c] : 0.f;
+            float acc = 0.f;
+#pragma unroll
+            for (int k0 = 0; k0 < KB; k0 += 4) {
+                if (k0 < kmax) {
+                    float v[4];
+#pragma unroll
+                    for (int k = k0; k < k0 + 4; ++k) v[k - k0] = at[(size_t)ik[k] * C + c];
+#pragma unroll
+                    for (int k = k0; k < k0 + 4; ++k) {
+                        acc = fmaf(dE[k], v[k - k0], acc);
+                        g[k] = fmaf(Gc, v[k - k0], g[k]);
+                    }
+                }
+            }
+            if (img) gp(A.image)[p * C + c] = acc;
+        }
+#pragma unroll
+        for (int k = 0; k < KB; ++k) finish(k, g[k]);
+    } else if (img) {
+        for (int c = 0; c < C; ++c) gp(A.image)[p * C + c] = 0.f;
+    }
+    if (A.wsum && P.valid) gp(A.wsum)[p] = ws;
+    if (A.kept && P.valid) {
+        // the kept indices in ascending depth, as in blend_body
+        const auto kp = gp(A.kept) + p * A.K;
+        for (int s = keff; s < A.K; ++s) kp[s] = -1;
+        for (int k = 0; k < keff; ++k) {
+            const double l = pl[(size_t)k * S];
+            int pos = 0;
+            for (int m = 0; m < keff; ++m) {
+                const double lm = pl[(size_t)m * S];
+                pos += (lm < l || (lm == l && m < k)) ? 1 : 0;
+            }
+            kp[pos] = gp(A.kl_i)[(size_t)k * S + P.q];
+        }
+    }
+    bwd_pair_loop<KB>(A, P.q, keff, kmax, s_dmd, lk, dE);
 }
 
 // Backward, tile phase: group the tile's pairs by kernel and reduce them.
@@ -1551,6 +1753,25 @@ __global__ __launch_bounds__(TILE_THREADS) void k_blend_sample(GroupDev g) {
 template <int KB>
 constexpr int bwd_waves() { return KB <= 20 ? 3 : KB <= 32 ? 2 : 1; }
 
+// After the pixel phase: the ranks of the reduction's pairs are loaded while
+// the other waves finish the pixel phase; at the workgroup barrier a tile
+// without kept pairs stops (its sum of dL/dD' is zero), any other goes on to
+// the tile reduction.
+template <int KB, bool NARROW>
+__device__ __forceinline__ void bwd_after_pix(const TraceArgs& A, int tile, int hcap, unsigned char* smem) {
+    const int ntx = (A.W + TILE - 1) / TILE;
+    const PixelCtx P = pixel_of(tile, ntx, A.H, A.W, A.cx, A.cy);
+    const int keff = P.valid ? gp(A.keff)[P.q] : 0;
+    int rk[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) rk[k] = k < keff ? gp(A.kl_r)[P.q + (size_t)k * A.S] : -1;
+    if (!__syncthreads_or(keff > 0)) {
+        if (threadIdx.x < 3) gp(A.tileD)[(size_t)tile * 3 + threadIdx.x] = 0.0;
+        return;
+    }
+    bwd_red_body<KB, NARROW>(A, hcap, tile, smem, rk);
+}
+
 template <int KB, bool NARROW>
 __global__ __launch_bounds__(TILE_THREADS, bwd_waves<KB>()) void k_bwd(GroupDev g, int hcap) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1567,17 +1788,18 @@ __global__ __launch_bounds__(TILE_THREADS, bwd_waves<KB>()) void k_bwd(GroupDev 
         }
     }
     bwd_pix_body<KB>(A, tile, reinterpret_cast<float*>(smem));
-    // the reduction's ranks are loaded while the other waves finish the pixel phase
-    int rk[KB];
-    {
-        const int ntx = (A.W + TILE - 1) / TILE;
-        const PixelCtx P = pixel_of(tile, ntx, A.H, A.W, A.cx, A.cy);
-        const int keff = P.valid ? gp(A.keff)[P.q] : 0;
-#pragma unroll
-        for (int k = 0; k < KB; ++k) rk[k] = k < keff ? gp(A.kl_r)[P.q + (size_t)k * A.S] : -1;
-    }
-    __syncthreads();
-    bwd_red_body<KB, NARROW>(A, hcap, tile, smem, rk);
+    bwd_after_pix<KB, NARROW>(A, tile, hcap, smem);
+}
+
+// Forward and backward of a tile in one workgroup (a call that asks for
+// both, with the upstream gradient given).
+template <int KB, bool NARROW>
+__global__ __launch_bounds__(TILE_THREADS, bwd_waves<KB>()) void k_fwdbwd(GroupDev g, int hcap) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    int tile;
+    const TraceArgs A = item_view(g, tile);
+    fwdbwd_pix_body<KB>(A, tile, reinterpret_cast<float*>(smem));
+    bwd_after_pix<KB, NARROW>(A, tile, hcap, smem);
 }
 
 // Diagnostics: the device Phi on an array.
@@ -1619,6 +1841,14 @@ static hipError_t run_kb(int which, const GroupDev& g, hipStream_t s, int max_c 
         else
             hipLaunchKernelGGL((k_bwd<KB, false>), dim3(nt), dim3(TILE_THREADS), bwd_lds_bytes(hcap, KB, max_c), s, g,
                                hcap);
+    } else if (which == 5) {
+        const int hcap = table_capacity(0);
+        if (max_c <= GRAD_STAGE_CH)
+            hipLaunchKernelGGL((k_fwdbwd<KB, true>), dim3(nt), dim3(TILE_THREADS), bwd_lds_bytes(hcap, KB, max_c), s, g,
+                               hcap);
+        else
+            hipLaunchKernelGGL((k_fwdbwd<KB, false>), dim3(nt), dim3(TILE_THREADS), bwd_lds_bytes(hcap, KB, max_c), s,
+                               g, hcap);
     } else {
         hipLaunchKernelGGL(k_blend_sample<KB>, dim3(nt), dim3(TILE_THREADS), sample_lds_bytes(max_c), s, g);
     }
@@ -1638,6 +1868,7 @@ static hipError_t dispatch(int which, const GroupDev& g, int kb, hipStream_t s, 
 hipError_t launch_select(const GroupDev& g, int kb, hipStream_t s) { return dispatch(0, g, kb, s); }
 hipError_t launch_blend(const GroupDev& g, int kb, hipStream_t s) { return dispatch(1, g, kb, s); }
 hipError_t launch_bwd(const GroupDev& g, int kb, int max_c, hipStream_t s) { return dispatch(2, g, kb, s, max_c); }
+hipError_t launch_fwdbwd(const GroupDev& g, int kb, int max_c, hipStream_t s) { return dispatch(5, g, kb, s, max_c); }
 hipError_t launch_blend_sample(const GroupDev& g, int kb, int max_c, hipStream_t s) {
     return dispatch(4, g, kb, s, max_c);
 }

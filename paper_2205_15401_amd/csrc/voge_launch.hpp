@@ -214,6 +214,7 @@ inline size_t tile_capacity(size_t total_kern, size_t total_tiles) { return 8 * 
 hipError_t launch_select(const GroupDev& g, int kb, hipStream_t s);
 hipError_t launch_blend(const GroupDev& g, int kb, hipStream_t s);
 hipError_t launch_bwd(const GroupDev& g, int kb, int max_c, hipStream_t s);   // pixel phase + tile reduction
+hipError_t launch_fwdbwd(const GroupDev& g, int kb, int max_c, hipStream_t s);   // blend, then the backward
 // blend plus the sampler; max_c: the largest channel count of the group's items
 hipError_t launch_blend_sample(const GroupDev& g, int kb, int max_c, hipStream_t s);
 hipError_t launch_phi(const float* x, float* y, int n, hipStream_t s);
