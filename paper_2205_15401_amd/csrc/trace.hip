@@ -562,25 +562,22 @@ __device__ __forceinline__ void sample_tile(const TraceArgs& A, bool valid, size
 }
 
 // ------------------------------------------------------------------- blend
-// SAMPLE: also run the sampler on the tile (smem: sample_lds_bytes).
-template <int KB, bool SAMPLE>
-__device__ __forceinline__ void blend_body(const TraceArgs& A, int tile, unsigned char* smem) {
-    const int ntx = (A.W + TILE - 1) / TILE;
-    const PixelCtx P = pixel_at(tile, balanced_slot(A, tile, ntx), ntx, A.H, A.W, A.cx, A.cy);
+// The blend's sums E_k = sum_m e^{q_m} Phi((l_k - l_m) sqrt(a_m)) of the
+// pixel at list index q (keff kept kernels; kmax the wave's largest count):
+// its kept depths into lk (0 past keff), the sums into E.  m streams from the
+// list (slot m+1 is loaded while slot m is computed), k sits in registers.
+// List loads are made by every lane of the wave, from slots below the
+// wave's largest kept count (which every lane's list has room for), and
+// lanes past their own count discard the value: loads under per-lane
+// branches would make the compiler wait for every load at once, the one
+// issued ahead included.
+template <int KB>
+__device__ __forceinline__ void blend_sums(const TraceArgs& A, size_t q, int keff, int kmax, double (&lk)[KB],
+                                           float (&E)[KB]) {
     const size_t S = A.S;
-    const int keff = P.valid ? gp(A.keff)[P.q] : 0;
-    const int kmax = wave_max_keff(keff);
-    const auto pl = gp(A.kl_l) + P.q;
-    const auto pm = gp(A.kl_m) + P.q;
-    const auto ps = gp(A.kl_s) + P.q;
-
-    double lk[KB];
-    float E[KB];
-    // List loads below are made by every lane of the wave, from slots below
-    // the wave's largest kept count (which every lane's list has room for),
-    // and lanes past their own count discard the value: loads under
-    // per-lane branches would make the compiler wait for every load at once,
-    // the one issued ahead included.
+    const auto pl = gp(A.kl_l) + q;
+    const auto pm = gp(A.kl_m) + q;
+    const auto ps = gp(A.kl_s) + q;
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
         lk[k] = 0.0;
@@ -590,8 +587,6 @@ __device__ __forceinline__ void blend_body(const TraceArgs& A, int tile, unsigne
             lk[k] = k < keff ? v : 0.0;
         }
     }
-    // E_k = sum_m m_m Phi((l_k - l_m) s_m): m streams from the list, k in registers
-    // slot m+1 is loaded while slot m is computed
     double ln = 0.0;
     float mn = 0.f, sn = 1.f;
     if (kmax > 0) {
@@ -623,6 +618,40 @@ __device__ __forceinline__ void blend_body(const TraceArgs& A, int tile, unsigne
             }
         }
     }
+}
+
+// The kept original indices of the pixel at list index q, written to the
+// image's kept array in ascending depth (the list itself is unordered):
+// slot k goes to the number of kept kernels nearer than it (equal depths in
+// slot order).
+__device__ __forceinline__ void write_kept(const TraceArgs& A, size_t q, size_t p, int keff) {
+    const size_t S = A.S;
+    const auto pl = gp(A.kl_l) + q;
+    const auto kp = gp(A.kept) + p * A.K;
+    for (int s = keff; s < A.K; ++s) kp[s] = -1;
+    for (int k = 0; k < keff; ++k) {
+        const double l = pl[(size_t)k * S];
+        int pos = 0;
+        for (int m = 0; m < keff; ++m) {
+            const double lm = pl[(size_t)m * S];
+            pos += (lm < l || (lm == l && m < k)) ? 1 : 0;
+        }
+        kp[pos] = gp(A.kl_i)[(size_t)k * S + q];
+    }
+}
+
+// SAMPLE: also run the sampler on the tile (smem: sample_lds_bytes).
+template <int KB, bool SAMPLE>
+__device__ __forceinline__ void blend_body(const TraceArgs& A, int tile, unsigned char* smem) {
+    const int ntx = (A.W + TILE - 1) / TILE;
+    const PixelCtx P = pixel_at(tile, balanced_slot(A, tile, ntx), ntx, A.H, A.W, A.cx, A.cy);
+    const size_t S = A.S;
+    const int keff = P.valid ? gp(A.keff)[P.q] : 0;
+    const int kmax = wave_max_keff(keff);
+    const auto pm = gp(A.kl_m) + P.q;
+    double lk[KB];
+    float E[KB];
+    blend_sums<KB>(A, P.q, keff, kmax, lk, E);
     if (!SAMPLE && !P.valid) return;
     const size_t p = (size_t)P.pi * A.W + P.pj;
     float Wt[KB];
@@ -734,22 +763,7 @@ __device__ __forceinline__ void blend_body(const TraceArgs& A, int tile, unsigne
         for (int c = 0; c < A.C; ++c) gp(A.image)[p * A.C + c] = 0.f;
     }
     if (A.wsum) gp(A.wsum)[p] = ws;
-    if (A.kept) {
-        // the kept indices in ascending depth (the list itself is unordered):
-        // slot k goes to the number of kept kernels nearer than it (equal
-        // depths in slot order)
-        const auto kp = gp(A.kept) + p * A.K;
-        for (int s = keff; s < A.K; ++s) kp[s] = -1;
-        for (int k = 0; k < keff; ++k) {
-            const double l = pl[(size_t)k * S];
-            int pos = 0;
-            for (int m = 0; m < keff; ++m) {
-                const double lm = pl[(size_t)m * S];
-                pos += (lm < l || (lm == l && m < k)) ? 1 : 0;
-            }
-            kp[pos] = gp(A.kl_i)[(size_t)k * S + P.q];
-        }
-    }
+    if (A.kept) write_kept(A, P.q, p, keff);
 }
 
 // --------------------------------------------------------------- backward
@@ -1130,52 +1144,10 @@ __device__ __forceinline__ void fwdbwd_pix_body(const TraceArgs& A, int tile, fl
     const int keff = P.valid ? gp(A.keff)[P.q] : 0;
     const int kmax = wave_max_keff(keff);
     const size_t p = (size_t)P.pi * A.W + P.pj;
-    const auto pl = gp(A.kl_l) + P.q;
     const auto pm = gp(A.kl_m) + P.q;
-    const auto ps = gp(A.kl_s) + P.q;
-
-    // the blend's sums E_k (as in blend_body)
     double lk[KB];
     float E[KB];
-#pragma unroll
-    for (int k = 0; k < KB; ++k) {
-        lk[k] = 0.0;
-        E[k] = 0.f;
-        if (k < kmax) {
-            const double v = pl[(size_t)k * S];
-            lk[k] = k < keff ? v : 0.0;
-        }
-    }
-    double ln = 0.0;
-    float mn = 0.f, sn = 1.f;
-    if (kmax > 0) {
-        const double a = pl[0];
-        const float b = pm[0], c = ps[0];
-        ln = keff > 0 ? a : 0.0;
-        mn = keff > 0 ? b : 0.f;
-        sn = keff > 0 ? c : 1.f;
-    }
-    for (int m = 0; m < kmax; ++m) {
-        const double lm = ln;
-        const float mm = mn, sms = sn * SQRT_LOG2E;
-        const bool nin = m + 1 < keff;
-        const size_t o = (size_t)(m + 1 < kmax ? m + 1 : m) * S;
-        const double a = pl[o];
-        const float b = pm[o], c = ps[o];
-        ln = nin ? a : 0.0;
-        mn = nin ? b : 0.f;
-        sn = nin ? c : 1.f;
-#pragma unroll
-        for (int k0 = 0; k0 < KB; k0 += 4) {
-            if (k0 < kmax) {
-#pragma unroll
-                for (int k = k0; k < k0 + 4 && k < KB; ++k) {
-                    const float xs = (float)(lk[k] - lm) * sms;
-                    E[k] = fmaf(mm, phi_from(xs, gauss_scaled(xs)), E[k]);
-                }
-            }
-        }
-    }
+    blend_sums<KB>(A, P.q, keff, kmax, lk, E);   // the blend's sums, as in blend_body
     // T_k waits in LDS (where g_k T_k goes later), W_k = T_k e^{q_k} in dE
     // until dE_k = -g_k W_k replaces it, and the original indices
     const int tid = threadIdx.x;
@@ -1284,20 +1256,7 @@ __device__ __forceinline__ void fwdbwd_pix_body(const TraceArgs& A, int tile, fl
         for (int c = 0; c < C; ++c) gp(A.image)[p * C + c] = 0.f;
     }
     if (A.wsum && P.valid) gp(A.wsum)[p] = ws;
-    if (A.kept && P.valid) {
-        // the kept indices in ascending depth, as in blend_body
-        const auto kp = gp(A.kept) + p * A.K;
-        for (int s = keff; s < A.K; ++s) kp[s] = -1;
-        for (int k = 0; k < keff; ++k) {
-            const double l = pl[(size_t)k * S];
-            int pos = 0;
-            for (int m = 0; m < keff; ++m) {
-                const double lm = pl[(size_t)m * S];
-                pos += (lm < l || (lm == l && m < k)) ? 1 : 0;
-            }
-            kp[pos] = gp(A.kl_i)[(size_t)k * S + P.q];
-        }
-    }
+    if (A.kept && P.valid) write_kept(A, P.q, p, keff);
     bwd_pair_loop<KB>(A, P.q, keff, kmax, s_dmd, lk, dE);
 }
 
