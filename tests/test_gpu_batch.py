@@ -224,6 +224,11 @@ def test_status_words_are_per_item():
 
 
 def test_forward_then_reuse_backward_equals_one_call():
+    """One forward + backward call (the blend and the backward in one kernel,
+    k_fwdbwd) against a forward call followed by a backward call that reuses
+    its kept sets (k_blend, then k_bwd): the same images bit for bit, and
+    gradients within the parity bound (their global sums add in either
+    order)."""
     rng = np.random.default_rng(15)
     scenes, items = mixed_batch(rng)
     dev = torch.device("cuda:0")
