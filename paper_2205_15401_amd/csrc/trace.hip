@@ -1666,15 +1666,18 @@ __device__ __forceinline__ TraceArgs item_view(const GroupDev& g, int& tile) {
 }
 
 // Waves per SIMD the select kernel must fit (a register cap for the
-// compiler): three at a K-buffer of 32 keys, which would otherwise drop to two.
-template <int KB>
-constexpr int select_waves() { return KB == 32 ? 3 : KB == 20 ? 6 : KB == 16 ? 7 : 1; }
+// compiler): three at a K-buffer of 32 keys, which would otherwise drop to
+// two; seven and eight at 20 and 16 keys for the record scan (six and seven
+// for the bin scan, whose bin entries take registers too; a tighter cap
+// spills).
+template <int KB, bool BINS>
+constexpr int select_waves() { return KB == 32 ? 3 : KB == 20 ? (BINS ? 6 : 7) : KB == 16 ? (BINS ? 7 : 8) : 1; }
 
 // BINS: the launch holds binned items, whose tiles' bins are sorted into the
 // dynamic LDS s_rank (BIN_MAX entries) and scanned in place of every record;
 // a launch without binned items compiles the record scan alone.
 template <int KB, bool BINS>
-__global__ __launch_bounds__(TILE_THREADS, select_waves<KB>()) void k_select(GroupDev g) {
+__global__ __launch_bounds__(TILE_THREADS, (select_waves<KB, BINS>())) void k_select(GroupDev g) {
     extern __shared__ __align__(16) uint32_t s_rank[];
     int tile;
     const TraceArgs A = item_view(g, tile);
