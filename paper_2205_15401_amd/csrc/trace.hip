@@ -1227,13 +1227,12 @@ __device__ __forceinline__ void fwdbwd_pix_body(const TraceArgs& A, int tile, fl
         }
     } else if (kmax > 0) {
         // other channel counts: the colour sum channel by channel, then g_k
-        float g[KB];
-#pragma unroll
-        for (int k = 0; k < KB; ++k) g[k] = 0.f;
+        // four slots at a time over all channels (a second gather of the
+        // rows; one channel per load keeps the registers of the pair loop's
+        // kernel free of spills)
         const auto at = gp(A.attrs);
         const auto Gp = gp(A.grad_image) + p * C;
         for (int c = 0; c < C; ++c) {
-            const float Gc = keff > 0 ? Gp[c] : 0.f;
             float acc = 0.f;
 #pragma unroll
             for (int k0 = 0; k0 < KB; k0 += 4) {
@@ -1242,16 +1241,24 @@ __device__ __forceinline__ void fwdbwd_pix_body(const TraceArgs& A, int tile, fl
 #pragma unroll
                     for (int k = k0; k < k0 + 4; ++k) v[k - k0] = at[(size_t)ik[k] * C + c];
 #pragma unroll
-                    for (int k = k0; k < k0 + 4; ++k) {
-                        acc = fmaf(dE[k], v[k - k0], acc);
-                        g[k] = fmaf(Gc, v[k - k0], g[k]);
-                    }
+                    for (int k = k0; k < k0 + 4; ++k) acc = fmaf(dE[k], v[k - k0], acc);
                 }
             }
             if (img) gp(A.image)[p * C + c] = acc;
         }
 #pragma unroll
-        for (int k = 0; k < KB; ++k) finish(k, g[k]);
+        for (int k0 = 0; k0 < KB; k0 += 4) {
+            if (k0 < kmax) {
+                float g4[4] = {0.f, 0.f, 0.f, 0.f};
+                for (int c = 0; c < C; ++c) {
+                    const float Gc = keff > 0 ? Gp[c] : 0.f;
+#pragma unroll
+                    for (int k = k0; k < k0 + 4; ++k) g4[k - k0] = fmaf(Gc, at[(size_t)ik[k] * C + c], g4[k - k0]);
+                }
+#pragma unroll
+                for (int k = k0; k < k0 + 4; ++k) finish(k, g4[k - k0]);
+            }
+        }
     } else if (img) {
         for (int c = 0; c < C; ++c) gp(A.image)[p * C + c] = 0.f;
     }
