@@ -281,6 +281,7 @@ BatchPlan plan_batch(const ItemShape* shapes, int n) {
     p.off_toff = take(4 * (nt + 1));
     p.off_tsum = take(4 * ((size_t)p.tscan_blocks + 1));
     p.off_tlist = take(4 * (size_t)p.tile_cap);
+    p.off_tmask = take(4 * (nt + (size_t)(n > 0 ? n : 1)));    // block masks, then the items' dense words
     p.fwd_bytes = off;
     // gM [3 nk] | gS [6 nk] | gA [total_attr]: one contiguous range, cleared at once
     p.off_grads = take(sizeof(float) * (9 * nk + p.total_attr));
@@ -361,7 +362,7 @@ struct BatchWs {
     double* camP;
     float4* bw;
     float* bwl;
-    uint32_t *tcnt, *tcur, *toff, *tsum, *tlist;
+    uint32_t *tcnt, *tcur, *toff, *tsum, *tlist, *tmask;
 };
 
 BatchWs carve_batch(void* ws, const voge::BatchPlan& p) {
@@ -399,6 +400,7 @@ BatchWs carve_batch(void* ws, const voge::BatchPlan& p) {
     w.toff = reinterpret_cast<uint32_t*>(b + p.off_toff);
     w.tsum = reinterpret_cast<uint32_t*>(b + p.off_tsum);
     w.tlist = reinterpret_cast<uint32_t*>(b + p.off_tlist);
+    w.tmask = reinterpret_cast<uint32_t*>(b + p.off_tmask);
     return w;
 }
 
@@ -429,6 +431,8 @@ voge::ItemDev item_record(const voge::BatchPlan& p, int j, const voge_item_t& sr
     t.tlist = w.tlist;
     t.tcap = p.tile_cap;
     t.binned = voge::item_binned(cfg, ip.s.N) ? 1 : 0;
+    t.tmask = w.tmask + ip.tile_start;
+    t.tdense = w.tmask + (p.total_tiles > 0 ? p.total_tiles : 1) + j;
     t.attrs = src.attrs;
     t.keff = w.keff + (size_t)ip.tile_start * voge::TILE_THREADS;
     t.kl_l = w.kl_l + lo;
@@ -497,6 +501,8 @@ voge::BatchDev batch_dev(const voge::BatchPlan& p, const BatchWs& w, const voge:
     b.toff = w.toff;
     b.tlist = w.tlist;
     b.tcap = p.tile_cap;
+    b.tmask = w.tmask;
+    b.tdense = w.tmask + (p.total_tiles > 0 ? p.total_tiles : 1);
     return b;
 }
 

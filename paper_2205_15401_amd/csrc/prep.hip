@@ -59,6 +59,10 @@ __global__ __launch_bounds__(PREP_THREADS) void k_prep_keys(BatchDev B, uint32_t
     const int item = item_of_block(B.pblk_item, B.n_items);
     const ItemDev& it = B.items[item];
     const int n = (blockIdx.x - it.pblk_start) * PREP_THREADS + threadIdx.x;
+    // the item's block masks start clear (k_block_cover sets them; an item
+    // without kernels has no prep block, and select finds no record to scan)
+    for (int t = n; t < it.t.n_tiles; t += it.n_pblk * PREP_THREADS) B.tmask[it.tile_start + t] = 0u;
+    if (n == 0) B.tdense[item] = 0u;
     if (n >= it.t.N) return;
     double M0[3], Sig[6], S0[6];
     uint32_t key = KEY_CULLED;
@@ -184,6 +188,115 @@ __global__ __launch_bounds__(PREP_THREADS) void k_prep_records(BatchDev B, int t
     cull[r] = cr;
     rec[r] = tr;
     geo[r] = g;
+}
+
+// ------------------------------------------------------------ block masks
+// Which 8x8 blocks of an item's screen some kernel's box meets (select skips
+// the others).  A workgroup takes one part of an item's boxes and counts, in
+// LDS, the boxes covering each cell of a grid over the image: every box adds
+// +1 and -1 at the four corners of its cell range (a difference array), and
+// prefix sums along the rows, then down the columns, turn the corner marks
+// into the number of boxes over each cell -- four LDS atomics per kernel
+// whatever its box's size.  LDS atomics are served about one lane per cycle
+// per CU, so an item's boxes are split over up to COVER_SPLIT workgroups of
+// COVER_RECS or more boxes, which OR their tiles' bits into the masks
+// (cleared by k_prep_keys).  The cells are the 8x8 blocks when their grid
+// fits COVER_CELLS, else the 16x16 tiles (a covered tile keeps all four of
+// its blocks), else the item is dense (every block scans).
+constexpr int COVER_THREADS = 1024;
+constexpr int COVER_CELLS = 16384;       // grid cells held in LDS (64 KB)
+constexpr int COVER_BATCH = 8;           // boxes per thread loaded together
+constexpr int COVER_RECS = 2048;         // boxes per workgroup, at least (but the last part)
+constexpr int COVER_SPLIT = 16;          // workgroups per item, at most
+
+// Workgroups per item of a batch whose largest item has max_n kernels.
+inline int cover_split(int max_n) {
+    return std::max(1, std::min(COVER_SPLIT, (max_n + COVER_RECS - 1) / COVER_RECS));
+}
+
+__global__ __launch_bounds__(COVER_THREADS) void k_block_cover(BatchDev B, const CullRec* __restrict__ cull,
+                                                               int split) {
+    __shared__ int g[COVER_CELLS];
+    const int item = blockIdx.x / split, part = blockIdx.x % split;
+    const ItemDev& it = B.items[item];
+    const int tid = threadIdx.x;
+    const int H = it.t.H, W = it.t.W;
+    const int nty = (H + TILE - 1) / TILE, ntx = (W + TILE - 1) / TILE;
+    // this part's boxes: [r_lo, r_hi) of the item's records
+    const int N = it.t.N;
+    const int per = std::max(COVER_RECS, (N + split - 1) / split);
+    const int r_lo = part * per, r_hi = std::min(N, r_lo + per);
+    if (r_lo >= r_hi) return;
+    int sh = 3;                              // cell = 2^sh pixels a side
+    int nci = (H + 7) >> 3, ncj = (W + 7) >> 3;
+    if ((nci + 1) * (ncj + 1) > COVER_CELLS) {
+        sh = 4;
+        nci = nty;
+        ncj = ntx;
+    }
+    const int gw = ncj + 1, gh = nci + 1;
+    if (gh * gw > COVER_CELLS) {
+        if (tid == 0) B.tdense[item] = 1u;
+        return;
+    }
+    for (int c = tid; c < gh * gw; c += COVER_THREADS) g[c] = 0;
+    __syncthreads();
+    // the boxes, COVER_BATCH per thread in flight at a time; every lane loads
+    // (past the end: the part's last record, then dropped), so that a
+    // batch's loads are all issued before the first wait
+    const CullRec* cr = cull + it.kern_start;
+    for (int r0 = r_lo + tid; r0 < r_hi; r0 += COVER_BATCH * COVER_THREADS) {
+        CullRec b[COVER_BATCH];
+#pragma unroll
+        for (int u = 0; u < COVER_BATCH; ++u) {
+            const int r = r0 + u * COVER_THREADS;
+            b[u] = cr[std::min(r, r_hi - 1)];
+            if (r >= r_hi) {
+                b[u].i0 = 1;
+                b[u].i1 = 0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < COVER_BATCH; ++u) {
+            if (b[u].i0 > b[u].i1 || b[u].j0 > b[u].j1) continue;     // culled or past the end: no box
+            const int ci0 = b[u].i0 >> sh, ci1 = (b[u].i1 >> sh) + 1;
+            const int cj0 = b[u].j0 >> sh, cj1 = (b[u].j1 >> sh) + 1;
+            atomicAdd(&g[ci0 * gw + cj0], 1);
+            atomicAdd(&g[ci0 * gw + cj1], -1);
+            atomicAdd(&g[ci1 * gw + cj0], -1);
+            atomicAdd(&g[ci1 * gw + cj1], 1);
+        }
+    }
+    __syncthreads();
+    // inclusive prefix sum of the n cells base, base + st, ... by one thread,
+    // eight cells loaded together (their loads do not wait for the stores)
+    auto scan = [&](int base, int n, int st) {
+        int acc = 0;
+        for (int c0 = 0; c0 < n; c0 += 8) {
+            int v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = c0 + u < n ? g[base + (c0 + u) * st] : 0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                acc += v[u];
+                if (c0 + u < n) g[base + (c0 + u) * st] = acc;
+            }
+        }
+    };
+    for (int i = tid; i < gh; i += COVER_THREADS) scan(i * gw, gw, 1);
+    __syncthreads();
+    for (int j = tid; j < gw; j += COVER_THREADS) scan(j, gh, gw);
+    __syncthreads();
+    for (int t = tid; t < it.t.n_tiles; t += COVER_THREADS) {
+        const int ti = t / ntx, tj = t % ntx;
+        uint32_t m = 0;
+        for (int q = 0; q < 4; ++q) {
+            // block (2 ti + q / 2, 2 tj + q % 2); blocks past the image stay clear
+            const int ci = (2 * ti + (q >> 1)) >> (sh - 3), cj = (2 * tj + (q & 1)) >> (sh - 3);
+            if (ci < nci && cj < ncj && g[ci * gw + cj] > 0) m |= 1u << q;
+        }
+        if (m) atomicOr(&B.tmask[it.tile_start + t], m);
+    }
 }
 
 // ------------------------------------------------------- coarse-stage bins
@@ -504,6 +617,8 @@ void launch_prep(const BatchDev& b, int total_pblk, int total_kern, int max_n, i
         // every item sorts in one workgroup's LDS
         hipLaunchKernelGGL(k_sort_items, dim3(b.n_items), dim3(ISORT_THREADS), 0, s, b, keys, vals);
         hipLaunchKernelGGL(k_prep_records, dim3(blocks), dim3(PREP_THREADS), 0, s, b, N, keys, vals, cull, rec, geo);
+        hipLaunchKernelGGL(k_block_cover, dim3(b.n_items * cover_split(max_n)), dim3(COVER_THREADS), 0, s, b, cull,
+                           cover_split(max_n));
         launch_bins(b, N, total_tiles, tscan_blocks, keys, tsum, cull, s);
         return;
     }
@@ -524,6 +639,8 @@ void launch_prep(const BatchDev& b, int total_pblk, int total_kern, int max_n, i
         t = vin; vin = vout; vout = t;
     }
     hipLaunchKernelGGL(k_prep_records, dim3(blocks), dim3(PREP_THREADS), 0, s, b, N, kin, vin, cull, rec, geo);
+    hipLaunchKernelGGL(k_block_cover, dim3(b.n_items * cover_split(max_n)), dim3(COVER_THREADS), 0, s, b, cull,
+                       cover_split(max_n));
     launch_bins(b, N, total_tiles, tscan_blocks, kin, tsum, cull, s);
 }
 

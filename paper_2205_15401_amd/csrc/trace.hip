@@ -323,7 +323,10 @@ __device__ __forceinline__ void select_body(const TraceArgs& A, int tile, const 
     int nkey = 0;                                // kept keys (at most K)
     int ub = 0;                                  // the wave's largest nkey (uniform)
     int kslot = 0;                               // the slot of kth
-    bool done = !P.valid;
+    // a block that no kernel's screen box meets has no candidate: it keeps
+    // nothing and scans nothing
+    const bool empty = gp(A.tdense)[0] == 0u && ((gp(A.tmask)[tile] >> wave) & 1u) == 0u;
+    bool done = !P.valid || empty;
     // One step: the list entries base .. base+63 (lane j holds the rank of
     // entry base + j in ent) whose boxes meet the block (hit); returns true
     // once the block is done.

@@ -45,6 +45,12 @@ struct TraceArgs {
     const uint32_t* tlist;     // the batch's pair list (item-local ranks, unordered per tile)
     uint32_t tcap;             // pair list capacity
     int binned;                // 0: the item is not binned (select scans all its records)
+    // blocks with candidates: per tile of the item, bit b set when some
+    // kernel's screen box meets the tile's 8x8 block b (b = 2 * row half +
+    // column half); *tdense set when a box too large to mark was met (then
+    // every block scans).  Select skips a block with its bit clear.
+    const uint32_t* tmask;     // [n_tiles]
+    const uint32_t* tdense;    // the item's word
     const float* attrs;
     // kept lists, slot-major [K][S]
     int32_t* keff;             // [S]
@@ -104,6 +110,10 @@ struct BatchDev {
     uint32_t* tlist;           // [tcap] item-local ranks, grouped by tile
     uint32_t tcap;
     int any_binned;            // some item is binned (else no bins are built)
+    // block masks over all items' tiles, then one dense word per item
+    // (cleared by k_prep_keys, set by k_prep_records)
+    uint32_t* tmask;           // [total tiles]
+    uint32_t* tdense;          // [n_items]
 };
 
 // One launch over the tiles of a group of items that share a K-buffer depth.
@@ -175,7 +185,7 @@ struct BatchPlan {
     size_t off_keys, off_vals, off_keys2, off_vals2, off_hist, off_cull, off_rec, off_geo;
     size_t off_keff, off_kl_l, off_kl_m, off_kl_s, off_kl_T, off_kl_r, off_kl_i;
     size_t off_grads, off_tileD, off_camP, off_bw, off_bwl;
-    size_t off_tcnt, off_tcur, off_toff, off_tsum, off_tlist;
+    size_t off_tcnt, off_tcur, off_toff, off_tsum, off_tlist, off_tmask;
     uint32_t tile_cap = 0;     // pair list capacity
     int tscan_blocks = 0;      // blocks of the tile-count scan
     size_t fwd_bytes, bwd_bytes;

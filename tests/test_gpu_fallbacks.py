@@ -268,3 +268,63 @@ def test_bins_on_and_off_render_the_same(which):
     pix = np.sort(np.random.default_rng(96).choice(H * W, 3000, replace=False))
     check_forward_vs_oracle(i1.numpy(), w1.numpy(), k1.numpy().reshape(H * W, K), scene, cam, K, pixels=pix,
                             name=f"{which} binned")
+
+
+def strip_scene(rng, n, focal, width, height, clusters=12):
+    """n small isotropic kernels in a few clusters spread along a wide strip
+    seen by the identity camera (most 8x8 blocks of the image are empty)."""
+    z = rng.uniform(2.0, 4.0, n)
+    centre = rng.uniform(-0.45, 0.45, clusters) * width
+    col = centre[rng.integers(0, clusters, n)] + rng.normal(0.0, 0.02 * min(width, 2000), n)
+    row = rng.uniform(-0.4, 0.4, n) * height
+    means = np.column_stack([row * z / focal, col * z / focal, z]).astype(np.float32)   # x: rows, y: columns
+    s = rng.uniform(0.005, 0.02, n).astype(np.float32)
+    covs = np.zeros((n, 6), np.float32)
+    covs[:, 0] = covs[:, 3] = covs[:, 5] = s ** 2
+    return S.Scene(means, covs, rng.uniform(0.0, 1.0, (n, 3)).astype(np.float32))
+
+
+@pytest.mark.parametrize("shape", ["strip", "square"])
+def test_block_masks_in_every_cell_mode(shape):
+    """Select skips the 8x8 blocks that no kernel's screen box meets, from
+    per-item masks counted on a grid of 8x8 cells, of 16x16 tiles when that
+    grid would not fit in LDS, and not at all beyond (every block scans).  A
+    144x30000 strip (no mask) and a 1040x1040 image (tile cells) render
+    bit-identically to one batch call over crops of them small enough for
+    8x8 cells (images, weight sums, kept sets), and sampled pixels of the
+    large image match the oracle."""
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(97)
+    if shape == "strip":
+        H, W, f = 144, 30000, 1000.0
+        scene = strip_scene(rng, 800, f, W, H)
+        crops = [(0, o, H, 1000) for o in range(0, W, 1000)]
+    else:
+        H = W = 1040
+        f = 1040.0
+        scene = S.cloud_scene(rng, 3000, 3, std_range=(0.005, 0.03))
+        crops = [(r, c, 520, 520) for r in (0, 520) for c in (0, 520)]
+    cam = S.Camera(R=np.eye(3, dtype=np.float32), T=np.zeros(3, np.float32), focal=f, cx=W / 2.0, cy=H / 2.0,
+                   height=H, width=W)
+    K = 16
+    m, c, a = to_dev(scene.means), to_dev(scene.covs), to_dev(scene.attrs)
+    img, ws, kept, _ = R.render_forward(m, c, a, R.camera_struct(cam), K, 0.01, with_wsum=True, with_kept=True)
+    torch.cuda.synchronize()
+    img = img.cpu().numpy().reshape(H, W, 3)
+    ws = ws.cpu().numpy().reshape(H, W)
+    kept = kept.cpu().numpy().reshape(H, W, K)
+    assert (kept[..., 0] >= 0).mean() > 0.02
+    cams = [S.Camera(R=cam.R, T=cam.T, focal=f, cx=cam.cx - c0, cy=cam.cy - r0, height=h, width=w)
+            for (r0, c0, h, w) in crops]
+    b = R.Batch([(m, c, a)], [(0, R.camera_struct(cc), K, 0.01) for cc in cams], dev, with_wsum=True,
+                with_kept=True)
+    b.run(forward=True)
+    torch.cuda.synchronize()
+    for i, (r0, c0, h, w) in enumerate(crops):
+        assert np.array_equal(b.images[i].cpu().numpy().reshape(h, w, 3), img[r0:r0 + h, c0:c0 + w])
+        assert np.array_equal(b.wsums[i].cpu().numpy().reshape(h, w), ws[r0:r0 + h, c0:c0 + w])
+        assert np.array_equal(b.kepts[i].cpu().numpy().reshape(h, w, K), kept[r0:r0 + h, c0:c0 + w])
+    hit = np.flatnonzero(kept.reshape(H * W, K)[:, 0] >= 0)
+    pix = np.sort(np.concatenate([rng.choice(hit, 600, replace=False), rng.choice(H * W, 200, replace=False)]))
+    check_forward_vs_oracle(img.reshape(H * W, 3), ws.reshape(H * W), kept.reshape(H * W, K), scene, cam, K,
+                            pixels=pix, name=f"{shape} block masks")
