@@ -981,8 +981,10 @@ __device__ __forceinline__ void bwd_pair_loop(const TraceArgs& A, size_t q, int 
         mn = nin ? pm[o + S] : 0.f;
         sn = nin ? ps[o + S] : 1.f;
         tn = nin ? pT[o + S] : 0.f;
-        const float sms = sm * SQRT_LOG2E, mmc = mm * INV_SQRT_PI;
-        float acc_dm = 0.f, acc_dx = 0.f, acc_dd = 0.f;
+        // dx_km = dE_k e_km m_m / sqrt(pi): the factor m_m / sqrt(pi) of slot
+        // m is applied once to the sums over k
+        const float sms = sm * SQRT_LOG2E, mmc = mm * INV_SQRT_PI, mcs = mmc * sm;
+        float acc_dm = 0.f, acc_t = 0.f, acc_td = 0.f;
 #pragma unroll
         for (int k0 = 0; k0 < KB; k0 += 4) {
             if (k0 < kmax) {
@@ -992,16 +994,17 @@ __device__ __forceinline__ void bwd_pair_loop(const TraceArgs& A, size_t q, int 
                     const float xs = d * sms;
                     const float ex = gauss_scaled(xs);
                     acc_dm = fmaf(dE[k], phi_from(xs, ex), acc_dm);
-                    const float dx = dE[k] * mmc * ex;
-                    dl[k] = fmaf(dx, sm, dl[k]);
-                    acc_dx += dx;
-                    acc_dd = fmaf(dx, d, acc_dd);
+                    const float t = dE[k] * ex;
+                    dl[k] = fmaf(t, mcs, dl[k]);
+                    acc_t += t;
+                    acc_td = fmaf(t, d, acc_td);
                 }
             }
         }
         if (in) {
             const float dmd_m = s_dmd[m * TILE_THREADS + tid];
-            st_f4(pbw + o, make_float4((dmd_m + acc_dm) * mm, -sm * acc_dx, acc_dd * (0.5f / sm), tm * mm));
+            st_f4(pbw + o, make_float4((dmd_m + acc_dm) * mm, -sm * (mmc * acc_t), (mmc * acc_td) * (0.5f / sm),
+                                       tm * mm));
         }
     }
     // the k-side part of dL/dl of each slot
