@@ -47,8 +47,9 @@ struct TraceArgs {
     int binned;                // 0: the item is not binned (select scans all its records)
     // blocks with candidates: per tile of the item, bit b set when some
     // kernel's screen box meets the tile's 8x8 block b (b = 2 * row half +
-    // column half); *tdense set when a box too large to mark was met (then
-    // every block scans).  Select skips a block with its bit clear.
+    // column half); *tdense set when the image is too large for the count
+    // grid in LDS (then every block scans).  Select skips a block with its
+    // bit clear.
     const uint32_t* tmask;     // [n_tiles]
     const uint32_t* tdense;    // the item's word
     const float* attrs;
@@ -111,7 +112,7 @@ struct BatchDev {
     uint32_t tcap;
     int any_binned;            // some item is binned (else no bins are built)
     // block masks over all items' tiles, then one dense word per item
-    // (cleared by k_prep_keys, set by k_prep_records)
+    // (cleared by k_prep_keys, set by k_block_cover)
     uint32_t* tmask;           // [total tiles]
     uint32_t* tdense;          // [n_items]
 };
