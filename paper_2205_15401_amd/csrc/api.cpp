@@ -503,6 +503,7 @@ voge::BatchDev batch_dev(const voge::BatchPlan& p, const BatchWs& w, const voge:
     b.tcap = p.tile_cap;
     b.tmask = w.tmask;
     b.tdense = w.tmask + (p.total_tiles > 0 ? p.total_tiles : 1);
+    b.masks = p.max_n >= voge::MASK_MIN_KERNELS ? 1 : 0;
     return b;
 }
 

@@ -59,10 +59,12 @@ __global__ __launch_bounds__(PREP_THREADS) void k_prep_keys(BatchDev B, uint32_t
     const int item = item_of_block(B.pblk_item, B.n_items);
     const ItemDev& it = B.items[item];
     const int n = (blockIdx.x - it.pblk_start) * PREP_THREADS + threadIdx.x;
-    // the item's block masks start clear (k_block_cover sets them; an item
-    // without kernels has no prep block, and select finds no record to scan)
-    for (int t = n; t < it.t.n_tiles; t += it.n_pblk * PREP_THREADS) B.tmask[it.tile_start + t] = 0u;
-    if (n == 0) B.tdense[item] = 0u;
+    // the item's block masks start clear (k_block_cover sets them), or the
+    // item is dense when the batch has no masks (an item without kernels has
+    // no prep block, and select finds no record to scan)
+    if (B.masks)
+        for (int t = n; t < it.t.n_tiles; t += it.n_pblk * PREP_THREADS) B.tmask[it.tile_start + t] = 0u;
+    if (n == 0) B.tdense[item] = B.masks ? 0u : 1u;
     if (n >= it.t.N) return;
     double M0[3], Sig[6], S0[6];
     uint32_t key = KEY_CULLED;
@@ -617,8 +619,9 @@ void launch_prep(const BatchDev& b, int total_pblk, int total_kern, int max_n, i
         // every item sorts in one workgroup's LDS
         hipLaunchKernelGGL(k_sort_items, dim3(b.n_items), dim3(ISORT_THREADS), 0, s, b, keys, vals);
         hipLaunchKernelGGL(k_prep_records, dim3(blocks), dim3(PREP_THREADS), 0, s, b, N, keys, vals, cull, rec, geo);
-        hipLaunchKernelGGL(k_block_cover, dim3(b.n_items * cover_split(max_n)), dim3(COVER_THREADS), 0, s, b, cull,
-                           cover_split(max_n));
+        if (b.masks)
+            hipLaunchKernelGGL(k_block_cover, dim3(b.n_items * cover_split(max_n)), dim3(COVER_THREADS), 0, s, b,
+                               cull, cover_split(max_n));
         launch_bins(b, N, total_tiles, tscan_blocks, keys, tsum, cull, s);
         return;
     }
@@ -639,8 +642,9 @@ void launch_prep(const BatchDev& b, int total_pblk, int total_kern, int max_n, i
         t = vin; vin = vout; vout = t;
     }
     hipLaunchKernelGGL(k_prep_records, dim3(blocks), dim3(PREP_THREADS), 0, s, b, N, kin, vin, cull, rec, geo);
-    hipLaunchKernelGGL(k_block_cover, dim3(b.n_items * cover_split(max_n)), dim3(COVER_THREADS), 0, s, b, cull,
-                       cover_split(max_n));
+    if (b.masks)
+        hipLaunchKernelGGL(k_block_cover, dim3(b.n_items * cover_split(max_n)), dim3(COVER_THREADS), 0, s, b, cull,
+                           cover_split(max_n));
     launch_bins(b, N, total_tiles, tscan_blocks, kin, tsum, cull, s);
 }
 

@@ -112,10 +112,17 @@ struct BatchDev {
     uint32_t tcap;
     int any_binned;            // some item is binned (else no bins are built)
     // block masks over all items' tiles, then one dense word per item
-    // (cleared by k_prep_keys, set by k_block_cover)
+    // (cleared by k_prep_keys, set by k_block_cover); without masks
+    // (masks = 0) k_prep_keys marks every item dense
     uint32_t* tmask;           // [total tiles]
     uint32_t* tdense;          // [n_items]
+    int masks;
 };
+
+// Kernels from which a batch's items get block masks (its largest item's
+// count): below it a block's record scan is a few dozen steps, shorter than
+// the mask launch.
+constexpr int MASK_MIN_KERNELS = 2048;
 
 // One launch over the tiles of a group of items that share a K-buffer depth.
 struct GroupDev {

@@ -289,15 +289,19 @@ def test_block_masks_in_every_cell_mode(shape):
     """Select skips the 8x8 blocks that no kernel's screen box meets, from
     per-item masks counted on a grid of 8x8 cells, of 16x16 tiles when that
     grid would not fit in LDS, and not at all beyond (every block scans).  A
-    144x30000 strip (no mask) and a 1040x1040 image (tile cells) render
-    bit-identically to one batch call over crops of them small enough for
-    8x8 cells (images, weight sums, kept sets), and sampled pixels of the
-    large image match the oracle."""
+    144x30000 strip (no mask) and a 1040x1040 image (tile cells), each of
+    more than 2,048 kernels (the batch size from which masks are built),
+    render bit-identically to one batch call over crops of them small enough
+    for 8x8 cells (images, weight sums, kept sets), and sampled pixels of the
+    large image match the oracle.  The large image is rendered in a batch of
+    as many items as the crops (itself and small pads), since the number of
+    items sets the depth-bucket resolution of the sort, hence the order of
+    equal-bucket kernels and of the blend's sums."""
     dev = torch.device("cuda:0")
     rng = np.random.default_rng(97)
     if shape == "strip":
         H, W, f = 144, 30000, 1000.0
-        scene = strip_scene(rng, 800, f, W, H)
+        scene = strip_scene(rng, 2500, f, W, H)
         crops = [(0, o, H, 1000) for o in range(0, W, 1000)]
     else:
         H = W = 1040
@@ -308,11 +312,15 @@ def test_block_masks_in_every_cell_mode(shape):
                    height=H, width=W)
     K = 16
     m, c, a = to_dev(scene.means), to_dev(scene.covs), to_dev(scene.attrs)
-    img, ws, kept, _ = R.render_forward(m, c, a, R.camera_struct(cam), K, 0.01, with_wsum=True, with_kept=True)
+    pad = S.Camera(R=cam.R, T=cam.T, focal=f, cx=cam.cx, cy=cam.cy, height=16, width=16)
+    full = R.Batch([(m, c, a)], [(0, R.camera_struct(cc), K, 0.01) for cc in [cam] + [pad] * (len(crops) - 1)], dev,
+                   with_wsum=True, with_kept=True)
+    full.run(forward=True)
     torch.cuda.synchronize()
-    img = img.cpu().numpy().reshape(H, W, 3)
-    ws = ws.cpu().numpy().reshape(H, W)
-    kept = kept.cpu().numpy().reshape(H, W, K)
+    img = full.images[0].cpu().numpy().reshape(H, W, 3)
+    ws = full.wsums[0].cpu().numpy().reshape(H, W)
+    kept = full.kepts[0].cpu().numpy().reshape(H, W, K)
+    del full
     assert (kept[..., 0] >= 0).mean() > 0.02
     cams = [S.Camera(R=cam.R, T=cam.T, focal=f, cx=cam.cx - c0, cy=cam.cy - r0, height=h, width=w)
             for (r0, c0, h, w) in crops]
