@@ -223,7 +223,7 @@ def roofline_of(phases, opc, K, workload, step_ms=None):
     flops = {"select": opc["flop_select"], "blend": opc["flop_blend"], "bwd": bwd,
              "fwdbwd": opc["flop_blend"] + bwd}
     kb = kb_of(K)
-    kname = {"select": f"k_select<{kb}>", "blend": f"k_blend<{kb}>", "bwd": f"k_bwd<{kb}>",
+    kname = {"select": f"k_select_wave<{kb}>", "blend": f"k_blend<{kb}>", "bwd": f"k_bwd<{kb}>",
              "fwdbwd": f"k_fwdbwd<{kb}>"}
     avg = {k: phases[k][0] / phases[k][1] for k in flops if k in phases and phases[k][1] > 0}
     per_kernel = {}
@@ -436,7 +436,7 @@ def sampler_roofline(phases, opc, K, workload):
     arithmetic (FP64 select; FP32 blend without packed instructions)."""
     flops = {"select": opc["flop_select"], "blend_sample": opc["flop_blend_weights"] + opc["flop_sample_reduce"]}
     kb = kb_of(K)
-    kname = {"select": f"k_select<{kb}>", "blend_sample": f"k_blend_sample<{kb}>"}
+    kname = {"select": f"k_select_wave<{kb}>", "blend_sample": f"k_blend_sample<{kb}>"}
     avg = {k: phases[k][0] / phases[k][1] for k in flops if k in phases and phases[k][1] > 0}
     dom = max(avg, key=avg.get)
     achieved = flops[dom] / (avg[dom] / 1e3) / 1e12

@@ -21,10 +21,12 @@ typedef struct voge_phase_time {
 
 /* Turn per-phase timing on or off for calls made through `ctx`.  When on,
  * every call records a HIP event before and after each phase on the caller's
- * stream: "select" is the single kernel k_select, "blend" k_blend, "bwd"
- * k_bwd, "fwdbwd" k_fwdbwd (the blend and the backward in one kernel, for
- * calls that ask for both); "prep" groups the per-kernel preparation and the
- * depth sort, "epilogue" the world-space epilogue.  Host memory only.
+ * stream: "select" is the single kernel k_select_wave (one wave per 8x8
+ * block; k_select with coarse-stage bins), "blend" k_blend, "bwd" k_bwd,
+ * "fwdbwd" k_fwdbwd (the blend and the backward in one kernel, for calls
+ * that ask for both); "prep" groups the per-kernel preparation, the depth
+ * sort and the block masks, "epilogue" the world-space epilogue.  Host
+ * memory only.
  * Returns 0 or VOGE_EINVAL. */
 int voge_profile_enable(voge_ctx_t* ctx, int enable);
 

@@ -299,12 +299,13 @@ __device__ __forceinline__ int load_bin(const TraceArgs& A, int tile, uint32_t* 
 // in s_rank (LDS); otherwise it is every record of the item (n_list = N),
 // entry j being rank j.
 template <int KB, bool BIN>
-__device__ __forceinline__ void select_body(const TraceArgs& A, int tile, const uint32_t* s_rank, const int n_list) {
+__device__ __forceinline__ void select_body(const TraceArgs& A, int tile, int blk, const uint32_t* s_rank,
+                                            const int n_list) {
     constexpr int CULL_AHEAD = cull_ahead(KB);
-    const int tid = threadIdx.x, lane = tid % WAVE;
-    const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);   // uniform in the wave
+    const int lane = threadIdx.x % WAVE;
+    const int wave = blk;                        // the tile's 8x8 block of this wave (uniform)
     const int ntx = (A.W + TILE - 1) / TILE;
-    const PixelCtx P = pixel_of(tile, ntx, A.H, A.W, A.cx, A.cy);
+    const PixelCtx P = pixel_at(tile, wave * WAVE + lane, ntx, A.H, A.W, A.cx, A.cy);
     const int bi0 = (tile / ntx) * TILE + (wave >> 1) * 8;            // this wave's block
     const int bj0 = (tile % ntx) * TILE + (wave & 1) * 8;
     const ConstRecPtr crec = const_rec(A.rec);
@@ -1694,14 +1695,30 @@ __global__ __launch_bounds__(TILE_THREADS, (select_waves<KB, BINS>())) void k_se
     extern __shared__ __align__(16) uint32_t s_rank[];
     int tile;
     const TraceArgs A = item_view(g, tile);
+    const int blk = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     if constexpr (BINS) {
         const int n_bin = load_bin(A, tile, s_rank);
         if (n_bin >= 0) {
-            select_body<KB, true>(A, tile, s_rank, n_bin);
+            select_body<KB, true>(A, tile, blk, s_rank, n_bin);
             return;
         }
     }
-    select_body<KB, false>(A, tile, nullptr, A.N);
+    select_body<KB, false>(A, tile, blk, nullptr, A.N);
+}
+
+// The record scan with one wave per workgroup: a workgroup is one 8x8
+// block, so the slot of a wave that ends takes any waiting block.  (With a
+// tile's four waves in one workgroup, a new tile needed a free slot on all
+// four SIMDs at once, and the blocks' unequal scans left slots idle.)  The
+// launch has four units per tile, dealt to the XCDs in bands like tiles.
+template <int KB>
+__global__ __launch_bounds__(WAVE, (select_waves<KB, false>())) void k_select_wave(GroupDev g) {
+    const int unit = tile_of_block(g.order);     // tile * 4 + block
+    const int gt = g.tile0 + unit / 4;
+    const int item = g.single >= 0 ? g.single : g.tile_item[gt];
+    const ItemDev* it = g.items + item;
+    const TraceArgs A = it->t;
+    select_body<KB, false>(A, gt - it->tile_start, unit % 4, nullptr, A.N);
 }
 
 template <int KB>
@@ -1805,7 +1822,7 @@ static hipError_t run_kb(int which, const GroupDev& g, hipStream_t s, int max_c 
         if (g.bins)
             hipLaunchKernelGGL((k_select<KB, true>), dim3(nt), dim3(TILE_THREADS), BIN_MAX * sizeof(uint32_t), s, g);
         else
-            hipLaunchKernelGGL((k_select<KB, false>), dim3(nt), dim3(TILE_THREADS), 0, s, g);
+            hipLaunchKernelGGL((k_select_wave<KB>), dim3(4 * nt), dim3(WAVE), 0, s, g);
     } else if (which == 1) {
         hipLaunchKernelGGL(k_blend<KB>, dim3(nt), dim3(TILE_THREADS), 0, s, g);
     } else if (which == 2) {
