@@ -22,7 +22,8 @@ typedef struct voge_phase_time {
 /* Turn per-phase timing on or off for calls made through `ctx`.  When on,
  * every call records a HIP event before and after each phase on the caller's
  * stream: "select" is the single kernel k_select_wave (one wave per 8x8
- * block; k_select with coarse-stage bins), "blend" k_blend, "bwd" k_bwd,
+ * block, launches of 2,048 tiles or more) or k_select (a tile per
+ * workgroup; with coarse-stage bins), "blend" k_blend, "bwd" k_bwd,
  * "fwdbwd" k_fwdbwd (the blend and the backward in one kernel, for calls
  * that ask for both); "prep" groups the per-kernel preparation, the depth
  * sort and the block masks, "epilogue" the world-space epilogue.  Host

@@ -1706,6 +1706,11 @@ __global__ __launch_bounds__(TILE_THREADS, (select_waves<KB, BINS>())) void k_se
     select_body<KB, false>(A, tile, blk, nullptr, A.N);
 }
 
+// Tiles from which select's record scan runs one wave per workgroup: with
+// fewer, all of a launch's blocks fit the chip's wave slots at once, and
+// four-wave workgroups spread them evenly over the SIMDs.
+constexpr int SELECT_WAVE_MIN_TILES = 2048;
+
 // The record scan with one wave per workgroup: a workgroup is one 8x8
 // block, so the slot of a wave that ends takes any waiting block.  (With a
 // tile's four waves in one workgroup, a new tile needed a free slot on all
@@ -1821,8 +1826,10 @@ static hipError_t run_kb(int which, const GroupDev& g, hipStream_t s, int max_c 
     if (which == 0) {
         if (g.bins)
             hipLaunchKernelGGL((k_select<KB, true>), dim3(nt), dim3(TILE_THREADS), BIN_MAX * sizeof(uint32_t), s, g);
-        else
+        else if (nt >= SELECT_WAVE_MIN_TILES)
             hipLaunchKernelGGL((k_select_wave<KB>), dim3(4 * nt), dim3(WAVE), 0, s, g);
+        else
+            hipLaunchKernelGGL((k_select<KB, false>), dim3(nt), dim3(TILE_THREADS), 0, s, g);
     } else if (which == 1) {
         hipLaunchKernelGGL(k_blend<KB>, dim3(nt), dim3(TILE_THREADS), 0, s, g);
     } else if (which == 2) {
